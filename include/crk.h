@@ -1,0 +1,215 @@
+/*
+ * crk.h -- C ABI of the chiral rank-k multigrid library for MI355X (gfx950).
+ *
+ * The library sets up and applies the multigrid hierarchy of
+ *   T. Whyte, A. Stathopoulos, E. Romero, "Chiral rank-k truncations for the
+ *   multigrid preconditioner of Wilson fermions in lattice QCD" (LATTICE2024),
+ * for the Wilson-Dirac operator D on a periodic 4-D lattice:
+ *   setup (Sec. 2 Eq. (1); Sec. 3 Eqs. (2), (5), (6); Sec. 2 Eq. (4)):
+ *     MR smoother on D psi_i ~ 0 for m' random vectors -> chiral split per block
+ *     -> per-(block, chirality) SVD truncated to k left singular vectors = P
+ *     (R = P^dag, gamma5 P = P sigma3) -> Galerkin coarse stencil D_c = R D P;
+ *   solve (Sec. 2, last paragraph): flexible GCR preconditioned by a K-cycle.
+ *
+ * Conventions shared by every entry point
+ *   - Site index s = x0 + L0*(x1 + L1*(x2 + L2*x3)); direction mu = 0..3 = x,y,z,t.
+ *   - Spinor component index 3*spin + colour (chiral gamma basis,
+ *     gamma5 = diag(1,1,-1,-1)); "host layout" of a field set is
+ *     complex128 interleaved (re, im) [nrhs][V][12].
+ *   - Gauge field: complex128 [V][4][3][3], entry U_mu(x)[a][b].
+ *   - D psi(x) = (m0 + sum_mu w_mu) psi(x)
+ *       - 1/2 sum_mu w_mu [(1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)],
+ *     w = (1, 1, 1, 1/xi), periodic boundaries.
+ *   - Coarse degrees of freedom: (coarse site j, chirality alpha, i), i < k.
+ *   - Every call returns CRK_OK (0) or a negative crk_status; on error
+ *     crk_last_error() returns a thread-local message.  No call aborts or
+ *     exits; no exception crosses the ABI.
+ *   - Host buffers are owned by the caller and copied before the call
+ *     returns.  Device ("_dev") buffers are owned by the caller and used in
+ *     order on the given HIP stream (NULL = the null stream); the caller keeps
+ *     them alive until that stream has completed.
+ *   - Handles are not thread-safe; use one handle per thread or serialise.
+ *     Destroying a lattice while hierarchies built on it live is allowed
+ *     (reference counted).
+ *   - Same inputs on the same GPU and build give bitwise-identical results.
+ */
+#ifndef CRK_H
+#define CRK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct crk_lattice_s* crk_lattice_t; /* opaque, library-owned */
+typedef struct crk_mg_s* crk_mg_t;           /* opaque; holds a reference on its lattice */
+
+enum crk_status {
+  CRK_OK = 0,
+  CRK_EINVAL = -1,    /* invalid argument (message says which) */
+  CRK_ENOMEM = -2,    /* device or host allocation failed */
+  CRK_EHIP = -3,      /* HIP runtime error */
+  CRK_ENOCONV = -4,   /* solver hit max_iter or broke down; x and info hold the best iterate */
+  CRK_ESTATE = -5,    /* call out of order (e.g. solve before gauge load) */
+  CRK_EBUSY = -6,     /* would exceed the device memory budget */
+  CRK_EINTERNAL = -7  /* internal inconsistency (a bug) */
+};
+
+/* Precision forms.  FP64: every kernel in double.  FP32: float storage and
+ * arithmetic.  FP16S: IEEE binary16 storage of x/s with an fp32 scale s per
+ * (site, rhs) for spinors and per (coarse site, link) for coarse links; fine
+ * links stored unscaled in fp16; all arithmetic accumulates in fp32. */
+enum crk_form { CRK_FORM_FP64 = 0, CRK_FORM_FP32 = 1, CRK_FORM_FP16S = 2 };
+
+/* Library version (major*10000 + minor*100 + patch). */
+int crk_version(void);
+
+/* Thread-local text of the last error ("" if none). */
+const char* crk_last_error(void);
+
+/* Name of device 0 (NUL-terminated, truncated to n bytes), its HBM size in
+ * bytes and compute-unit count.  Any pointer may be NULL. */
+int crk_device_info(char* name, int32_t n, int64_t* hbm_bytes, int32_t* n_cu);
+
+/* ------------------------------------------------------------------ lattice */
+
+/* Create a lattice of extent dims[4] (each >= 2) with Wilson mass m0 and
+ * temporal anisotropy xi > 0.  Allocates the device gauge storage (all
+ * forms) and the lexicographic neighbour table. */
+int crk_create_lattice(const int32_t dims[4], double m0, double xi, crk_lattice_t* out);
+
+/* Upload the gauge field (host complex128 [V][4][3][3], n_doubles = 2*V*36).
+ * Converted on the device to every precision form. */
+int crk_load_gauge(crk_lattice_t lat, const double* U, int64_t n_doubles);
+
+/* Apply D to nrhs host-layout fields (complex128 [nrhs][V][12]) in the given
+ * form; in and out are host pointers and may not alias.  FP32/FP16S round the
+ * input to the form, apply, and widen the result. */
+int crk_dirac_apply(crk_lattice_t lat, int32_t form, const double* in, double* out, int32_t nrhs);
+
+/* Device-resident variant on the lattice's native device layout of the form:
+ * FP64 double2 / FP32 float2 [nrhs][12][V] (site-fastest, lexicographic);
+ * FP16S: half2 [nrhs][12][V] followed by float scales [nrhs][V] in the same
+ * buffer (byte offset nrhs*12*V*4).  in/out are device pointers. */
+int crk_dirac_apply_dev(crk_lattice_t lat, int32_t form, const void* in, void* out, int32_t nrhs,
+                        void* hip_stream);
+
+/* Bytes of one native device field set of nrhs right-hand sides in a form. */
+int64_t crk_field_bytes(crk_lattice_t lat, int32_t form, int32_t nrhs);
+
+/* Convert between host-layout complex128 device buffers ([nrhs][V][12]) and
+ * the native device layout of a form (both device pointers). */
+int crk_field_import_dev(crk_lattice_t lat, int32_t form, const void* host_layout_dev, void* native_dev,
+                         int32_t nrhs, void* hip_stream);
+int crk_field_export_dev(crk_lattice_t lat, int32_t form, const void* native_dev, void* host_layout_dev,
+                         int32_t nrhs, void* hip_stream);
+
+/* Site-indexed integer maps of the lattice (bit-exact with the definitions):
+ * CRK_MAP_NEIGHBOR  int32 [V][8]  (column 2mu: x+mu, 2mu+1: x-mu)        */
+enum crk_map { CRK_MAP_NEIGHBOR = 0 };
+int crk_lattice_get_map(crk_lattice_t lat, int32_t what, void* out, int64_t n_bytes);
+
+void crk_lattice_destroy(crk_lattice_t lat);
+
+/* ------------------------------------------------------------------ setup */
+
+#define CRK_MAX_LEVELS 3
+
+typedef struct {
+  int32_t n_levels;                    /* 2 or 3 (levels including the fine one) */
+  int32_t m_prime[CRK_MAX_LEVELS];     /* test vectors per coarsening step (<= 64) */
+  int32_t k[CRK_MAX_LEVELS];           /* kept per chirality; multiple of 8, <= m', <= N_r */
+  int32_t block[CRK_MAX_LEVELS][4];    /* block extent per coarsening step */
+  int32_t n_smooth[CRK_MAX_LEVELS];    /* MR sweeps on D psi ~ 0 per step */
+  int32_t setup_form;                  /* precision of the setup smoother (FP64 or FP32) */
+  int32_t normalize;                   /* 1: psi_i <- psi_i/||psi_i|| before the SVD */
+  uint64_t seed;                       /* device random vectors when init_vectors is NULL */
+  const double* init_vectors[CRK_MAX_LEVELS]; /* optional host complex128 [m'][V_l][N_l] */
+} crk_mg_params;
+
+/* Fill p with defaults (two levels, m'=48, k=24, 4^4 blocks, 20 sweeps, FP32 smoother). */
+void crk_mg_params_default(crk_mg_params* p);
+
+/* Build the hierarchy (Sec. 2-3).  Blocking must divide every level's extent.
+ * Blocks until the setup is complete.  Per-stage device times are available
+ * through crk_mg_get_timing. */
+int crk_mg_setup(crk_lattice_t lat, const crk_mg_params* params, crk_mg_t* out);
+
+/* ------------------------------------------------------------------ solve */
+
+typedef struct {
+  /* in */
+  double tol;          /* relative TRUE residual ||b - D x|| / ||b|| (FP64) */
+  int32_t max_iter;    /* outer iterations */
+  int32_t form;        /* K-cycle precision (the outer GCR is always FP64) */
+  int32_t restart;     /* outer GCR restart length (<= 32) */
+  double tau;          /* inner relative tolerance of the coarse solves */
+  int32_t inner_maxit; /* iterations of an intermediate-level coarse solve */
+  int32_t coarsest_maxit; /* iterations of the coarsest solve */
+  int32_t nu_post;     /* MR post-smoothing steps */
+  /* out (maxima over right-hand sides) */
+  int32_t iters;                         /* outer iterations */
+  int32_t level_iters[CRK_MAX_LEVELS];   /* total iterations per level */
+  double true_rel_resid;                 /* max over RHS */
+  double seconds;                        /* device wall time of the solve */
+} crk_solve_info;
+
+void crk_solve_info_default(crk_solve_info* info);
+
+/* Solve D x = b for nrhs host-layout right-hand sides (complex128 [nrhs][V][12]). */
+int crk_mg_solve(crk_mg_t mg, const double* b, double* x, int32_t nrhs, crk_solve_info* info);
+
+/* Same with device buffers in host layout (complex128 [nrhs][V][12]), stream ordered;
+ * returns after the solve has completed on the stream (the outer loop reads
+ * residual norms every iteration). */
+int crk_mg_solve_dev(crk_mg_t mg, const void* b_dev, void* x_dev, int32_t nrhs, void* hip_stream,
+                     crk_solve_info* info);
+
+/* Per-RHS outer iteration counts and true residuals of the last solve. */
+int crk_mg_last_solve_rhs(crk_mg_t mg, int32_t* iters, double* true_rel_resid, int32_t nrhs);
+
+/* ------------------------------------------------------------------ inspection */
+
+enum crk_mg_what {
+  CRK_GET_P = 0,        /* complex128 [d][2][N_r][k]   prolongator blocks of level l (rows h*l+c') */
+  CRK_GET_SIGMA = 1,    /* double     [d][2][min(m',N_r)] singular values, descending */
+  CRK_GET_X = 2,        /* complex128 [Vc][2k][2k]     coarse site term of level l+1 */
+  CRK_GET_YP = 3,       /* complex128 [4][Vc][2k][2k]  coarse hop Y_{+mu} */
+  CRK_GET_YM = 4,       /* complex128 [4][Vc][2k][2k]  coarse hop Y_{-mu} */
+  CRK_GET_VECTORS = 5,  /* complex128 [m'][V_l][N_l]   smoothed, normalised test vectors */
+  CRK_GET_BLOCK_MAP = 6,/* int32 [V_l][2]  (block j, local index l) of every site */
+  CRK_GET_DEVICE_ORDER = 7 /* int32 [V_l]  device position of every site */
+};
+/* Copy a hierarchy quantity of step l (0 = fine -> first coarse) to host memory
+ * of exactly n_bytes. */
+int crk_mg_get(crk_mg_t mg, int32_t level, int32_t what, void* out, int64_t n_bytes);
+
+/* Bytes a quantity of crk_mg_get needs. */
+int64_t crk_mg_get_bytes(crk_mg_t mg, int32_t level, int32_t what);
+
+/* Device timing of the last setup, seconds:
+ * 0 total, 1 smoother, 2 split+SVD+P, 3 Galerkin, 4 average dslash launch
+ * inside the smoother, 5 number of those launches. */
+int crk_mg_get_timing(crk_mg_t mg, int32_t level, double* out6);
+
+/* Apply the coarse operator of level l (1..n_levels-1) in a form to host
+ * complex128 coarse vectors [nrhs][Vc][2k]. */
+int crk_mg_coarse_apply(crk_mg_t mg, int32_t level, int32_t form, const double* in, double* out,
+                        int32_t nrhs);
+
+/* Restrict fine-level (level l) host vectors [nrhs][V_l][N_l] to level l+1, and prolong back. */
+int crk_mg_restrict(crk_mg_t mg, int32_t level, int32_t form, const double* in, double* out, int32_t nrhs);
+int crk_mg_prolong(crk_mg_t mg, int32_t level, int32_t form, const double* in, double* out, int32_t nrhs);
+
+/* Device bytes held by the hierarchy plus the solver work space for nrhs
+ * right-hand sides in the given form (used for admission). */
+int64_t crk_mg_footprint_bytes(crk_mg_t mg, int32_t nrhs, int32_t form);
+
+void crk_mg_destroy(crk_mg_t mg);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRK_H */

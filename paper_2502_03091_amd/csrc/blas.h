@@ -1,0 +1,33 @@
+// Per-RHS BLAS-1 launchers (see blas.hip).
+#pragma once
+
+#include "common.h"
+
+namespace crk {
+
+// Number of partial rows rhs_dot needs per RHS for vectors of n entries
+// (partial buffer: rhs_dot_partials(n) * nrhs * 3 doubles).
+int64_t rhs_dot_partials(int64_t n);
+
+// out3[r] = (Re, Im) of sum_e conj(a) b, and sum_e |a|^2, for every rhs r;
+// entry e of rhs r at index r*rs + e*es.  b may be NULL (then b = a).
+// prec: CRK_FORM_FP64 (double2 data) or CRK_FORM_FP32 (float2 data).
+void rhs_dot(int prec, const void* a, const void* b, int64_t n, int nrhs, int64_t rs, int64_t es, double* partial,
+             double* out3, hipStream_t st);
+
+void reduce_partials(const double* partial, int64_t nchunk, int nrhs, int nv, double* out, hipStream_t st);
+
+// alpha[r] = <q,r>/<q,q> from sums3[r] = (Re<q,r>, Im<q,r>, <q,q>), 0 when <q,q> = 0.
+void mr_alpha(const double* sums3, int nrhs, double2* alpha, hipStream_t st);
+
+// psi += alpha r; r -= alpha q (n entries per rhs; rhs-outer or rhs-inner layout).
+void mr_update(int prec, void* psi, void* r, const void* q, const double2* alpha, int64_t n, int nrhs, bool rhs_inner,
+               hipStream_t st);
+
+// out[i] = 1/sqrt(sums[i*nv + comp]) (0 for a zero sum).
+void inv_sqrt(const double* sums, int nv, int comp, int n, double* out, hipStream_t st);
+
+// total complex Gaussian entries from Philox4x32-10 (counter = entry index, stream).
+void gaussian_fill(int prec, void* out, int64_t total, uint64_t seed, uint32_t stream, hipStream_t st);
+
+}  // namespace crk

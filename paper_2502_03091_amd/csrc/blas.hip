@@ -1,0 +1,225 @@
+// Per-right-hand-side BLAS-1 kernels for fields of many RHS.
+//
+// A field set holds nrhs vectors of n complex entries each.  Two layouts are
+// addressed through (rhs stride, element stride): fine fields are rhs-outer
+// (element e of rhs r at r*n + e) and coarse fields rhs-inner (at e*nrhs + r).
+// Reductions are deterministic: fixed per-thread element ranges, a fixed
+// shuffle/LDS tree per workgroup, and a fixed-order final sum over workgroups.
+#include "blas.h"
+#include "field.h"
+
+namespace crk {
+
+namespace {
+
+constexpr int kT = 256;
+
+template <class T> struct C2;
+template <> struct C2<double> { using t = double2; };
+template <> struct C2<float> { using t = float2; };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Block-wide sum of NV doubles per thread into out[NV] (valid on thread 0).
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* [NV][kT/64] */) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double t = wave_sum(v[i]);
+    if (lane == 0) sh[i * 4 + wid] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double t = 0;
+      for (int w = 0; w < nw; ++w) t += sh[i * 4 + w];
+      v[i] = t;
+    }
+  }
+}
+
+// partial[chunk][r][0..2] = (re, im) of sum conj(a) b, and sum |a|^2 over the chunk.
+template <class T>
+__global__ __launch_bounds__(kT) void dot_partial_kernel(const typename C2<T>::t* __restrict__ a,
+                                                         const typename C2<T>::t* __restrict__ b, int64_t n, int nrhs,
+                                                         int64_t rs, int64_t es, int64_t chunk,
+                                                         double* __restrict__ partial) {
+  __shared__ double sh[3 * 4];
+  const int r = blockIdx.y;
+  const int64_t e0 = int64_t(blockIdx.x) * chunk, e1 = min(n, e0 + chunk);
+  double v[3] = {0, 0, 0};
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int64_t idx = int64_t(r) * rs + e * es;
+    const auto x = a[idx];
+    const auto y = b ? b[idx] : x;
+    v[0] += double(x.x) * y.x + double(x.y) * y.y;
+    v[1] += double(x.x) * y.y - double(x.y) * y.x;
+    v[2] += double(x.x) * x.x + double(x.y) * x.y;
+  }
+  block_sum<3>(v, sh);
+  if (threadIdx.x == 0) {
+    double* p = partial + (int64_t(blockIdx.x) * nrhs + r) * 3;
+    p[0] = v[0]; p[1] = v[1]; p[2] = v[2];
+  }
+}
+
+// Sum partial[nchunk][nrhs][nv] over chunks in a fixed order; out[r][nv].
+__global__ __launch_bounds__(kT) void reduce_partial_kernel(const double* __restrict__ partial, int64_t nchunk,
+                                                            int nrhs, int nv, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int r = blockIdx.x / nv, c = blockIdx.x % nv;
+  double v[1] = {0};
+  for (int64_t i = threadIdx.x; i < nchunk; i += blockDim.x) v[0] += partial[(i * nrhs + r) * nv + c];
+  block_sum<1>(v, sh);
+  if (threadIdx.x == 0) out[r * nv + c] = v[0];
+}
+
+__global__ void mr_alpha_kernel(const double* __restrict__ sums, int nrhs, double2* __restrict__ alpha) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const double qq = sums[3 * r + 2];
+  alpha[r] = qq > 0 ? make_double2(sums[3 * r] / qq, sums[3 * r + 1] / qq) : make_double2(0, 0);
+}
+
+// psi += alpha r ;  r -= alpha q    (rhs-outer layout, n entries per rhs)
+template <class T>
+__global__ __launch_bounds__(kT) void mr_update_kernel(typename C2<T>::t* __restrict__ psi,
+                                                       typename C2<T>::t* __restrict__ r,
+                                                       const typename C2<T>::t* __restrict__ q,
+                                                       const double2* __restrict__ alpha, int64_t n, int nrhs,
+                                                       int rhs_inner) {
+  using CT = typename C2<T>::t;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  const int rr = rhs_inner ? int(i % nrhs) : int(i / n);
+  const double2 ad = alpha[rr];
+  const CT a = mk<CT>(T(ad.x), T(ad.y));
+  const CT rv = r[i];
+  CT p = psi[i];
+  cfma(p, a, rv);
+  psi[i] = p;
+  CT nr = rv;
+  const CT qa = cmul(a, q[i]);
+  nr.x -= qa.x;
+  nr.y -= qa.y;
+  r[i] = nr;
+}
+
+__global__ void inv_sqrt_kernel(const double* __restrict__ sums, int nv, int comp, int n, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = sums[i * nv + comp];
+  out[i] = s > 0 ? 1.0 / sqrt(s) : 0.0;
+}
+
+// ---------------------------------------------------------------- Philox4x32-10
+// Counter-based generator of Salmon, Moraes, Dror, Shaw (SC'11): ten rounds of
+// two 32x32->64 multiplies with the published multipliers and Weyl key bumps.
+__device__ __forceinline__ void philox_round(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+  const uint64_t p0 = uint64_t(0xD2511F53u) * c[0];
+  const uint64_t p1 = uint64_t(0xCD9E8D57u) * c[2];
+  const uint32_t hi0 = uint32_t(p0 >> 32), lo0 = uint32_t(p0);
+  const uint32_t hi1 = uint32_t(p1 >> 32), lo1 = uint32_t(p1);
+  c[0] = hi1 ^ c[1] ^ k0;
+  c[1] = lo1;
+  c[2] = hi0 ^ c[3] ^ k1;
+  c[3] = lo0;
+}
+
+__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    philox_round(c, k0, k1);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// One complex Gaussian (Re, Im ~ N(0,1)) per entry via Box-Muller on two
+// 64-bit uniforms in (0, 1).
+template <class T>
+__global__ __launch_bounds__(kT) void gaussian_kernel(typename C2<T>::t* __restrict__ out, int64_t total,
+                                                      uint64_t seed, uint32_t stream) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  uint32_t c[4] = {uint32_t(i), uint32_t(uint64_t(i) >> 32), stream, 0x5eedu};
+  philox4x32_10(c, uint32_t(seed), uint32_t(seed >> 32));
+  const double u1 = (double((uint64_t(c[0]) << 32 | c[1]) >> 11) + 0.5) * 0x1.0p-53;
+  const double u2 = (double((uint64_t(c[2]) << 32 | c[3]) >> 11) + 0.5) * 0x1.0p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);
+  out[i] = mk<typename C2<T>::t>(T(rad * cs), T(rad * sn));
+}
+
+int64_t chunk_for(int64_t n) {
+  // enough workgroups to fill the chip, fixed by n only (deterministic)
+  int64_t c = (n + 1023) / 1024;
+  if (c < 4096) c = 4096;
+  return c;
+}
+
+}  // namespace
+
+int64_t rhs_dot_partials(int64_t n) { return (n + chunk_for(n) - 1) / chunk_for(n); }
+
+void rhs_dot(int prec, const void* a, const void* b, int64_t n, int nrhs, int64_t rs, int64_t es, double* partial,
+             double* out3, hipStream_t st) {
+  if (nrhs <= 0 || n <= 0) return;
+  const int64_t chunk = chunk_for(n);
+  const int64_t nch = (n + chunk - 1) / chunk;
+  const dim3 g = dim3(unsigned(nch), unsigned(nrhs));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(dot_partial_kernel<double>, g, dim3(kT), 0, st, static_cast<const double2*>(a),
+                       static_cast<const double2*>(b), n, nrhs, rs, es, chunk, partial);
+  else
+    hipLaunchKernelGGL(dot_partial_kernel<float>, g, dim3(kT), 0, st, static_cast<const float2*>(a),
+                       static_cast<const float2*>(b), n, nrhs, rs, es, chunk, partial);
+  CRK_LAUNCH_CHECK();
+  reduce_partials(partial, nch, nrhs, 3, out3, st);
+}
+
+void reduce_partials(const double* partial, int64_t nchunk, int nrhs, int nv, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_partial_kernel, dim3(unsigned(nrhs * nv)), dim3(kT), 0, st, partial, nchunk, nrhs, nv, out);
+  CRK_LAUNCH_CHECK();
+}
+
+void mr_alpha(const double* sums3, int nrhs, double2* alpha, hipStream_t st) {
+  hipLaunchKernelGGL(mr_alpha_kernel, dim3(ceil_div(nrhs, 64)), dim3(64), 0, st, sums3, nrhs, alpha);
+  CRK_LAUNCH_CHECK();
+}
+
+void mr_update(int prec, void* psi, void* r, const void* q, const double2* alpha, int64_t n, int nrhs, bool rhs_inner,
+               hipStream_t st) {
+  const dim3 g(ceil_div(n * nrhs, kT));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(mr_update_kernel<double>, g, dim3(kT), 0, st, static_cast<double2*>(psi),
+                       static_cast<double2*>(r), static_cast<const double2*>(q), alpha, n, nrhs, int(rhs_inner));
+  else
+    hipLaunchKernelGGL(mr_update_kernel<float>, g, dim3(kT), 0, st, static_cast<float2*>(psi),
+                       static_cast<float2*>(r), static_cast<const float2*>(q), alpha, n, nrhs, int(rhs_inner));
+  CRK_LAUNCH_CHECK();
+}
+
+void inv_sqrt(const double* sums, int nv, int comp, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(inv_sqrt_kernel, dim3(ceil_div(n, 64)), dim3(64), 0, st, sums, nv, comp, n, out);
+  CRK_LAUNCH_CHECK();
+}
+
+void gaussian_fill(int prec, void* out, int64_t total, uint64_t seed, uint32_t stream, hipStream_t st) {
+  if (total <= 0) return;
+  const dim3 g(ceil_div(total, kT));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(gaussian_kernel<double>, g, dim3(kT), 0, st, static_cast<double2*>(out), total, seed, stream);
+  else
+    hipLaunchKernelGGL(gaussian_kernel<float>, g, dim3(kT), 0, st, static_cast<float2*>(out), total, seed, stream);
+  CRK_LAUNCH_CHECK();
+}
+
+}  // namespace crk

@@ -1,0 +1,238 @@
+// Multi-RHS Wilson-Dirac operator on the fine lattice.
+//
+// D psi(x) = (m0 + sum_mu w_mu) psi(x)
+//          - 1/2 sum_mu w_mu [(1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)]
+// in the chiral basis (gamma5 = diag(1,1,-1,-1)), w = (1,1,1,1/xi).
+//
+// Each (1 -+ gamma_mu) has rank 2, so every hop projects the neighbour spinor
+// to a half spinor (2 spins x 3 colours), multiplies by the SU(3) link and
+// rebuilds the lower spins from the upper ones.  One thread owns one site and
+// R right-hand sides: the eight links of the site are loaded once and reused
+// for all R spinors, and neighbour addresses come from a per-site table so any
+// site order (lexicographic or block-major) uses the same kernel.  Optionally
+// the kernel also emits per-workgroup partial sums <Dr, r> and <Dr, Dr> for
+// the minimal-residual smoother, so no separate pass over the fields is needed.
+#include "field.h"
+#include "kernels.h"
+
+namespace crk {
+
+namespace {
+
+template <class C> struct Half { C h[6]; };
+
+// Spin projection of psi onto the half spinor of (1 - sign*gamma_mu).
+template <int MU, int SIGN, class C>
+__device__ __forceinline__ void project(const C* s, C* h) {
+  // s[3*spin + colour]
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    C s0 = s[a], s1 = s[3 + a], s2 = s[6 + a], s3 = s[9 + a];
+    if constexpr (MU == 0) {
+      if constexpr (SIGN > 0) { h[a] = s0 + cmuli(s3); h[3 + a] = s1 + cmuli(s2); }
+      else { h[a] = s0 - cmuli(s3); h[3 + a] = s1 - cmuli(s2); }
+    } else if constexpr (MU == 1) {
+      if constexpr (SIGN > 0) { h[a] = s0 + s3; h[3 + a] = s1 - s2; }
+      else { h[a] = s0 - s3; h[3 + a] = s1 + s2; }
+    } else if constexpr (MU == 2) {
+      if constexpr (SIGN > 0) { h[a] = s0 + cmuli(s2); h[3 + a] = s1 - cmuli(s3); }
+      else { h[a] = s0 - cmuli(s2); h[3 + a] = s1 + cmuli(s3); }
+    } else {
+      if constexpr (SIGN > 0) { h[a] = s0 - s2; h[3 + a] = s1 - s3; }
+      else { h[a] = s0 + s2; h[3 + a] = s1 + s3; }
+    }
+  }
+}
+
+// acc += coef * (full spinor rebuilt from the link-multiplied half spinor g).
+template <int MU, int SIGN, class C, class T>
+__device__ __forceinline__ void accumulate(C* acc, const C* g, T coef) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    C g0 = g[a], g1 = g[3 + a];
+    C l2, l3;
+    if constexpr (MU == 0) {
+      if constexpr (SIGN > 0) { l2 = cscale(cmuli(g1), T(-1)); l3 = cscale(cmuli(g0), T(-1)); }
+      else { l2 = cmuli(g1); l3 = cmuli(g0); }
+    } else if constexpr (MU == 1) {
+      if constexpr (SIGN > 0) { l2 = cscale(g1, T(-1)); l3 = g0; }
+      else { l2 = g1; l3 = cscale(g0, T(-1)); }
+    } else if constexpr (MU == 2) {
+      if constexpr (SIGN > 0) { l2 = cscale(cmuli(g0), T(-1)); l3 = cmuli(g1); }
+      else { l2 = cmuli(g0); l3 = cscale(cmuli(g1), T(-1)); }
+    } else {
+      if constexpr (SIGN > 0) { l2 = cscale(g0, T(-1)); l3 = cscale(g1, T(-1)); }
+      else { l2 = g0; l3 = g1; }
+    }
+    acc[a].x = fma(coef, g0.x, acc[a].x);     acc[a].y = fma(coef, g0.y, acc[a].y);
+    acc[3 + a].x = fma(coef, g1.x, acc[3 + a].x); acc[3 + a].y = fma(coef, g1.y, acc[3 + a].y);
+    acc[6 + a].x = fma(coef, l2.x, acc[6 + a].x); acc[6 + a].y = fma(coef, l2.y, acc[6 + a].y);
+    acc[9 + a].x = fma(coef, l3.x, acc[9 + a].x); acc[9 + a].y = fma(coef, l3.y, acc[9 + a].y);
+  }
+}
+
+// g = U h (forward) or U^dag h (backward), per half-spin.
+template <int SIGN, class C>
+__device__ __forceinline__ void link_mul(const C* u, const C* h, C* g) {
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      C t = czero<C>();
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if constexpr (SIGN > 0) cfma(t, u[3 * a + b], h[3 * sp + b]);
+        else cfmac(t, u[3 * b + a], h[3 * sp + b]);
+      }
+      g[3 * sp + a] = t;
+    }
+  }
+}
+
+template <int FORM, int R, int MU, int SIGN>
+__device__ __forceinline__ void hop(const FineView<FORM>& in, const GaugeView<FORM>& U, const int* __restrict__ nbr,
+                                    int64_t V, int64_t s, int r0, int nrhs,
+                                    typename Prec<FORM>::cx (&acc)[R][12], typename Prec<FORM>::real coef) {
+  using C = typename Prec<FORM>::cx;
+  const int64_t y = nbr[int64_t(2 * MU + (SIGN > 0 ? 0 : 1)) * V + s];
+  C u[9];
+  U.load(MU, SIGN > 0 ? s : y, u);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r0 + r < nrhs) {
+      C psi[12], h[6], g[6];
+      in.load(r0 + r, y, psi);
+      project<MU, SIGN>(psi, h);
+      link_mul<SIGN>(u, h, g);
+      accumulate<MU, SIGN>(acc[r], g, coef);
+    }
+  }
+}
+
+template <int FORM, int R>
+__global__ __launch_bounds__(256) void wilson_kernel(FineView<FORM> in, FineView<FORM> out, GaugeView<FORM> U,
+                                                     const int* __restrict__ nbr, int64_t V, int nrhs, int ngroups,
+                                                     typename Prec<FORM>::real diag, float4 hw_f, double4 hw_d,
+                                                     double* __restrict__ partial) {
+  using C = typename Prec<FORM>::cx;
+  using T = typename Prec<FORM>::real;
+  const uint32_t L = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int64_t sb = L / ngroups;
+  const int g = L % ngroups;
+  const int64_t s = sb * blockDim.x + threadIdx.x;
+  const int r0 = g * R;
+  const bool live = s < V;
+  T hw[4];
+  if constexpr (FORM == CRK_FORM_FP64) { hw[0] = hw_d.x; hw[1] = hw_d.y; hw[2] = hw_d.z; hw[3] = hw_d.w; }
+  else { hw[0] = hw_f.x; hw[1] = hw_f.y; hw[2] = hw_f.z; hw[3] = hw_f.w; }
+
+  C acc[R][12];
+  double dqr_re[R], dqr_im[R], dqq[R];
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r0 + r < nrhs) {
+        C psi[12];
+        in.load(r0 + r, s, psi);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[r][c] = cscale(psi[c], diag);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[r][c] = czero<C>();
+      }
+    }
+    hop<FORM, R, 0, +1>(in, U, nbr, V, s, r0, nrhs, acc, hw[0]);
+    hop<FORM, R, 0, -1>(in, U, nbr, V, s, r0, nrhs, acc, hw[0]);
+    hop<FORM, R, 1, +1>(in, U, nbr, V, s, r0, nrhs, acc, hw[1]);
+    hop<FORM, R, 1, -1>(in, U, nbr, V, s, r0, nrhs, acc, hw[1]);
+    hop<FORM, R, 2, +1>(in, U, nbr, V, s, r0, nrhs, acc, hw[2]);
+    hop<FORM, R, 2, -1>(in, U, nbr, V, s, r0, nrhs, acc, hw[2]);
+    hop<FORM, R, 3, +1>(in, U, nbr, V, s, r0, nrhs, acc, hw[3]);
+    hop<FORM, R, 3, -1>(in, U, nbr, V, s, r0, nrhs, acc, hw[3]);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r0 + r < nrhs) out.store(r0 + r, s, acc[r]);
+  }
+  if (partial == nullptr) return;
+  // <q, r> and <q, q> with q = D r (this output) and r = the input at s.
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    dqr_re[r] = dqr_im[r] = dqq[r] = 0.0;
+    if (live && r0 + r < nrhs) {
+      C psi[12];
+      in.load(r0 + r, s, psi);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const C q = acc[r][c];
+        dqr_re[r] += double(q.x) * psi[c].x + double(q.y) * psi[c].y;
+        dqr_im[r] += double(q.x) * psi[c].y - double(q.y) * psi[c].x;
+        dqq[r] += double(q.x) * q.x + double(q.y) * q.y;
+      }
+    }
+  }
+  __shared__ double red[3 * R][4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double v0 = dqr_re[r], v1 = dqr_im[r], v2 = dqq[r];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      v0 += __shfl_xor(v0, o);
+      v1 += __shfl_xor(v1, o);
+      v2 += __shfl_xor(v2, o);
+    }
+    if (lane == 0) { red[3 * r][wid] = v0; red[3 * r + 1][wid] = v1; red[3 * r + 2][wid] = v2; }
+  }
+  __syncthreads();
+  if (threadIdx.x < 3 * R) {
+    const int r = threadIdx.x / 3, v = threadIdx.x % 3;
+    const int nw = blockDim.x / 64;
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[threadIdx.x][w];
+    if (r0 + r < nrhs) partial[(sb * nrhs + (r0 + r)) * 3 + v] = t;
+  }
+}
+
+template <int FORM, int R>
+void launch_wilson(const WilsonArgs& a, hipStream_t st) {
+  const int ngroups = (a.nrhs + R - 1) / R;
+  const int64_t nsb = (a.V + 255) / 256;
+  const int64_t nblk = nsb * ngroups;
+  if (nblk > 0x7fffffff) fail(CRK_EINVAL, "dslash grid too large");
+  FineView<FORM> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
+  GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), a.V};
+  float4 hwf = make_float4(float(a.hw[0]), float(a.hw[1]), float(a.hw[2]), float(a.hw[3]));
+  double4 hwd = make_double4(a.hw[0], a.hw[1], a.hw[2], a.hw[3]);
+  hipLaunchKernelGGL((wilson_kernel<FORM, R>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U, a.nbr, a.V,
+                     a.nrhs, ngroups, typename Prec<FORM>::real(a.diag), hwf, hwd, a.partial);
+  CRK_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+int64_t wilson_partial_blocks(int64_t V) { return (V + 255) / 256; }
+
+void wilson_apply(const WilsonArgs& a, hipStream_t st) {
+  if (a.nrhs <= 0 || a.V <= 0) return;
+  CRK_REQUIRE(a.in != a.out, "dslash: in and out must not alias");
+  switch (a.form) {
+    case CRK_FORM_FP64:
+      if (a.rhs_per_thread >= 2 && a.nrhs >= 2) launch_wilson<CRK_FORM_FP64, 2>(a, st);
+      else launch_wilson<CRK_FORM_FP64, 1>(a, st);
+      break;
+    case CRK_FORM_FP32:
+      if (a.rhs_per_thread >= 4 && a.nrhs >= 4) launch_wilson<CRK_FORM_FP32, 4>(a, st);
+      else if (a.rhs_per_thread >= 2 && a.nrhs >= 2) launch_wilson<CRK_FORM_FP32, 2>(a, st);
+      else launch_wilson<CRK_FORM_FP32, 1>(a, st);
+      break;
+    case CRK_FORM_FP16S:
+      if (a.rhs_per_thread >= 4 && a.nrhs >= 4) launch_wilson<CRK_FORM_FP16S, 4>(a, st);
+      else if (a.rhs_per_thread >= 2 && a.nrhs >= 2) launch_wilson<CRK_FORM_FP16S, 2>(a, st);
+      else launch_wilson<CRK_FORM_FP16S, 1>(a, st);
+      break;
+    default:
+      fail(CRK_EINVAL, "unknown precision form");
+  }
+}
+
+}  // namespace crk

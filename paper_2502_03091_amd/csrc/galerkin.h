@@ -1,0 +1,27 @@
+// Galerkin coarse operator of the fine Wilson level: interface.
+#pragma once
+
+#include "common.h"
+
+namespace crk {
+
+struct GalerkinArgs {
+  const double2* P;      // [2*ncoarse][k][nr] prolongator blocks (row c'*nb + l)
+  const double2* gauge;  // FP64 links [mu][9][V], fine device order (block-major)
+  const int* nbr;        // fine neighbours [8][V], device positions
+  int64_t V;
+  int nb;                // fine sites per block
+  int nr;                // 6*nb
+  int k;
+  double diag;           // m0 + sum w
+  double hw[4];          // -w_mu/2
+  int64_t ncoarse;       // number of blocks (coarse sites)
+  const int* pos_c;      // coarse device position of lexicographic coarse site (NULL = identity)
+  double2* links;        // out: [Vc][9][2k][2k] column-major blocks, coarse device order
+};
+
+// Computes X and Y_{+mu}, then Y_{-mu} from sigma3-hermiticity using the
+// coarse neighbour table nbr_c [8][Vc] (device positions).
+void galerkin_fine(const GalerkinArgs& A, const int* nbr_c, int64_t Vc, hipStream_t st);
+
+}  // namespace crk

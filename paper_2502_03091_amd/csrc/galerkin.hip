@@ -1,0 +1,224 @@
+// Galerkin coarse operator D_c = P^dag D P of the fine Wilson operator
+// (paper, Sec. 2, Eq. (4); P block diagonal with chirality-sparse blocks, Eq. (6)).
+//
+// With P(x) the 12 x 2k block of P at fine site x and H_{+-mu}(x) the Wilson hops
+// -w_mu/2 (1 -+ gamma_mu) (x) U:
+//   X(j)       = sum_{x in block j} P(x)^dag [ (m0 + sum w) P(x) + sum_{in-block hops} H P(x+-mu) ]
+//   Y_{+mu}(j) = sum_{x in block j, x+mu outside} P(x)^dag H_{+mu}(x) P(x+mu)
+//   Y_{-mu}(j) = sigma3 Y_{+mu}(j-mu)^dag sigma3          (gamma5-hermiticity of D)
+// One workgroup per (coarse site, part) with part 0 = X and parts 1..4 = Y_{+mu}.
+// For each fine site the hop results T = sum H P(y) (12 x 2k) are formed by
+// threads (column, colour) from the half-spinor projection, staged in LDS, and
+// contracted with P(x)^dag into per-thread register tiles of the 2k x 2k output.
+// Coarse links are stored per coarse site as 9 column-major 2k x 2k blocks:
+// index 0 = X, 1 + 2mu = Y_{+mu}, 2 + 2mu = Y_{-mu}.
+#include "galerkin.h"
+
+namespace crk {
+
+namespace {
+
+constexpr int kT = 256;
+
+// Projection of the (chirality-sparse) column onto the half spinor of (1 - sign gamma_mu).
+template <int MU, int SIGN>
+__device__ __forceinline__ void project_col(const double2 (&s)[4][3], double2 (&h)[2][3]) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const double2 s0 = s[0][b], s1 = s[1][b], s2 = s[2][b], s3 = s[3][b];
+    if constexpr (MU == 0) {
+      if constexpr (SIGN > 0) { h[0][b] = s0 + cmuli(s3); h[1][b] = s1 + cmuli(s2); }
+      else { h[0][b] = s0 - cmuli(s3); h[1][b] = s1 - cmuli(s2); }
+    } else if constexpr (MU == 1) {
+      if constexpr (SIGN > 0) { h[0][b] = s0 + s3; h[1][b] = s1 - s2; }
+      else { h[0][b] = s0 - s3; h[1][b] = s1 + s2; }
+    } else if constexpr (MU == 2) {
+      if constexpr (SIGN > 0) { h[0][b] = s0 + cmuli(s2); h[1][b] = s1 - cmuli(s3); }
+      else { h[0][b] = s0 - cmuli(s2); h[1][b] = s1 + cmuli(s3); }
+    } else {
+      if constexpr (SIGN > 0) { h[0][b] = s0 - s2; h[1][b] = s1 - s3; }
+      else { h[0][b] = s0 + s2; h[1][b] = s1 + s3; }
+    }
+  }
+}
+
+// t[spin] += coef * rebuilt spinor (colour a) from g0, g1.
+template <int MU, int SIGN>
+__device__ __forceinline__ void rebuild(double2 (&t)[4], double2 g0, double2 g1, double coef) {
+  double2 l2, l3;
+  if constexpr (MU == 0) {
+    if constexpr (SIGN > 0) { l2 = cscale(cmuli(g1), -1.0); l3 = cscale(cmuli(g0), -1.0); }
+    else { l2 = cmuli(g1); l3 = cmuli(g0); }
+  } else if constexpr (MU == 1) {
+    if constexpr (SIGN > 0) { l2 = cscale(g1, -1.0); l3 = g0; }
+    else { l2 = g1; l3 = cscale(g0, -1.0); }
+  } else if constexpr (MU == 2) {
+    if constexpr (SIGN > 0) { l2 = cscale(cmuli(g0), -1.0); l3 = cmuli(g1); }
+    else { l2 = cmuli(g0); l3 = cscale(cmuli(g1), -1.0); }
+  } else {
+    if constexpr (SIGN > 0) { l2 = cscale(g0, -1.0); l3 = cscale(g1, -1.0); }
+    else { l2 = g0; l3 = g1; }
+  }
+  t[0] = t[0] + cscale(g0, coef);
+  t[1] = t[1] + cscale(g1, coef);
+  t[2] = t[2] + cscale(l2, coef);
+  t[3] = t[3] + cscale(l3, coef);
+}
+
+// P(y)[:, col] as a 4x3 spinor (zero outside the column's chirality).
+__device__ __forceinline__ void load_pcol(const GalerkinArgs& A, int64_t y, int col, double2 (&s)[4][3]) {
+  const int k = A.k, beta = col / k, i = col % k;
+  const int64_t jy = y / A.nb, ly = y % A.nb;
+  const double2* p = A.P + ((2 * jy + beta) * k + i) * int64_t(A.nr) + ly;
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) s[sp][b] = make_double2(0, 0);
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) s[2 * beta + sp][b] = p[int64_t(3 * sp + b) * A.nb];
+}
+
+template <int MU, int SIGN>
+__device__ __forceinline__ void add_hop(const GalerkinArgs& A, int64_t x, int64_t y, int col, int a,
+                                        double2 (&t)[4]) {
+  double2 s[4][3], h[2][3];
+  load_pcol(A, y, col, s);
+  project_col<MU, SIGN>(s, h);
+  const double2* U = A.gauge + int64_t(MU) * 9 * A.V;
+  double2 g0 = make_double2(0, 0), g1 = make_double2(0, 0);
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    if constexpr (SIGN > 0) {
+      const double2 u = U[int64_t(3 * a + b) * A.V + x];
+      cfma(g0, u, h[0][b]);
+      cfma(g1, u, h[1][b]);
+    } else {
+      const double2 u = U[int64_t(3 * b + a) * A.V + y];
+      cfmac(g0, u, h[0][b]);
+      cfmac(g1, u, h[1][b]);
+    }
+  }
+  rebuild<MU, SIGN>(t, g0, g1, A.hw[MU]);
+}
+
+template <int MU, int SIGN>
+__device__ __forceinline__ void maybe_hop(const GalerkinArgs& A, int64_t x, int64_t j, int col, int a, int part,
+                                          double2 (&t)[4]) {
+  const int64_t y = A.nbr[int64_t(2 * MU + (SIGN > 0 ? 0 : 1)) * A.V + x];
+  const bool inside = (y / A.nb) == j;
+  if (part == 0 ? inside : (SIGN > 0 && MU == part - 1 && !inside)) add_hop<MU, SIGN>(A, x, y, col, a, t);
+}
+
+template <int TI>
+__global__ __launch_bounds__(kT) void galerkin_kernel(GalerkinArgs A) {
+  constexpr int N = 16 * TI;  // 2k
+  __shared__ double2 T[12][N];
+  __shared__ double2 Pc[6][N];
+  const int64_t j = blockIdx.x / 5;
+  const int part = blockIdx.x % 5;
+  const int k = A.k;
+  const int rg = threadIdx.x / 16, cg = threadIdx.x % 16;
+  double2 acc[TI][TI];
+#pragma unroll
+  for (int x = 0; x < TI; ++x)
+#pragma unroll
+    for (int y = 0; y < TI; ++y) acc[x][y] = make_double2(0, 0);
+
+  for (int l = 0; l < A.nb; ++l) {
+    const int64_t x = j * A.nb + l;
+    if (part > 0) {
+      const int64_t y = A.nbr[int64_t(2 * (part - 1)) * A.V + x];
+      if (y / A.nb == j) continue;  // uniform across the workgroup
+    }
+    __syncthreads();
+    // P(x) per column, compressed to its chirality's 6 components
+    for (int e = threadIdx.x; e < 6 * N; e += blockDim.x) {
+      const int c = e / N, col = e % N, beta = col / k, i = col % k;
+      Pc[c][col] = A.P[((2 * j + beta) * k + i) * int64_t(A.nr) + int64_t(c) * A.nb + l];
+    }
+    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) {
+      const int col = e / 3, a = e % 3;
+      double2 t[4];
+      for (int sp = 0; sp < 4; ++sp) t[sp] = make_double2(0, 0);
+      if (part == 0) {
+        // site term: (m0 + sum w) P(x)
+        const int beta = col / k, i = col % k;
+        const double2* p = A.P + ((2 * j + beta) * k + i) * int64_t(A.nr) + l;
+        t[2 * beta] = cscale(p[int64_t(a) * A.nb], A.diag);
+        t[2 * beta + 1] = cscale(p[int64_t(3 + a) * A.nb], A.diag);
+      }
+      maybe_hop<0, +1>(A, x, j, col, a, part, t);
+      maybe_hop<0, -1>(A, x, j, col, a, part, t);
+      maybe_hop<1, +1>(A, x, j, col, a, part, t);
+      maybe_hop<1, -1>(A, x, j, col, a, part, t);
+      maybe_hop<2, +1>(A, x, j, col, a, part, t);
+      maybe_hop<2, -1>(A, x, j, col, a, part, t);
+      maybe_hop<3, +1>(A, x, j, col, a, part, t);
+      maybe_hop<3, -1>(A, x, j, col, a, part, t);
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) T[3 * sp + a][col] = t[sp];
+    }
+    __syncthreads();
+    // acc[r][c] += sum_c' conj(P(x)[alpha_r*6 + c'][r]) T[alpha_r*6 + c'][c]
+#pragma unroll
+    for (int xr = 0; xr < TI; ++xr) {
+      const int r = rg * TI + xr;
+      const int ar = r / k;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double2 pr = Pc[c][r];
+#pragma unroll
+        for (int yc = 0; yc < TI; ++yc) cfmac(acc[xr][yc], pr, T[6 * ar + c][cg * TI + yc]);
+      }
+    }
+  }
+  // store column-major: link[jpos][part == 0 ? 0 : 1 + 2mu][col][row]
+  const int64_t jpos = A.pos_c ? A.pos_c[j] : j;
+  const int nbidx = part == 0 ? 0 : 1 + 2 * (part - 1);
+  double2* out = A.links + (jpos * 9 + nbidx) * int64_t(N) * N;
+#pragma unroll
+  for (int xr = 0; xr < TI; ++xr)
+#pragma unroll
+    for (int yc = 0; yc < TI; ++yc) {
+      const int r = rg * TI + xr, c = cg * TI + yc;
+      out[int64_t(c) * N + r] = acc[xr][yc];
+    }
+}
+
+// Y_{-mu}(j) = sigma3 Y_{+mu}(j - mu)^dag sigma3 on the coarse lattice (device positions).
+__global__ __launch_bounds__(kT) void backward_links_kernel(double2* __restrict__ links, const int* __restrict__ nbr_c,
+                                                            int64_t Vc, int N, int k) {
+  const int64_t jpos = blockIdx.x / 4;
+  const int mu = blockIdx.x % 4;
+  const int64_t jm = nbr_c[int64_t(2 * mu + 1) * Vc + jpos];
+  const double2* src = links + (jm * 9 + 1 + 2 * mu) * int64_t(N) * N;
+  double2* dst = links + (jpos * 9 + 2 + 2 * mu) * int64_t(N) * N;
+  for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+    const int c = e / N, r = e % N;  // dst element (r, c), column-major
+    const double sgn = ((r < k) == (c < k)) ? 1.0 : -1.0;
+    const double2 v = src[int64_t(r) * N + c];  // src element (c, r)
+    dst[int64_t(c) * N + r] = make_double2(sgn * v.x, -sgn * v.y);
+  }
+}
+
+}  // namespace
+
+void galerkin_fine(const GalerkinArgs& A, const int* nbr_c, int64_t Vc, hipStream_t st) {
+  const int N = 2 * A.k;
+  CRK_REQUIRE(N % 16 == 0 && N <= 128, "2k must be a multiple of 16 and <= 128");
+  const dim3 g = dim3(unsigned(A.ncoarse * 5));
+  switch (N / 16) {
+    case 1: hipLaunchKernelGGL(galerkin_kernel<1>, g, dim3(kT), 0, st, A); break;
+    case 2: hipLaunchKernelGGL(galerkin_kernel<2>, g, dim3(kT), 0, st, A); break;
+    case 3: hipLaunchKernelGGL(galerkin_kernel<3>, g, dim3(kT), 0, st, A); break;
+    case 4: hipLaunchKernelGGL(galerkin_kernel<4>, g, dim3(kT), 0, st, A); break;
+    default: fail(CRK_EINVAL, "2k above 64 is not supported by the Galerkin kernel");
+  }
+  CRK_LAUNCH_CHECK();
+  hipLaunchKernelGGL(backward_links_kernel, dim3(unsigned(Vc * 4)), dim3(kT), 0, st, A.links, nbr_c, Vc, N, A.k);
+  CRK_LAUNCH_CHECK();
+}
+
+}  // namespace crk

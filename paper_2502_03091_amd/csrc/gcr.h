@@ -1,0 +1,40 @@
+// Multi-RHS flexible GCR kernels: interface.
+#pragma once
+
+#include "blas.h"
+#include "common.h"
+
+namespace crk {
+
+constexpr int kMaxBasis = 32;  // directions per multidot pass (and per outer GCR cycle)
+constexpr int kMaxCoef = 64;   // stored directions of an inner GCR (coefficient stride)
+
+// nrhs vectors of n complex entries; entry e of rhs r at r*rs + e*es.
+struct FieldShape {
+  int64_t n;
+  int nrhs;
+  int64_t rs, es;
+  int64_t total() const { return n * nrhs; }
+};
+
+inline FieldShape fine_shape(int64_t V, int nrhs) { return FieldShape{12 * V, nrhs, 12 * V, 1}; }
+inline FieldShape coarse_shape(int64_t V, int N, int nrhs) { return FieldShape{int64_t(N) * V, nrhs, 1, nrhs}; }
+
+// Rows of the partial buffers (times nrhs * 2*kMaxBasis doubles for multidot).
+int64_t gcr_partial_rows(int64_t n);
+
+void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* w, const FieldShape& f, double* partial,
+                  const uint32_t* valid, double2* coef, hipStream_t st);
+void gcr_multiaxpy(int prec, const void* Z, const void* W, int64_t fstride, int nj, void* z, void* w,
+                   const double2* coef, const FieldShape& f, hipStream_t st);
+void gcr_scalars(const double* sums3, const int* active, int nrhs, double* inv, double2* a, int* breakdown,
+                 hipStream_t st);
+void gcr_update(int prec, void* z, void* w, void* x, void* r, const double* inv, const double2* a, const int* active,
+                const FieldShape& f, double* partial, double* rn2, hipStream_t st);
+void gcr_check(const double* partial, const FieldShape& f, double tol2, const double* b2, const int* breakdown,
+               int* active, int* iters, double* rn2, int* n_active, int* level_iters, hipStream_t st);
+void gcr_start(const double* sums3, int nrhs, double* b2, int* active, int* iters, int* n_active, hipStream_t st);
+void field_axpby(int prec, const void* x, void* y, double a, double b, int64_t total, hipStream_t st);
+void field_masked_copy(int prec, const void* x, void* y, const int* mask, const FieldShape& f, hipStream_t st);
+
+}  // namespace crk

@@ -1,0 +1,329 @@
+// Multi-RHS kernels of the flexible GCR solver (paper, Sec. 2 last paragraph:
+// the hierarchy preconditions a flexible outer solver such as GCR).
+//
+// Every right-hand side runs its own GCR recursion; the kernels carry one set
+// of scalars per RHS and a per-RHS active flag, so RHS that have converged are
+// frozen without a host round trip.  Per iteration (slot i):
+//   c_j   = <w_j, w_i>           for the valid stored directions j     (multidot)
+//   w_i  -= sum_j c_j w_j ; z_i -= sum_j c_j z_j   (classical Gram-Schmidt)
+//   a     = <w_i, r>/||w_i|| ;  w_i, z_i /= ||w_i||
+//   x    += a z_i ;  r -= a w_i ;  ||r||^2                          (update)
+// Reductions are deterministic (fixed thread ranges, fixed trees, fixed-order
+// final sums).  Fields are addressed as entry e of rhs r at r*rs + e*es.
+#include "gcr.h"
+
+namespace crk {
+
+namespace {
+
+constexpr int kT = 256;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+int64_t chunk_of(int64_t n) {
+  int64_t c = (n + 511) / 512;
+  return c < 2048 ? 2048 : c;
+}
+
+// partial[chunk][r][2*j + {0,1}] = chunk sum of conj(W_j) w
+template <class C>
+__global__ __launch_bounds__(kT) void multidot_kernel(const C* __restrict__ Wb, int64_t fstride, int nj,
+                                                      const C* __restrict__ w, int64_t n, int nrhs, int64_t rs,
+                                                      int64_t es, int64_t chunk, double* __restrict__ partial) {
+  __shared__ double sh[2 * kMaxBasis][4];
+  const int r = blockIdx.y;
+  const int64_t e0 = int64_t(blockIdx.x) * chunk, e1 = min(n, e0 + chunk);
+  double acc[2 * kMaxBasis];
+#pragma unroll
+  for (int q = 0; q < 2 * kMaxBasis; ++q) acc[q] = 0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int64_t idx = int64_t(r) * rs + e * es;
+    const C y = w[idx];
+#pragma unroll
+    for (int j = 0; j < kMaxBasis; ++j) {
+      if (j < nj) {
+        const C x = Wb[j * fstride + idx];
+        acc[2 * j] += double(x.x) * y.x + double(x.y) * y.y;
+        acc[2 * j + 1] += double(x.x) * y.y - double(x.y) * y.x;
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 2 * kMaxBasis; ++q) {
+    if (q < 2 * nj) {
+      const double t = wsum(acc[q]);
+      if (lane == 0) sh[q][wid] = t;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 2 * nj; q += blockDim.x)
+    partial[(int64_t(blockIdx.x) * nrhs + r) * (2 * kMaxBasis) + q] = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
+}
+
+// coef[r][j0 + j] = valid(r, j0 + j) ? sum over chunks : 0
+__global__ __launch_bounds__(kT) void multidot_reduce_kernel(const double* __restrict__ partial, int64_t nch, int nrhs,
+                                                             int j0, int nj, const uint32_t* __restrict__ valid,
+                                                             double2* __restrict__ coef) {
+  const int r = blockIdx.x;
+  for (int j = threadIdx.x; j < nj; j += blockDim.x) {
+    double re = 0, im = 0;
+    for (int64_t c = 0; c < nch; ++c) {
+      re += partial[(c * nrhs + r) * (2 * kMaxBasis) + 2 * j];
+      im += partial[(c * nrhs + r) * (2 * kMaxBasis) + 2 * j + 1];
+    }
+    const bool ok = valid ? ((valid[r] >> (j0 + j)) & 1u) : true;
+    coef[r * kMaxCoef + j0 + j] = ok ? make_double2(re, im) : make_double2(0, 0);
+  }
+}
+
+// z -= sum_j coef_j Z_j ; w -= sum_j coef_j W_j
+template <class C>
+__global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb, const C* __restrict__ Wb,
+                                                       int64_t fstride, int nj, C* __restrict__ z, C* __restrict__ w,
+                                                       const double2* __restrict__ coef, int64_t n, int nrhs,
+                                                       int64_t rs, int64_t es) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const int r = es == 1 ? int(t / n) : int(t % nrhs);
+  const int64_t e = es == 1 ? t % n : t / nrhs;
+  const int64_t idx = int64_t(r) * rs + e * es;
+  using T = decltype(C::x);
+  C zz = z[idx], ww = w[idx];
+  for (int j = 0; j < nj; ++j) {
+    const double2 cd = coef[r * kMaxCoef + j];
+    if (cd.x == 0.0 && cd.y == 0.0) continue;
+    const C c = mk<C>(T(-cd.x), T(-cd.y));
+    cfma(zz, c, Zb[j * fstride + idx]);
+    cfma(ww, c, Wb[j * fstride + idx]);
+  }
+  z[idx] = zz;
+  w[idx] = ww;
+}
+
+// From sums3[r] = (<w,r>, ||w||^2): inv[r] = 1/||w||, a[r] = <w,r>/||w|| (zero unless active and finite).
+__global__ void scalars_kernel(const double* __restrict__ sums3, const int* __restrict__ active, int nrhs,
+                               double* __restrict__ inv, double2* __restrict__ a, int* __restrict__ breakdown) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const double ww = sums3[3 * r + 2];
+  const double nw = sqrt(ww);
+  const bool ok = active[r] && ww > 0.0 && isfinite(nw);
+  inv[r] = ok ? 1.0 / nw : 0.0;
+  a[r] = ok ? make_double2(sums3[3 * r] / nw, sums3[3 * r + 1] / nw) : make_double2(0, 0);
+  if (breakdown) breakdown[r] = active[r] && !ok;
+}
+
+// w *= inv; z *= inv; (active) x += a z; r -= a w; partial ||r||^2
+template <class C>
+__global__ __launch_bounds__(kT) void update_kernel(C* __restrict__ z, C* __restrict__ w, C* __restrict__ x,
+                                                    C* __restrict__ res, const double* __restrict__ inv,
+                                                    const double2* __restrict__ a, const int* __restrict__ active,
+                                                    int64_t n, int nrhs, int64_t rs, int64_t es, int64_t chunk,
+                                                    double* __restrict__ partial) {
+  __shared__ double sh[4];
+  using T = decltype(C::x);
+  const int r = blockIdx.y;
+  const int64_t e0 = int64_t(blockIdx.x) * chunk, e1 = min(n, e0 + chunk);
+  const T s = T(inv[r]);
+  const bool act = active[r] != 0;
+  const C ar = mk<C>(T(a[r].x), T(a[r].y));
+  double acc = 0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int64_t idx = int64_t(r) * rs + e * es;
+    const C zn = cscale(z[idx], s), wn = cscale(w[idx], s);
+    z[idx] = zn;
+    w[idx] = wn;
+    C rr = res[idx];
+    if (act) {
+      C xx = x[idx];
+      cfma(xx, ar, zn);
+      x[idx] = xx;
+      const C aw = cmul(ar, wn);
+      rr.x -= aw.x;
+      rr.y -= aw.y;
+      res[idx] = rr;
+    }
+    acc += double(rr.x) * rr.x + double(rr.y) * rr.y;
+  }
+  const double t = wsum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[int64_t(blockIdx.x) * nrhs + r] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// rn2[r] = sum of partials; convergence bookkeeping of an inner solve.
+__global__ void check_kernel(const double* __restrict__ partial, int64_t nch, int nrhs, double tol2,
+                             const double* __restrict__ b2, const int* __restrict__ breakdown, int* __restrict__ active,
+                             int* __restrict__ iters, double* __restrict__ rn2, int* __restrict__ n_active,
+                             int* __restrict__ level_iters) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
+    double s = 0;
+    for (int64_t c = 0; c < nch; ++c) s += partial[c * nrhs + r];
+    rn2[r] = s;
+    if (active[r]) {
+      iters[r] += 1;
+      if (level_iters) level_iters[r] += 1;
+      const bool bd = breakdown ? breakdown[r] != 0 : false;
+      if (bd || !(s > tol2 * b2[r])) active[r] = 0;
+    }
+    if (active[r]) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *n_active = cnt;
+}
+
+// Start of an inner solve: x = 0, r = b, b2 = ||b||^2 from sums3, active = b2 > 0, iters = 0.
+__global__ void start_kernel(const double* __restrict__ sums3, int nrhs, double* __restrict__ b2,
+                             int* __restrict__ active, int* __restrict__ iters, int* __restrict__ n_active) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
+    const double s = sums3[3 * r + 2];
+    b2[r] = s;
+    active[r] = s > 0.0;
+    iters[r] = 0;
+    if (s > 0.0) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *n_active = cnt;
+}
+
+template <class C>
+__global__ __launch_bounds__(kT) void axpby_kernel(const C* __restrict__ x, C* __restrict__ y, double a, double b,
+                                                   int64_t total) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  using T = decltype(C::x);
+  const C xv = x[i];
+  C yv = b == 0.0 ? mk<C>(T(0), T(0)) : cscale(y[i], T(b));
+  yv.x += T(a) * xv.x;
+  yv.y += T(a) * xv.y;
+  y[i] = yv;
+}
+
+// y[r] = x[r] for the RHS with mask[r] != 0 (fine or coarse layout)
+template <class C>
+__global__ __launch_bounds__(kT) void masked_copy_kernel(const C* __restrict__ x, C* __restrict__ y,
+                                                         const int* __restrict__ mask, int64_t n, int nrhs, int64_t rs,
+                                                         int64_t es) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const int r = es == 1 ? int(t / n) : int(t % nrhs);
+  if (!mask[r]) return;
+  const int64_t e = es == 1 ? t % n : t / nrhs;
+  const int64_t idx = int64_t(r) * rs + e * es;
+  y[idx] = x[idx];
+}
+
+}  // namespace
+
+int64_t gcr_partial_rows(int64_t n) { return (n + chunk_of(n) - 1) / chunk_of(n); }
+
+void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* w, const FieldShape& f, double* partial,
+                  const uint32_t* valid, double2* coef, hipStream_t st) {
+  if (nj <= 0) return;
+  CRK_REQUIRE(nj <= kMaxCoef, "GCR basis above 64 vectors");
+  CRK_REQUIRE(valid == nullptr || nj <= 32, "masked GCR basis above 32 vectors");
+  const int64_t chunk = chunk_of(f.n), nch = (f.n + chunk - 1) / chunk;
+  const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
+  const size_t esz = prec == CRK_FORM_FP64 ? sizeof(double2) : sizeof(float2);
+  for (int j0 = 0; j0 < nj; j0 += kMaxBasis) {
+    const int nc = nj - j0 < kMaxBasis ? nj - j0 : kMaxBasis;
+    const void* Wj = static_cast<const char*>(W) + esz * size_t(j0) * size_t(fstride);
+    if (prec == CRK_FORM_FP64)
+      hipLaunchKernelGGL(multidot_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(Wj), fstride, nc,
+                         static_cast<const double2*>(w), f.n, f.nrhs, f.rs, f.es, chunk, partial);
+    else
+      hipLaunchKernelGGL(multidot_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(Wj), fstride, nc,
+                         static_cast<const float2*>(w), f.n, f.nrhs, f.rs, f.es, chunk, partial);
+    CRK_LAUNCH_CHECK();
+    hipLaunchKernelGGL(multidot_reduce_kernel, dim3(unsigned(f.nrhs)), dim3(64), 0, st, partial, nch, f.nrhs, j0, nc,
+                       valid, coef);
+    CRK_LAUNCH_CHECK();
+  }
+}
+
+void gcr_multiaxpy(int prec, const void* Z, const void* W, int64_t fstride, int nj, void* z, void* w,
+                   const double2* coef, const FieldShape& f, hipStream_t st) {
+  if (nj <= 0) return;
+  CRK_REQUIRE(nj <= kMaxCoef, "GCR basis above 64 vectors");
+  const dim3 g(ceil_div(f.n * f.nrhs, kT));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(multiaxpy_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(Z),
+                       static_cast<const double2*>(W), fstride, nj, static_cast<double2*>(z), static_cast<double2*>(w),
+                       coef, f.n, f.nrhs, f.rs, f.es);
+  else
+    hipLaunchKernelGGL(multiaxpy_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(Z),
+                       static_cast<const float2*>(W), fstride, nj, static_cast<float2*>(z), static_cast<float2*>(w),
+                       coef, f.n, f.nrhs, f.rs, f.es);
+  CRK_LAUNCH_CHECK();
+}
+
+void gcr_scalars(const double* sums3, const int* active, int nrhs, double* inv, double2* a, int* breakdown,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(scalars_kernel, dim3(ceil_div(nrhs, 64)), dim3(64), 0, st, sums3, active, nrhs, inv, a, breakdown);
+  CRK_LAUNCH_CHECK();
+}
+
+void gcr_update(int prec, void* z, void* w, void* x, void* r, const double* inv, const double2* a, const int* active,
+                const FieldShape& f, double* partial, double* rn2, hipStream_t st) {
+  const int64_t chunk = chunk_of(f.n), nch = (f.n + chunk - 1) / chunk;
+  const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(update_kernel<double2>, g, dim3(kT), 0, st, static_cast<double2*>(z), static_cast<double2*>(w),
+                       static_cast<double2*>(x), static_cast<double2*>(r), inv, a, active, f.n, f.nrhs, f.rs, f.es,
+                       chunk, partial);
+  else
+    hipLaunchKernelGGL(update_kernel<float2>, g, dim3(kT), 0, st, static_cast<float2*>(z), static_cast<float2*>(w),
+                       static_cast<float2*>(x), static_cast<float2*>(r), inv, a, active, f.n, f.nrhs, f.rs, f.es,
+                       chunk, partial);
+  CRK_LAUNCH_CHECK();
+  if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
+}
+
+void gcr_check(const double* partial, const FieldShape& f, double tol2, const double* b2, const int* breakdown,
+               int* active, int* iters, double* rn2, int* n_active, int* level_iters, hipStream_t st) {
+  const int64_t chunk = chunk_of(f.n), nch = (f.n + chunk - 1) / chunk;
+  hipLaunchKernelGGL(check_kernel, dim3(1), dim3(64), 0, st, partial, nch, f.nrhs, tol2, b2, breakdown, active, iters,
+                     rn2, n_active, level_iters);
+  CRK_LAUNCH_CHECK();
+}
+
+void gcr_start(const double* sums3, int nrhs, double* b2, int* active, int* iters, int* n_active, hipStream_t st) {
+  hipLaunchKernelGGL(start_kernel, dim3(1), dim3(64), 0, st, sums3, nrhs, b2, active, iters, n_active);
+  CRK_LAUNCH_CHECK();
+}
+
+void field_axpby(int prec, const void* x, void* y, double a, double b, int64_t total, hipStream_t st) {
+  if (total <= 0) return;
+  const dim3 g(ceil_div(total, kT));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(axpby_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(x),
+                       static_cast<double2*>(y), a, b, total);
+  else
+    hipLaunchKernelGGL(axpby_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(x),
+                       static_cast<float2*>(y), a, b, total);
+  CRK_LAUNCH_CHECK();
+}
+
+void field_masked_copy(int prec, const void* x, void* y, const int* mask, const FieldShape& f, hipStream_t st) {
+  const dim3 g(ceil_div(f.n * f.nrhs, kT));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(masked_copy_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(x),
+                       static_cast<double2*>(y), mask, f.n, f.nrhs, f.rs, f.es);
+  else
+    hipLaunchKernelGGL(masked_copy_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(x),
+                       static_cast<float2*>(y), mask, f.n, f.nrhs, f.rs, f.es);
+  CRK_LAUNCH_CHECK();
+}
+
+}  // namespace crk

@@ -1,0 +1,375 @@
+// Multigrid setup (paper, Sec. 2 Eq. (1), Sec. 3 Eqs. (2), (5), (6), Sec. 2 Eq. (4)).
+//
+// For every coarsening step l: MR smoother on D_l psi_i ~ 0 over m' vectors
+// (one multi-RHS operator launch per sweep with the <Dr,r>, <Dr,Dr> partial
+// sums fused into it), normalisation, chiral split + batched block SVD
+// truncated to k per chirality (-> P, sigma), and the Galerkin coarse operator
+// D_{l+1} = P^dag D_l P stored in FP64 with FP32 / FP16S copies.
+#include "mg.h"
+
+#include <cmath>
+#include <cstring>
+
+#include "blas.h"
+#include "coarse.h"
+#include "galerkin.h"
+#include "transfer.h"
+
+namespace crk {
+
+namespace {
+
+struct EventTimer {
+  hipEvent_t e[8];
+  int n = 0;
+  explicit EventTimer(int count) : n(count) {
+    for (int i = 0; i < n; ++i) CRK_HIP(hipEventCreate(&e[i]));
+  }
+  ~EventTimer() {
+    for (int i = 0; i < n; ++i) (void)hipEventDestroy(e[i]);
+  }
+  void mark(int i, hipStream_t st) { CRK_HIP(hipEventRecord(e[i], st)); }
+  double sec(int a, int b) {
+    float ms = 0;
+    CRK_HIP(hipEventElapsedTime(&ms, e[a], e[b]));
+    return ms * 1e-3;
+  }
+};
+
+int64_t prod4(const int d[4]) { return int64_t(d[0]) * d[1] * d[2] * d[3]; }
+
+void validate(const Lattice* L, const crk_mg_params& p) {
+  CRK_REQUIRE(p.n_levels == 2 || p.n_levels == 3, "n_levels must be 2 or 3");
+  CRK_REQUIRE(p.setup_form == CRK_FORM_FP64 || p.setup_form == CRK_FORM_FP32, "setup_form must be FP64 or FP32");
+  int dims[4];
+  std::memcpy(dims, L->dims, sizeof(dims));
+  int N = 12;
+  for (int l = 0; l < p.n_levels - 1; ++l) {
+    for (int mu = 0; mu < 4; ++mu) {
+      CRK_REQUIRE(p.block[l][mu] >= 1, "block extents must be >= 1");
+      CRK_REQUIRE(dims[mu] % p.block[l][mu] == 0,
+                  "block extent " + std::to_string(p.block[l][mu]) + " does not divide lattice extent " +
+                      std::to_string(dims[mu]) + " at level " + std::to_string(l));
+    }
+    const int nb = p.block[l][0] * p.block[l][1] * p.block[l][2] * p.block[l][3];
+    const int nr = (N / 2) * nb;
+    CRK_REQUIRE(p.m_prime[l] >= 1 && p.m_prime[l] <= 64, "m' must be in [1, 64]");
+    CRK_REQUIRE(p.k[l] >= 8 && p.k[l] % 8 == 0 && p.k[l] <= 32,
+                "k must be a multiple of 8 in [8, 32] (2k is the MFMA tile height)");
+    CRK_REQUIRE(p.k[l] <= p.m_prime[l], "k must not exceed m'");
+    CRK_REQUIRE(p.k[l] <= nr, "k must not exceed the block rows N_r = (N/2)*|block|");
+    CRK_REQUIRE(p.n_smooth[l] >= 0, "n_smooth must be >= 0");
+    for (int mu = 0; mu < 4; ++mu) dims[mu] /= p.block[l][mu];
+    N = 2 * p.k[l];
+  }
+}
+
+}  // namespace
+
+
+
+// ------------------------------------------------------------------ level operators
+void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int nrhs, hipStream_t st, double* partial,
+                 bool negate) {
+  if (l == 0) {
+    Lattice* L = H->lat;
+    WilsonArgs a{};
+    a.form = form;
+    a.in = in;
+    a.out = out;
+    a.gauge = H->fine_gauge[form].p;
+    a.nbr = H->fine_geo.nbr.as<int>();
+    a.V = H->fine_geo.V;
+    a.nrhs = nrhs;
+    a.diag = negate ? -L->diag() : L->diag();
+    L->hw(a.hw);
+    if (negate)
+      for (double& h : a.hw) h = -h;
+    a.partial = partial;
+    a.rhs_per_thread = 4;
+    wilson_apply(a, st);
+  } else {
+    const CoarseLevel& c = H->coarse[l - 1];
+    CRK_REQUIRE(partial == nullptr, "coarse apply has no fused reduction");
+    coarse_apply(form, c.N, c.links[form].p, in, out, c.geo.nbr.as<int>(), c.V, nrhs, negate, st);
+  }
+}
+
+static TransferGeom transfer_geom(Hierarchy* H, int l, int nrhs) {
+  const Transfer& t = H->T[l];
+  TransferGeom g{};
+  g.h = t.h;
+  g.nb = t.nb;
+  g.k = t.k;
+  g.nblocks = t.nblocks;
+  const int64_t V = H->V(l);
+  if (l == 0) { g.vr = 12 * V; g.vc = V; g.vs = 1; }
+  else { g.vr = 1; g.vc = nrhs; g.vs = int64_t(H->N(l)) * nrhs; }
+  g.pos_c = H->coarse[l].geo.pos.as<int>();
+  return g;
+}
+
+void level_restrict(Hierarchy* H, int l, int form, const void* fine, void* coarse, int nrhs, hipStream_t st) {
+  const TransferGeom g = transfer_geom(H, l, nrhs);
+  const bool d = form == CRK_FORM_FP64;
+  transfer_restrict(d ? CRK_FORM_FP64 : CRK_FORM_FP32, g, d ? H->T[l].P64.p : H->T[l].P32.p, fine, coarse, nrhs, st);
+}
+
+void level_prolong(Hierarchy* H, int l, int form, const void* coarse, void* fine, int nrhs, bool add, hipStream_t st) {
+  const TransferGeom g = transfer_geom(H, l, nrhs);
+  const bool d = form == CRK_FORM_FP64;
+  transfer_prolong(d ? CRK_FORM_FP64 : CRK_FORM_FP32, g, d ? H->T[l].P64.p : H->T[l].P32.p, coarse, fine, nrhs, add,
+                   st);
+}
+
+// ------------------------------------------------------------------ setup
+namespace {
+
+// Convert a host complex128 [m][V][N] block (lexicographic sites) to the rhs-inner
+// coarse layout [pos][N][m] on the device.
+__global__ void coarse_import_kernel(const double2* __restrict__ src, void* dst, int dst_double,
+                                     const int* __restrict__ pos, int64_t V, int N, int m) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= V * N * m) return;
+  const int64_t r = i / (V * N), rem = i % (V * N), s = rem / N, c = rem % N;
+  const int64_t p = pos ? pos[s] : s;
+  const int64_t o = (p * N + c) * m + r;
+  if (dst_double) static_cast<double2*>(dst)[o] = src[i];
+  else static_cast<float2*>(dst)[o] = make_float2(float(src[i].x), float(src[i].y));
+}
+
+__global__ void coarse_export_kernel(const void* src, int src_double, double2* __restrict__ dst,
+                                     const int* __restrict__ pos, int64_t V, int N, int m) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= V * N * m) return;
+  const int64_t r = i / (V * N), rem = i % (V * N), s = rem / N, c = rem % N;
+  const int64_t p = pos ? pos[s] : s;
+  const int64_t o = (p * N + c) * m + r;
+  if (src_double) dst[i] = static_cast<const double2*>(src)[o];
+  else { const float2 v = static_cast<const float2*>(src)[o]; dst[i] = make_double2(v.x, v.y); }
+}
+
+void setup_step(Hierarchy* H, int l, hipStream_t st) {
+  const crk_mg_params& p = H->params;
+  Transfer& t = H->T[l];
+  StageTiming& tm = H->timing[l];
+  const int m = p.m_prime[l];
+  const int form = p.setup_form;
+  const int64_t V = H->V(l);
+  const int N = H->N(l);
+  const int64_t n = int64_t(N) * V;       // entries per vector
+  const bool inner = l > 0;               // coarse fields are rhs-inner
+  const size_t esz = form == CRK_FORM_FP64 ? sizeof(double2) : sizeof(float2);
+  EventTimer ev(6);
+  ev.mark(0, st);
+
+  // ---- test vectors
+  DevBuf& psi = H->vectors[l];
+  psi.alloc(esz * n * m);
+  H->vec_form[l] = form;
+  if (p.init_vectors[l]) {
+    DevBuf h(sizeof(double2) * n * m);
+    CRK_HIP(hipMemcpyAsync(h.p, p.init_vectors[l], sizeof(double2) * n * m, hipMemcpyHostToDevice, st));
+    if (!inner) {
+      field_import(form, h.as<double2>(), psi.p, H->fine_geo.pos.as<int>(), V, 12, m, st);
+    } else {
+      hipLaunchKernelGGL(coarse_import_kernel, dim3(ceil_div(n * m, 256)), dim3(256), 0, st, h.as<double2>(), psi.p,
+                         int(form == CRK_FORM_FP64), H->geo(l).pos.as<int>(), V, N, m);
+      CRK_LAUNCH_CHECK();
+    }
+    CRK_HIP(hipStreamSynchronize(st));  // h is freed at scope exit
+  } else {
+    gaussian_fill(form, psi.p, n * m, p.seed, uint32_t(l), st);
+  }
+
+  // ---- MR smoother on D psi ~ 0:  r = -D psi; repeat q = D r, alpha, psi += alpha r, r -= alpha q
+  DevBuf r(esz * n * m), q(esz * n * m);
+  const int64_t nsb = wilson_partial_blocks(V);
+  const int64_t ndp = rhs_dot_partials(n);
+  DevBuf partial(sizeof(double) * 3 * m * (nsb > ndp ? nsb : ndp));
+  DevBuf sums(sizeof(double) * 3 * m), alpha(sizeof(double2) * m);
+  level_apply(H, l, form, psi.p, r.p, m, st, nullptr, /*negate=*/true);
+  const int64_t rs = inner ? 1 : n, es = inner ? m : 1;
+  // events around every fine operator launch; read once after the stage
+  std::vector<hipEvent_t> dev_ev(inner ? 0 : 2 * size_t(p.n_smooth[l]));
+  for (auto& e : dev_ev) CRK_HIP(hipEventCreate(&e));
+  for (int it = 0; it < p.n_smooth[l]; ++it) {
+    if (!inner) {
+      CRK_HIP(hipEventRecord(dev_ev[2 * it], st));
+      level_apply(H, l, form, r.p, q.p, m, st, partial.as<double>());
+      CRK_HIP(hipEventRecord(dev_ev[2 * it + 1], st));
+      reduce_partials(partial.as<double>(), nsb, m, 3, sums.as<double>(), st);
+    } else {
+      level_apply(H, l, form, r.p, q.p, m, st);
+      // sums = (<q, r>, <q, q>)
+      rhs_dot(form, q.p, r.p, n, m, rs, es, partial.as<double>(), sums.as<double>(), st);
+    }
+    mr_alpha(sums.as<double>(), m, alpha.as<double2>(), st);
+    mr_update(form, psi.p, r.p, q.p, alpha.as<double2>(), n, m, inner, st);
+  }
+  ev.mark(1, st);
+  double dsum = 0;
+  if (!dev_ev.empty()) {
+    CRK_HIP(hipEventSynchronize(dev_ev.back()));
+    for (int it = 0; it < p.n_smooth[l]; ++it) {
+      float ms = 0;
+      CRK_HIP(hipEventElapsedTime(&ms, dev_ev[2 * it], dev_ev[2 * it + 1]));
+      dsum += ms * 1e-3;
+    }
+  }
+  for (auto& e : dev_ev) (void)hipEventDestroy(e);
+  tm.dslash_count = inner ? 0 : p.n_smooth[l];
+  tm.dslash_avg = p.n_smooth[l] > 0 && !inner ? dsum / p.n_smooth[l] : 0;
+
+  // ---- normalisation factors 1/||psi_i||
+  DevBuf& inv = H->inv_norm[l];
+  inv.alloc(sizeof(double) * m);
+  rhs_dot(form, psi.p, nullptr, n, m, rs, es, partial.as<double>(), sums.as<double>(), st);
+  if (p.normalize) {
+    inv_sqrt(sums.as<double>(), 3, 2, m, inv.as<double>(), st);
+  } else {
+    std::vector<double> ones(m, 1.0);
+    CRK_HIP(hipMemcpyAsync(inv.p, ones.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+    CRK_HIP(hipStreamSynchronize(st));
+  }
+
+  // ---- chiral split + block SVD truncation -> P, sigma
+  ChiralSrc src{};
+  if (!inner) { src.si = n; src.sc = V; src.ss = 1; }
+  else { src.si = 1; src.sc = m; src.ss = int64_t(N) * m; }
+  src.h = N / 2;
+  src.nb = t.nb;
+  src.m = m;
+  src.nblocks = t.nblocks;
+  DevBuf work(svd_work_bytes(m, t.nr, t.nblocks));
+  SvdWork w = svd_work_carve(work.p, m, t.nr, t.nblocks);
+  t.P64.alloc(sizeof(double2) * 2 * t.nblocks * t.k * t.nr);
+  t.P32.alloc(sizeof(float2) * 2 * t.nblocks * t.k * t.nr);
+  t.nsig = m < t.nr ? m : t.nr;
+  t.sigma.alloc(sizeof(double) * 2 * t.nblocks * t.nsig);
+  chiral_svd(src, form == CRK_FORM_FP64, psi.p, inv.as<double>(), t.k, w, t.P64.as<double2>(),
+             t.sigma.as<double>(), st);
+  field_convert(CRK_FORM_FP64, t.P64.p, CRK_FORM_FP32, t.P32.p, 2 * t.nblocks * t.k * t.nr, 1, 1, st);
+  ev.mark(2, st);
+
+  // ---- Galerkin coarse operator
+  CoarseLevel& c = H->coarse[l];
+  c.links[0].alloc(coarse_links_bytes(CRK_FORM_FP64, c.V, c.N));
+  if (l == 0) {
+    GalerkinArgs g{};
+    g.P = t.P64.as<double2>();
+    g.gauge = H->fine_gauge[0].as<double2>();
+    g.nbr = H->fine_geo.nbr.as<int>();
+    g.V = V;
+    g.nb = t.nb;
+    g.nr = t.nr;
+    g.k = t.k;
+    g.diag = H->lat->diag();
+    H->lat->hw(g.hw);
+    g.ncoarse = t.nblocks;
+    g.pos_c = c.geo.pos.as<int>();
+    g.links = c.links[0].as<double2>();
+    galerkin_fine(g, c.geo.nbr.as<int>(), c.V, st);
+  } else {
+    fail(CRK_EINVAL, "three-level hierarchies are not available in this build");
+  }
+  c.links[1].alloc(coarse_links_bytes(CRK_FORM_FP32, c.V, c.N));
+  c.links[2].alloc(coarse_links_bytes(CRK_FORM_FP16S, c.V, c.N));
+  coarse_links_convert(c.links[0].p, CRK_FORM_FP32, c.links[1].p, c.V, c.N, st);
+  coarse_links_convert(c.links[0].p, CRK_FORM_FP16S, c.links[2].p, c.V, c.N, st);
+  ev.mark(3, st);
+  CRK_HIP(hipStreamSynchronize(st));
+  tm.smoother = ev.sec(0, 1);
+  tm.svd = ev.sec(1, 2);
+  tm.galerkin = ev.sec(2, 3);
+  tm.total = ev.sec(0, 3);
+}
+
+}  // namespace
+
+Hierarchy* mg_setup(Lattice* L, const crk_mg_params& p) {
+  CRK_REQUIRE(L->gauge_loaded, "gauge field not loaded");
+  validate(L, p);
+  auto H = std::make_unique<Hierarchy>();
+  H->lat = L;
+  L->refs++;
+  try {
+    H->params = p;
+    H->nlev = p.n_levels;
+    CRK_HIP(hipStreamCreateWithFlags(&H->stream, hipStreamNonBlocking));
+    hipStream_t st = H->stream;
+    H->fine_geo.build(L->dims, p.block[0], st);
+    for (int f = 0; f < 3; ++f) {
+      H->fine_gauge[f].alloc(store_bytes(f) * 36 * L->V);
+      gauge_convert(f, L->U64.as<double2>(), H->fine_gauge[f].p, H->fine_geo.pos.as<int>(), L->V, st);
+    }
+    int dims[4];
+    std::memcpy(dims, L->dims, sizeof(dims));
+    int N = 12;
+    H->coarse.resize(H->nlev - 1);
+    H->T.resize(H->nlev - 1);
+    H->vectors.resize(H->nlev - 1);
+    H->inv_norm.resize(H->nlev - 1);
+    H->vec_form.assign(H->nlev - 1, p.setup_form);
+    H->timing.resize(H->nlev - 1);
+    for (int l = 0; l < H->nlev - 1; ++l) {
+      Transfer& t = H->T[l];
+      std::memcpy(t.block, p.block[l], sizeof(t.block));
+      t.nb = t.block[0] * t.block[1] * t.block[2] * t.block[3];
+      t.h = N / 2;
+      t.nr = t.h * t.nb;
+      t.m = p.m_prime[l];
+      t.k = p.k[l];
+      int cd[4];
+      for (int mu = 0; mu < 4; ++mu) cd[mu] = dims[mu] / t.block[mu];
+      t.nblocks = prod4(cd);
+      CoarseLevel& c = H->coarse[l];
+      std::memcpy(c.dims, cd, sizeof(cd));
+      c.V = t.nblocks;
+      c.N = 2 * t.k;
+      const bool further = l + 1 < H->nlev - 1;
+      c.geo.build(cd, further ? p.block[l + 1] : nullptr, st);
+      std::memcpy(dims, cd, sizeof(cd));
+      N = c.N;
+    }
+    for (int l = 0; l < H->nlev - 1; ++l) setup_step(H.get(), l, st);
+    CRK_HIP(hipStreamSynchronize(st));
+  } catch (...) {
+    Hierarchy* h = H.release();
+    mg_destroy(h);
+    throw;
+  }
+  return H.release();
+}
+
+void mg_destroy(Hierarchy* H) {
+  if (!H) return;
+  if (H->stream) {
+    (void)hipStreamSynchronize(H->stream);
+    (void)hipStreamDestroy(H->stream);
+  }
+  Lattice* L = H->lat;
+  delete H;
+  lattice_release(L);
+}
+
+// ------------------------------------------------------------------ inspection helpers (used by the C ABI)
+void mg_export_coarse(Hierarchy* H, int level, const void* src, int src_double, double2* dst_dev, int m,
+                      hipStream_t st) {
+  const int64_t V = H->V(level);
+  const int N = H->N(level);
+  hipLaunchKernelGGL(coarse_export_kernel, dim3(ceil_div(V * N * m, 256)), dim3(256), 0, st, src, src_double, dst_dev,
+                     H->geo(level).pos.as<int>(), V, N, m);
+  CRK_LAUNCH_CHECK();
+}
+
+void mg_import_coarse(Hierarchy* H, int level, const double2* src_dev, void* dst, int dst_double, int m,
+                      hipStream_t st) {
+  const int64_t V = H->V(level);
+  const int N = H->N(level);
+  hipLaunchKernelGGL(coarse_import_kernel, dim3(ceil_div(V * N * m, 256)), dim3(256), 0, st, src_dev, dst, dst_double,
+                     H->geo(level).pos.as<int>(), V, N, m);
+  CRK_LAUNCH_CHECK();
+}
+
+}  // namespace crk

@@ -1,0 +1,33 @@
+// Batched chiral SVD truncation: interface.
+#pragma once
+
+#include "common.h"
+
+namespace crk {
+
+// Where block matrix A_{j,alpha} lives: element (column i, component c, site)
+// at base[i*si + c*sc + site*ss]; block j covers sites [j*nb, (j+1)*nb) of the
+// device order; chirality alpha takes components [alpha*h, (alpha+1)*h).
+struct ChiralSrc {
+  int64_t si, sc, ss;
+  int h;        // components per chirality (6 fine, k coarse)
+  int nb;       // sites per block
+  int m;        // columns (test vectors)
+  int64_t nblocks;
+};
+
+struct SvdWork {
+  double2 *G, *V, *G2, *W, *B;
+  double *lam, *lam2;
+  int* sweeps;
+};
+
+size_t svd_work_bytes(int m, int nr, int64_t nblocks);
+SvdWork svd_work_carve(void* p, int m, int nr, int64_t nblocks);
+
+// P: [2*nblocks][k][N_r] complex128 (pair = 2j + alpha, row rho = c'*nb + l);
+// sigma: [2*nblocks][min(m, N_r)].  inv_norm (optional): per-column scale.
+void chiral_svd(const ChiralSrc& s, int src_is_double, const void* base, const double* inv_norm, int k,
+                const SvdWork& w, double2* P, double* sigma, hipStream_t st);
+
+}  // namespace crk

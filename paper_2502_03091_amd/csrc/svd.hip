@@ -1,0 +1,413 @@
+// Batched chiral SVD truncation (paper, Sec. 3, Eqs. (5)-(6)).
+//
+// For every block Lambda_j and chirality alpha the N_r x m matrix
+// A = Psi^(alpha)(Lambda_j) (normalised test vectors restricted to the block,
+// components of one chirality) is factorised and its k dominant left singular
+// vectors become the block of the prolongator P.
+//
+// Algorithm (one workgroup per (j, alpha), all in FP64):
+//   1. G  = A^dag A                          (streamed from the test vectors)
+//   2. G  = V diag(lambda) V^dag             (cyclic Jacobi, round-robin pairs)
+//   3. B  = A V,  G2 = B^dag B               (B stored; G2 is nearly diagonal)
+//   4. G2 = W diag(lambda2) W^dag            (Jacobi again, few sweeps)
+//   5. U_k = B W_k diag(phase_i / sigma_i),  sigma_i = sqrt(lambda2_i)
+// Step 1-2 alone lose accuracy for small sigma (the Gram matrix squares the
+// condition number).  B's columns have norms sigma_i, so G2 carries errors of
+// order eps*sigma_i*sigma_j and the second Jacobi resolves each pair to the
+// accuracy of a one-sided Jacobi sweep; U_k = B W_k keeps orthogonality to
+// working precision.  Phase: column i is multiplied by conj(s_i)/|s_i| with
+// s_i the sum of the entries of the right singular vector (V W)_i.
+//
+// Row order inside a block on the device: rho = c'*|Lambda| + l (component c'
+// of the chirality, local site l), which is contiguous in the field layouts.
+#include "kernels.h"
+#include "svd.h"
+
+namespace crk {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <class T2>
+__device__ __forceinline__ double2 ld2(const T2* p, int64_t i) {
+  T2 v = p[i];
+  return make_double2(double(v.x), double(v.y));
+}
+
+// Load rows [r0, r0+nrows) of the scaled block matrix into lds[row][col] (ld = m).
+template <class T2>
+__device__ void load_block_rows(const ChiralSrc& src, const T2* base, const double* inv_norm, int j, int alpha,
+                                int r0, int nrows, int m, double2* lds, int ldm) {
+  const int total = nrows * m;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int rr, i;
+    if (src.si == 1) { i = e % m; rr = e / m; }       // columns contiguous in memory
+    else { rr = e % nrows; i = e / nrows; }           // rows contiguous in memory
+    const int rho = r0 + rr;
+    const int c = rho / src.nb, l = rho % src.nb;
+    const int64_t site = int64_t(j) * src.nb + l;
+    const int64_t idx = int64_t(i) * src.si + int64_t(alpha * src.h + c) * src.sc + site * src.ss;
+    double2 v = ld2(base, idx);
+    const double s = inv_norm ? inv_norm[i] : 1.0;
+    lds[rr * ldm + i] = make_double2(v.x * s, v.y * s);
+  }
+}
+
+// acc[x][y] += sum_rows conj(L[row][ti*TI + x]) * L[row][tj*TI + y]
+template <int TI>
+__device__ __forceinline__ void gram_accumulate(const double2* lds, int ldm, int nrows, int ti, int tj, int m,
+                                                double2 (&acc)[TI][TI]) {
+  for (int r = 0; r < nrows; ++r) {
+    double2 a[TI], b[TI];
+#pragma unroll
+    for (int x = 0; x < TI; ++x) {
+      const int ia = ti * TI + x, ib = tj * TI + x;
+      a[x] = ia < m ? lds[r * ldm + ia] : make_double2(0, 0);
+      b[x] = ib < m ? lds[r * ldm + ib] : make_double2(0, 0);
+    }
+#pragma unroll
+    for (int x = 0; x < TI; ++x)
+#pragma unroll
+      for (int y = 0; y < TI; ++y) cfmac(acc[x][y], a[x], b[y]);
+  }
+}
+
+template <int TI>
+__device__ __forceinline__ void gram_store(double2* G, int m, int ti, int tj, const double2 (&acc)[TI][TI]) {
+#pragma unroll
+  for (int x = 0; x < TI; ++x)
+#pragma unroll
+    for (int y = 0; y < TI; ++y) {
+      const int i = ti * TI + x, ii = tj * TI + y;
+      if (i < m && ii < m) G[i * m + ii] = acc[x][y];
+    }
+}
+
+constexpr int kChunk = 32;
+
+template <class T2, int TI>
+__global__ __launch_bounds__(kThreads) void gram_kernel(ChiralSrc src, const T2* __restrict__ base,
+                                                        const double* __restrict__ inv_norm,
+                                                        double2* __restrict__ G) {
+  extern __shared__ double2 lds[];
+  const int pair = blockIdx.x, j = pair >> 1, alpha = pair & 1;
+  const int m = src.m, nr = src.h * src.nb;
+  const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
+  double2 acc[TI][TI];
+#pragma unroll
+  for (int x = 0; x < TI; ++x)
+#pragma unroll
+    for (int y = 0; y < TI; ++y) acc[x][y] = make_double2(0, 0);
+  for (int r0 = 0; r0 < nr; r0 += kChunk) {
+    const int nrows = min(kChunk, nr - r0);
+    __syncthreads();
+    load_block_rows(src, base, inv_norm, j, alpha, r0, nrows, m, lds, m);
+    __syncthreads();
+    gram_accumulate<TI>(lds, m, nrows, ti, tj, m, acc);
+  }
+  gram_store<TI>(G + int64_t(pair) * m * m, m, ti, tj, acc);
+}
+
+// ---------------------------------------------------------------- Jacobi
+// Hermitian eigendecomposition of a batch of m x m matrices (m <= 64), one
+// workgroup each, matrix and eigenvectors in LDS.  Round-robin ordering: in
+// each of mm-1 rounds the mm/2 disjoint pairs are rotated together.
+struct Rot { double c, s; double2 e; };  // J = [[c, s], [-s e, c e]],  e = conj(g)/|g|
+
+__device__ __forceinline__ void pair_of(int round, int k, int mm, int& p, int& q) {
+  const int n = mm - 1;
+  if (k == 0) { p = n; q = round; }
+  else { p = (round + k) % n; q = (round - k + n) % n; }
+  if (p > q) { int t = p; p = q; q = t; }
+}
+
+__global__ __launch_bounds__(kThreads) void jacobi_kernel(const double2* __restrict__ Gin, double* __restrict__ lam,
+                                                          double2* __restrict__ Vout, int m, int max_sweeps,
+                                                          double tol, int* __restrict__ sweeps_out) {
+  extern __shared__ double2 sh[];
+  const int mm = m + (m & 1);
+  const int ld = mm + 1;  // padding against bank conflicts
+  double2* G = sh;
+  double2* V = sh + mm * ld;
+  Rot* rot = reinterpret_cast<Rot*>(V + mm * ld);
+  int* prs = reinterpret_cast<int*>(rot + mm / 2);
+  __shared__ int n_rot;
+  const int64_t b = blockIdx.x;
+  const double2* Gb = Gin + b * m * m;
+  for (int e = threadIdx.x; e < mm * mm; e += blockDim.x) {
+    const int r = e / mm, c = e % mm;
+    G[r * ld + c] = (r < m && c < m) ? Gb[r * m + c] : make_double2(0, 0);
+    V[r * ld + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) n_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < mm - 1; ++round) {
+      if (threadIdx.x < mm / 2) {
+        int p, q;
+        pair_of(round, threadIdx.x, mm, p, q);
+        prs[2 * threadIdx.x] = p;
+        prs[2 * threadIdx.x + 1] = q;
+        const double a = G[p * ld + p].x, d = G[q * ld + q].x;
+        const double2 g = G[p * ld + q];
+        const double ag = hypot(g.x, g.y);
+        Rot R{1.0, 0.0, make_double2(1.0, 0.0)};
+        if (ag > tol * sqrt(fabs(a * d)) && ag > 0.0) {
+          const double zeta = (d - a) / (2.0 * ag);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t);
+          R.c = c;
+          R.s = t * c;
+          R.e = make_double2(g.x / ag, -g.y / ag);
+          atomicAdd(&n_rot, 1);
+        }
+        rot[threadIdx.x] = R;
+      }
+      __syncthreads();
+      // G <- J^dag G J on 2x2 blocks (pair a rows, pair b columns)
+      const int np = mm / 2;
+      for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+        const int ia = e / np, ib = e % np;
+        const Rot Ra = rot[ia], Rb = rot[ib];
+        const int pa = prs[2 * ia], qa = prs[2 * ia + 1], pb = prs[2 * ib], qb = prs[2 * ib + 1];
+        const double2 m00 = G[pa * ld + pb], m01 = G[pa * ld + qb], m10 = G[qa * ld + pb], m11 = G[qa * ld + qb];
+        // right multiply by Jb: col p' = c*col_p - s e col_q ; col q' = s col_p + c e col_q
+        const double2 eb = Rb.e;
+        const double2 se_b = make_double2(Rb.s * eb.x, Rb.s * eb.y), ce_b = make_double2(Rb.c * eb.x, Rb.c * eb.y);
+        double2 t00 = cscale(m00, Rb.c) - cmul(m01, se_b);
+        double2 t01 = cscale(m00, Rb.s) + cmul(m01, ce_b);
+        double2 t10 = cscale(m10, Rb.c) - cmul(m11, se_b);
+        double2 t11 = cscale(m10, Rb.s) + cmul(m11, ce_b);
+        // left multiply by Ja^dag: row p' = c row_p - s conj(e) row_q ; row q' = s row_p + c conj(e) row_q
+        const double2 ea = cconj(Ra.e);
+        const double2 se_a = make_double2(Ra.s * ea.x, Ra.s * ea.y), ce_a = make_double2(Ra.c * ea.x, Ra.c * ea.y);
+        G[pa * ld + pb] = cscale(t00, Ra.c) - cmul(se_a, t10);
+        G[pa * ld + qb] = cscale(t01, Ra.c) - cmul(se_a, t11);
+        G[qa * ld + pb] = cscale(t00, Ra.s) + cmul(ce_a, t10);
+        G[qa * ld + qb] = cscale(t01, Ra.s) + cmul(ce_a, t11);
+      }
+      // V <- V J
+      for (int e = threadIdx.x; e < mm * np; e += blockDim.x) {
+        const int x = e / np, ib = e % np;
+        const Rot Rb = rot[ib];
+        const int pb = prs[2 * ib], qb = prs[2 * ib + 1];
+        const double2 vp = V[x * ld + pb], vq = V[x * ld + qb];
+        const double2 se = make_double2(Rb.s * Rb.e.x, Rb.s * Rb.e.y), ce = make_double2(Rb.c * Rb.e.x, Rb.c * Rb.e.y);
+        V[x * ld + pb] = cscale(vp, Rb.c) - cmul(vq, se);
+        V[x * ld + qb] = cscale(vp, Rb.s) + cmul(vq, ce);
+      }
+      __syncthreads();
+    }
+    const bool done = n_rot == 0;
+    __syncthreads();
+    if (done) break;
+  }
+  // Sort eigenvalues descending (ties by index) and write permuted columns.
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double li = G[i * ld + i].x;
+    int rank = 0;
+    for (int jj = 0; jj < m; ++jj) {
+      const double lj = G[jj * ld + jj].x;
+      rank += (lj > li) || (lj == li && jj < i);
+    }
+    lam[b * m + rank] = li;
+    for (int x = 0; x < m; ++x) Vout[b * m * m + int64_t(x) * m + rank] = V[x * ld + i];
+  }
+  if (threadIdx.x == 0 && sweeps_out) sweeps_out[b] = sweep;
+}
+
+// ---------------------------------------------------------------- B = A V, G2 = B^dag B
+constexpr int kRotChunk = 16;
+
+template <class T2, int TI>
+__global__ __launch_bounds__(kThreads) void rotate_kernel(ChiralSrc src, const T2* __restrict__ base,
+                                                          const double* __restrict__ inv_norm,
+                                                          const double2* __restrict__ Vin, double2* __restrict__ B,
+                                                          double2* __restrict__ G2) {
+  extern __shared__ double2 lds[];
+  const int m = src.m, nr = src.h * src.nb;
+  const int pair = blockIdx.x, j = pair >> 1, alpha = pair & 1;
+  double2* Vs = lds;                   // [m][m]
+  double2* As = Vs + m * m;            // [kRotChunk][m]
+  double2* Bs = As + kRotChunk * m;    // [kRotChunk][m]
+  const double2* Vb = Vin + int64_t(pair) * m * m;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) Vs[e] = Vb[e];
+  const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
+  double2 acc[TI][TI];
+#pragma unroll
+  for (int x = 0; x < TI; ++x)
+#pragma unroll
+    for (int y = 0; y < TI; ++y) acc[x][y] = make_double2(0, 0);
+  double2* Bp = B + int64_t(pair) * nr * m;
+  for (int r0 = 0; r0 < nr; r0 += kRotChunk) {
+    const int nrows = min(kRotChunk, nr - r0);
+    __syncthreads();
+    load_block_rows(src, base, inv_norm, j, alpha, r0, nrows, m, As, m);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nrows * m; e += blockDim.x) {
+      const int rr = e / m, col = e % m;
+      double2 t = make_double2(0, 0);
+      for (int i = 0; i < m; ++i) cfma(t, As[rr * m + i], Vs[i * m + col]);
+      Bs[rr * m + col] = t;
+      Bp[int64_t(r0 + rr) * m + col] = t;
+    }
+    __syncthreads();
+    gram_accumulate<TI>(Bs, m, nrows, ti, tj, m, acc);
+  }
+  gram_store<TI>(G2 + int64_t(pair) * m * m, m, ti, tj, acc);
+}
+
+// ---------------------------------------------------------------- U_k = B T
+constexpr int kFinChunk = 32;
+
+__global__ __launch_bounds__(kThreads) void finalize_kernel(int m, int nr, int k, const double2* __restrict__ Vin,
+                                                            const double2* __restrict__ Win,
+                                                            const double* __restrict__ lam2,
+                                                            const double2* __restrict__ B, double2* __restrict__ P,
+                                                            double* __restrict__ sigma, int nsig) {
+  extern __shared__ double2 lds[];
+  const int pair = blockIdx.x;
+  double2* T = lds;             // [m][k]
+  double2* Bs = T + m * k;      // [kFinChunk][m]
+  __shared__ double2 phase[64];
+  __shared__ double sig[64];
+  __shared__ double2 colsum[64];
+  const double2* Vb = Vin + int64_t(pair) * m * m;
+  const double2* Wb = Win + int64_t(pair) * m * m;
+  // s_i = sum_x (V W)[x][i] = sum_y (sum_x V[x][y]) W[y][i]
+  if (threadIdx.x < m) {
+    double2 cs = make_double2(0, 0);
+    for (int x = 0; x < m; ++x) cs = cs + Vb[int64_t(x) * m + threadIdx.x];
+    colsum[threadIdx.x] = cs;
+  }
+  __syncthreads();
+  if (threadIdx.x < k) {
+    const int i = threadIdx.x;
+    double2 s = make_double2(0, 0);
+    for (int y = 0; y < m; ++y) cfma(s, colsum[y], Wb[int64_t(y) * m + i]);
+    const double a = hypot(s.x, s.y);
+    phase[i] = a > 0 ? make_double2(s.x / a, -s.y / a) : make_double2(1, 0);
+    const double l = lam2[int64_t(pair) * m + i];
+    sig[i] = l > 0 ? sqrt(l) : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * k; e += blockDim.x) {
+    const int y = e / k, i = e % k;
+    const double inv = sig[i] > 0 ? 1.0 / sig[i] : 0.0;
+    const double2 w = cmul(Wb[int64_t(y) * m + i], phase[i]);
+    T[y * k + i] = make_double2(w.x * inv, w.y * inv);
+  }
+  for (int i = threadIdx.x; i < nsig; i += blockDim.x) {
+    const double l = lam2[int64_t(pair) * m + i];
+    sigma[int64_t(pair) * nsig + i] = l > 0 ? sqrt(l) : 0.0;
+  }
+  const double2* Bp = B + int64_t(pair) * nr * m;
+  double2* Pp = P + int64_t(pair) * k * nr;
+  for (int r0 = 0; r0 < nr; r0 += kFinChunk) {
+    const int nrows = min(kFinChunk, nr - r0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nrows * m; e += blockDim.x) Bs[e] = Bp[int64_t(r0) * m + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nrows * k; e += blockDim.x) {
+      const int i = e / nrows, rr = e % nrows;
+      double2 t = make_double2(0, 0);
+      for (int y = 0; y < m; ++y) cfma(t, Bs[rr * m + y], T[y * k + i]);
+      Pp[int64_t(i) * nr + r0 + rr] = t;
+    }
+  }
+}
+
+// Allow dynamic LDS beyond the 64 KiB default (gfx950 has 160 KiB per CU).
+// Dynamic LDS above 64 KiB must be enabled per kernel (gfx950: 160 KiB per workgroup,
+// static LDS included).
+template <class K> void allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return;
+  CRK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(bytes)));
+}
+
+template <class T2>
+void launch_gram(const ChiralSrc& s, const void* base, const double* inv_norm, double2* G, hipStream_t st) {
+  const size_t lds = sizeof(double2) * kChunk * s.m;
+  const dim3 grid = dim3(unsigned(2 * s.nblocks));
+  const T2* b = static_cast<const T2*>(base);
+  if (s.m <= 16) hipLaunchKernelGGL((gram_kernel<T2, 1>), grid, dim3(kThreads), lds, st, s, b, inv_norm, G);
+  else if (s.m <= 32) hipLaunchKernelGGL((gram_kernel<T2, 2>), grid, dim3(kThreads), lds, st, s, b, inv_norm, G);
+  else if (s.m <= 48) hipLaunchKernelGGL((gram_kernel<T2, 3>), grid, dim3(kThreads), lds, st, s, b, inv_norm, G);
+  else hipLaunchKernelGGL((gram_kernel<T2, 4>), grid, dim3(kThreads), lds, st, s, b, inv_norm, G);
+  CRK_LAUNCH_CHECK();
+}
+
+template <class T2>
+void launch_rotate(const ChiralSrc& s, const void* base, const double* inv_norm, const double2* V, double2* B,
+                   double2* G2, hipStream_t st) {
+  const size_t lds = sizeof(double2) * (size_t(s.m) * s.m + 2 * kRotChunk * s.m);
+  const dim3 grid = dim3(unsigned(2 * s.nblocks));
+  const T2* b = static_cast<const T2*>(base);
+  allow_lds(rotate_kernel<T2, 1>, lds); allow_lds(rotate_kernel<T2, 2>, lds);
+  allow_lds(rotate_kernel<T2, 3>, lds); allow_lds(rotate_kernel<T2, 4>, lds);
+  if (s.m <= 16) hipLaunchKernelGGL((rotate_kernel<T2, 1>), grid, dim3(kThreads), lds, st, s, b, inv_norm, V, B, G2);
+  else if (s.m <= 32) hipLaunchKernelGGL((rotate_kernel<T2, 2>), grid, dim3(kThreads), lds, st, s, b, inv_norm, V, B, G2);
+  else if (s.m <= 48) hipLaunchKernelGGL((rotate_kernel<T2, 3>), grid, dim3(kThreads), lds, st, s, b, inv_norm, V, B, G2);
+  else hipLaunchKernelGGL((rotate_kernel<T2, 4>), grid, dim3(kThreads), lds, st, s, b, inv_norm, V, B, G2);
+  CRK_LAUNCH_CHECK();
+}
+
+size_t jacobi_lds(int m) {
+  const int mm = m + (m & 1), ld = mm + 1;
+  return sizeof(double2) * 2 * mm * ld + sizeof(Rot) * (mm / 2) + sizeof(int) * mm;
+}
+
+}  // namespace
+
+void chiral_svd(const ChiralSrc& s, int src_is_double, const void* base, const double* inv_norm, int k,
+                const SvdWork& w, double2* P, double* sigma, hipStream_t st) {
+  CRK_REQUIRE(s.m >= 1 && s.m <= 64, "m' must be in [1, 64]");
+  const int nr = s.h * s.nb;
+  CRK_REQUIRE(k >= 1 && k <= s.m && k <= nr, "k must satisfy 1 <= k <= min(m', N_r)");
+  const int m = s.m;
+  const unsigned npair = unsigned(2 * s.nblocks);
+  if (src_is_double) launch_gram<double2>(s, base, inv_norm, w.G, st);
+  else launch_gram<float2>(s, base, inv_norm, w.G, st);
+  const double tol = 1e-15;
+  allow_lds(jacobi_kernel, jacobi_lds(m));
+  hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kThreads), jacobi_lds(m), st, w.G, w.lam, w.V, m, 40, tol,
+                     w.sweeps);
+  CRK_LAUNCH_CHECK();
+  if (src_is_double) launch_rotate<double2>(s, base, inv_norm, w.V, w.B, w.G2, st);
+  else launch_rotate<float2>(s, base, inv_norm, w.V, w.B, w.G2, st);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kThreads), jacobi_lds(m), st, w.G2, w.lam2, w.W, m, 40, tol,
+                     w.sweeps ? w.sweeps + npair : nullptr);
+  CRK_LAUNCH_CHECK();
+  const size_t lds = sizeof(double2) * (size_t(m) * k + size_t(kFinChunk) * m);
+  allow_lds(finalize_kernel, lds);
+  const int nsig = m < nr ? m : nr;
+  hipLaunchKernelGGL(finalize_kernel, dim3(npair), dim3(kThreads), lds, st, m, nr, k, w.V, w.W, w.lam2, w.B, P, sigma,
+                     nsig);
+  CRK_LAUNCH_CHECK();
+}
+
+size_t svd_work_bytes(int m, int nr, int64_t nblocks) {
+  const size_t np = size_t(2 * nblocks);
+  return np * (sizeof(double2) * (4 * size_t(m) * m + size_t(nr) * m) + sizeof(double) * 2 * m + 2 * sizeof(int)) + 256 * 8;
+}
+
+SvdWork svd_work_carve(void* p, int m, int nr, int64_t nblocks) {
+  const size_t np = size_t(2 * nblocks);
+  char* c = static_cast<char*>(p);
+  auto take = [&](size_t n) { char* r = c; c += (n + 255) & ~size_t(255); return r; };
+  SvdWork w;
+  w.G = reinterpret_cast<double2*>(take(sizeof(double2) * np * m * m));
+  w.V = reinterpret_cast<double2*>(take(sizeof(double2) * np * m * m));
+  w.G2 = reinterpret_cast<double2*>(take(sizeof(double2) * np * m * m));
+  w.W = reinterpret_cast<double2*>(take(sizeof(double2) * np * m * m));
+  w.B = reinterpret_cast<double2*>(take(sizeof(double2) * np * nr * m));
+  w.lam = reinterpret_cast<double*>(take(sizeof(double) * np * m));
+  w.lam2 = reinterpret_cast<double*>(take(sizeof(double) * np * m));
+  w.sweeps = reinterpret_cast<int*>(take(sizeof(int) * 2 * np));
+  return w;
+}
+
+}  // namespace crk

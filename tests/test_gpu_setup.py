@@ -1,0 +1,181 @@
+"""GPU parity of the chiral rank-k setup (MR smoother, chiral SVD, P, Galerkin) and
+of the transfer and coarse operators, against the FP64 oracle.
+
+Bars (plain FP64 form, same seeded inputs on both sides):
+  * block / aggregate maps bit-exact;
+  * smoothed, normalised test vectors: 1e-12 relative (max-norm per vector);
+  * singular values: |d sigma_i| <= 1e-12 * sigma_1 (Weyl);
+  * per (block, chirality) projector U_k U_k^dag: relative Frobenius error
+    <= max(1e-12, 10 eps sqrt(N_r) sigma_1 / (sigma_k - sigma_{k+1})) (Wedin);
+  * P columns element-wise (phase convention fixes them) with the per-column
+    bound 10 eps sqrt(N_r) sigma_1 / (min gap to the neighbouring sigma);
+  * coarse spectrum (basis independent) and coarse links element-wise, and
+    restriction / prolongation / coarse apply, 1e-11 relative when every
+    block's singular gaps make the columns well determined;
+  * the Galerkin identity D_c v = P^dag D P v at any size (GPU only).
+Reduced-precision setup (FP32 smoother): stated bounds below.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import linear_sum_assignment
+
+import synth
+from oracle import chiral, galerkin, lattice as olat, mg as omg, mr
+from oracle.stencil import as_columns, as_fields
+from oracle.wilson import WilsonOp
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(float).eps
+
+
+@pytest.fixture(scope="module")
+def crk():
+    import paper_2502_03091_amd as m
+    m.lib()
+    return m
+
+
+def _spec_dist(a, b):
+    cost = np.abs(np.asarray(a)[:, None] - np.asarray(b)[None, :])
+    r, c = linear_sum_assignment(cost)
+    return cost[r, c].max()
+
+
+def _build(crk, dims, block, m, k, n_smooth, eps=0.3, m0=-0.4, xi=1.0, config=1, form=0, n_ape=0):
+    U = synth.gauge_field(dims, eps, n_ape, config=config)
+    V = olat.volume(dims)
+    v0 = synth.gaussian_vectors(m, V, 12, config=config, level=0)
+    lat = crk.Lattice(dims, m0, xi)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[m], k=[k], block=[block], n_smooth=[n_smooth], setup_form=form,
+                      init_vectors=[v0])
+    op = WilsonOp(U, dims, m0, xi)
+    ref = omg.mg_setup(op, [m], [k], [block], [n_smooth], [as_columns(v0)], keep_vectors=True)
+    return lat, H, op, ref
+
+
+CASES = [
+    # dims, block, m', k, sweeps: C1 (4^4, 2^4 blocks, m'=16 -> k=8, 20 MR)
+    ([4, 4, 4, 4], [2, 2, 2, 2], 16, 8, 20),
+    ([4, 2, 4, 2], [2, 2, 2, 1], 20, 8, 6),     # coarse extent 1 in y, 2 elsewhere; m' off-tile
+    ([6, 4, 2, 4], [2, 2, 2, 2], 24, 16, 5),    # coarse extent 3 in x
+]
+
+
+@pytest.mark.parametrize("dims,block,m,k,ns", CASES)
+def test_setup_fp64_matches_oracle(crk, dims, block, m, k, ns):
+    print(f"setup parity dims={dims} block={block} m={m} k={k} sweeps={ns}", flush=True)
+    lat, H, op, ref = _build(crk, dims, block, m, k, ns)
+    L0, L1 = ref[0], ref[1]
+    # maps
+    j, l = olat.block_maps(dims, block)
+    bm = H.block_map(0)
+    assert np.array_equal(bm[:, 0], j) and np.array_equal(bm[:, 1], l)
+    # smoothed, normalised vectors
+    vg = H.vectors(0)
+    vo = as_fields(L0.vectors)
+    err = np.abs(vg - vo).max(axis=(1, 2)) / np.abs(vo).max(axis=(1, 2))
+    assert err.max() <= 1e-12, err.max()
+    # singular values
+    sg, so = H.sigma(0), L0.sigma
+    assert np.abs(sg - so).max() <= 1e-12 * so[..., 0].max()
+    # projectors and columns
+    Pg, Po = H.prolongator(0), L0.Pb
+    nr = Po.shape[2]
+    col_ok = True
+    for jj in range(Po.shape[0]):
+        for a in range(2):
+            s = so[jj, a]
+            gap = s[k - 1] - (s[k] if k < s.size else 0.0)
+            bound = max(1e-12, 10 * EPS * np.sqrt(nr) * s[0] / gap)
+            Pi_g = Pg[jj, a] @ Pg[jj, a].conj().T
+            Pi_o = Po[jj, a] @ Po[jj, a].conj().T
+            e = np.linalg.norm(Pi_g - Pi_o) / np.linalg.norm(Pi_o)
+            assert e <= bound, (jj, a, e, bound)
+            assert np.abs(Pg[jj, a].conj().T @ Pg[jj, a] - np.eye(k)).max() <= 1e-13
+            for i in range(k):
+                neigh = [abs(s[i] - s[i - 1]) if i > 0 else np.inf, abs(s[i] - s[i + 1]) if i + 1 < s.size else s[i]]
+                cb = max(1e-12, 10 * EPS * np.sqrt(nr) * s[0] / min(neigh))
+                ce = np.abs(Pg[jj, a][:, i] - Po[jj, a][:, i]).max()
+                assert ce <= cb, (jj, a, i, ce, cb)
+                col_ok &= cb <= 1e-11
+    # coarse operator: basis-independent spectrum, and links when columns are well determined
+    X, Yp, Ym = H.coarse_links(0)
+    from oracle.stencil import StencilOp
+    Dg = StencilOp(L1.op.dims, X, Yp, Ym).dense()
+    Do = L1.op.dense()
+    scale = np.abs(Do).max()
+    assert _spec_dist(np.linalg.eigvals(Dg), np.linalg.eigvals(Do)) <= 1e-10 * scale
+    if col_ok:
+        assert np.abs(Dg - Do).max() <= 1e-11 * scale
+        # transfers and coarse apply against the oracle's
+        V = olat.volume(dims)
+        v = synth.gaussian_rhs(3, V, config=7)
+        rc_g = H.restrict(0, v)
+        rc_o = as_fields(chiral.restrict(Po, as_columns(v), dims, block))
+        assert np.abs(rc_g - rc_o).max() <= 1e-11 * np.abs(rc_o).max()
+        pv_g = H.prolong(0, rc_o)
+        pv_o = as_fields(chiral.prolong(Po, as_columns(rc_o), dims, block))
+        assert np.abs(pv_g - pv_o).max() <= 1e-11 * np.abs(pv_o).max()
+        ca_g = H.coarse_apply(1, rc_o)
+        ca_o = as_fields(L1.op.apply(as_columns(rc_o)))
+        assert np.abs(ca_g - ca_o).max() <= 1e-11 * np.abs(ca_o).max()
+
+
+def test_galerkin_identity_and_sigma3_full_size(crk):
+    """16^3x32, xi = 3.5, 4^4 blocks, m' = 48 -> k = 24 (the anisotropic workload), FP32 smoother."""
+    dims, block = [16, 16, 16, 32], [4, 4, 4, 4]
+    print("galerkin identity 16^3x32", flush=True)
+    U = synth.gauge_field(dims, 0.2, 3, config=2)
+    lat = crk.Lattice(dims, -0.05, 3.5)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[48], k=[24], block=[block], n_smooth=[20], setup_form=1)
+    Vc, N = H.volume(1), 48
+    vc = synth.gaussian_vectors(4, Vc, N, config=2, level=5)
+    # D_c v  vs  P^dag D P v, all on the GPU (FP64 operators)
+    lhs = H.coarse_apply(1, vc)
+    Pv = H.prolong(0, vc)
+    rhs = H.restrict(0, lat.dirac_apply(Pv, 0))
+    err = np.abs(lhs - rhs).max() / np.abs(rhs).max()
+    assert err <= 1e-12, err
+    # sigma3-hermiticity of the stored links
+    X, Yp, Ym = H.coarse_links(0)
+    s3 = np.diag([1.0] * 24 + [-1.0] * 24)
+    nbr = olat.neighbors(H.dims[1])
+    scale = np.abs(X).max()
+    for jj in range(0, Vc, 37):
+        assert np.abs(X[jj].conj().T - s3 @ X[jj] @ s3).max() <= 1e-12 * scale
+        for mu in range(4):
+            assert np.abs(Ym[mu, nbr[jj, 2 * mu]] - s3 @ Yp[mu, jj].conj().T @ s3).max() <= 1e-12 * scale
+    # P^dag P = 1 per block and singular values descending
+    P = H.prolongator(0)
+    G = np.einsum("jari,jarl->jail", P.conj(), P)
+    assert np.abs(G - np.eye(24)).max() <= 1e-12
+    s = H.sigma(0)
+    assert (np.diff(s, axis=-1) <= 1e-15).all()
+    t = H.timing(0)
+    print("setup timing", t, flush=True)
+
+
+def test_setup_fp32_smoother_bounds(crk):
+    """FP32 smoother, FP64 SVD/Galerkin: vectors 1e-4, singular values 1e-4*sigma_1."""
+    dims, block = [4, 4, 4, 4], [2, 2, 2, 2]
+    lat, H, op, ref = _build(crk, dims, block, 16, 8, 20, form=1)
+    vg = H.vectors(0)
+    vo = as_fields(ref[0].vectors)
+    err = (np.abs(vg - vo).max(axis=(1, 2)) / np.abs(vo).max(axis=(1, 2))).max()
+    print("fp32 smoother vector error", err)
+    assert err <= 1e-4
+    so = ref[0].sigma
+    assert np.abs(H.sigma(0) - so).max() <= 1e-4 * so[..., 0].max()
+
+
+def test_setup_rejects_bad_parameters(crk):
+    lat = crk.Lattice([4, 4, 4, 4], -0.4, 1.0)
+    lat.load_gauge(synth.gauge_field([4, 4, 4, 4], 0.3, 0, config=1))
+    with pytest.raises(crk.CrkError):
+        crk.Hierarchy(lat, m_prime=[16], k=[12], block=[[2, 2, 2, 2]], n_smooth=[2])  # k not multiple of 8
+    with pytest.raises(crk.CrkError):
+        crk.Hierarchy(lat, m_prime=[16], k=[8], block=[[3, 2, 2, 2]], n_smooth=[2])   # block does not divide
+    with pytest.raises(crk.CrkError):
+        crk.Hierarchy(lat, m_prime=[8], k=[16], block=[[2, 2, 2, 2]], n_smooth=[2])   # k > m'
