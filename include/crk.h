@@ -88,10 +88,13 @@ int crk_load_gauge(crk_lattice_t lat, const double* U, int64_t n_doubles);
  * input to the form, apply, and widen the result. */
 int crk_dirac_apply(crk_lattice_t lat, int32_t form, const double* in, double* out, int32_t nrhs);
 
-/* Device-resident variant on the lattice's native device layout of the form:
- * FP64 double2 / FP32 float2 [nrhs][12][V] (site-fastest, lexicographic);
- * FP16S: half2 [nrhs][12][V] followed by float scales [nrhs][V] in the same
- * buffer (byte offset nrhs*12*V*4).  in/out are device pointers. */
+/* Device-resident variant on the lattice's native device layout of the form
+ * (site-vectorised): with Vp = V rounded up to a multiple of 64, entry
+ * (rhs r, component c, lexicographic site s) is complex element
+ * (r*Vp + 64*floor(s/64))*12 + 64*c + s%64 of the buffer (FP64 double2,
+ * FP32 float2, FP16S half2 of x/scale followed by the float scales [nrhs][Vp]
+ * at byte offset nrhs*12*Vp*4).  in/out are device pointers; padding sites
+ * are neither read nor written. */
 int crk_dirac_apply_dev(crk_lattice_t lat, int32_t form, const void* in, void* out, int32_t nrhs,
                         void* hip_stream);
 

@@ -5,8 +5,8 @@
 //
 //   (D_c v)(j) = X(j) v(j) + sum_mu [ Y_{+mu}(j) v(j+mu) + Y_{-mu}(j) v(j-mu) ]
 //
-// One wavefront computes the full 2k x 16 output tile of one coarse site and
-// 16 right-hand sides, looping over the nine links and over K in steps of 4
+// One wavefront computes a 16 x 16 output tile (16 rows of one coarse site, 16
+// right-hand sides), looping over the nine links and over K in steps of 4
 // with v_mfma_{f32,f64}_16x16x4: a complex product is four real MFMAs
 // (re += Ar Br - Ai Bi, im += Ar Bi + Ai Br).  Links are column-major 2k x 2k
 // blocks, so the 16 rows an A operand needs are one contiguous 16-entry run;
@@ -38,52 +38,50 @@ template <> struct Mfma<double> {
   }
 };
 
-template <class T, int MT>
+// One wavefront per (coarse site, 16-RHS tile, 16-row tile): 2k/16 wavefronts per
+// site and tile share the B operands through the cache, which gives the small
+// coarse lattices enough wavefronts to fill the chip.
+template <class T>
 __global__ __launch_bounds__(64) void coarse_mfma_kernel(const typename cplx_t<T>::type* __restrict__ links,
                                                          const typename cplx_t<T>::type* __restrict__ in,
                                                          typename cplx_t<T>::type* __restrict__ out,
                                                          const int* __restrict__ nbr, int64_t Vc, int nrhs,
-                                                         int ntiles, T sign) {
+                                                         int ntiles, int N, T sign) {
   using C = typename cplx_t<T>::type;
   using A = typename Mfma<T>::acc;
-  constexpr int N = 16 * MT;
-  const int64_t j = blockIdx.x / ntiles;
-  const int tile = blockIdx.x % ntiles;
+  const int MT = N / 16;
+  const int mt = blockIdx.x % MT;
+  const int64_t rest = blockIdx.x / MT;
+  const int tile = int(rest % ntiles);
+  const int64_t j = rest / ntiles;
   const int lane = threadIdx.x;
   const int n = tile * 16 + (lane & 15);
   const int kq = lane >> 4;
   const bool live = n < nrhs;
-  A are[MT], aim[MT];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) { are[mt] = A{0, 0, 0, 0}; aim[mt] = A{0, 0, 0, 0}; }
+  A are = A{0, 0, 0, 0}, aim = A{0, 0, 0, 0};
   for (int nb = 0; nb < 9; ++nb) {
     const int64_t s = nb == 0 ? j : int64_t(nbr[int64_t(nb - 1) * Vc + j]);
-    const C* Lb = links + (j * 9 + nb) * int64_t(N) * N;
-    const C* vb = in + s * int64_t(N) * nrhs;
+    const C* Lb = links + (j * 9 + nb) * int64_t(N) * N + mt * 16 + (lane & 15);
+    const C* vb = in + s * int64_t(N) * nrhs + n;
 #pragma unroll 4
     for (int ks = 0; ks < N / 4; ++ks) {
       const int kk = ks * 4 + kq;
-      const C bv = live ? vb[int64_t(kk) * nrhs + n] : C{0, 0};
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const C av = Lb[int64_t(kk) * N + mt * 16 + (lane & 15)];
-        are[mt] = Mfma<T>::op(av.x, bv.x, are[mt]);
-        are[mt] = Mfma<T>::op(-av.y, bv.y, are[mt]);
-        aim[mt] = Mfma<T>::op(av.x, bv.y, aim[mt]);
-        aim[mt] = Mfma<T>::op(av.y, bv.x, aim[mt]);
-      }
+      const C bv = live ? vb[int64_t(kk) * nrhs] : C{0, 0};
+      const C av = Lb[int64_t(kk) * N];
+      are = Mfma<T>::op(av.x, bv.x, are);
+      are = Mfma<T>::op(-av.y, bv.y, are);
+      aim = Mfma<T>::op(av.x, bv.y, aim);
+      aim = Mfma<T>::op(av.y, bv.x, aim);
     }
   }
   if (!live) return;
-  C* ob = out + j * int64_t(N) * nrhs;
+  C* ob = out + j * int64_t(N) * nrhs + n;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      // accumulator layout: f32 16x16x4 holds rows 4*(lane/16) + i, f64 16x16x4 rows lane/16 + 4*i
-      const int row = mt * 16 + (sizeof(T) == 8 ? kq + 4 * i : kq * 4 + i);
-      ob[int64_t(row) * nrhs + n] = C{sign * are[mt][i], sign * aim[mt][i]};
-    }
+  for (int i = 0; i < 4; ++i) {
+    // accumulator layout: f32 16x16x4 holds rows 4*(lane/16) + i, f64 16x16x4 rows lane/16 + 4*i
+    const int row = mt * 16 + (sizeof(T) == 8 ? kq + 4 * i : kq * 4 + i);
+    ob[int64_t(row) * nrhs] = C{sign * are[i], sign * aim[i]};
+  }
 }
 
 // FP16 links with a per-(site, link) fp32 scale; fp32 vectors; fp32 accumulation.
@@ -194,18 +192,11 @@ template <class T>
 void launch_mfma(int N, const void* links, const void* in, void* out, const int* nbr, int64_t Vc, int nrhs, T sign,
                  hipStream_t st) {
   using C = typename cplx_t<T>::type;
+  CRK_REQUIRE(N % 16 == 0 && N >= 16 && N <= 64, "coarse operator: 2k must be 16, 32, 48 or 64");
   const int ntiles = (nrhs + 15) / 16;
-  const dim3 g = dim3(unsigned(Vc * ntiles));
-  const C* L = static_cast<const C*>(links);
-  const C* x = static_cast<const C*>(in);
-  C* y = static_cast<C*>(out);
-  switch (N / 16) {
-    case 1: hipLaunchKernelGGL((coarse_mfma_kernel<T, 1>), g, dim3(64), 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
-    case 2: hipLaunchKernelGGL((coarse_mfma_kernel<T, 2>), g, dim3(64), 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
-    case 3: hipLaunchKernelGGL((coarse_mfma_kernel<T, 3>), g, dim3(64), 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
-    case 4: hipLaunchKernelGGL((coarse_mfma_kernel<T, 4>), g, dim3(64), 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
-    default: fail(CRK_EINVAL, "coarse operator: 2k must be 16, 32, 48 or 64");
-  }
+  const dim3 g = dim3(unsigned(Vc * ntiles * (N / 16)));
+  hipLaunchKernelGGL((coarse_mfma_kernel<T>), g, dim3(64), 0, st, static_cast<const C*>(links),
+                     static_cast<const C*>(in), static_cast<C*>(out), nbr, Vc, nrhs, ntiles, N, sign);
   CRK_LAUNCH_CHECK();
 }
 

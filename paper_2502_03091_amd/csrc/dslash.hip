@@ -12,14 +12,14 @@
 // site order (lexicographic or block-major) uses the same kernel.  Optionally
 // the kernel also emits per-workgroup partial sums <Dr, r> and <Dr, Dr> for
 // the minimal-residual smoother, so no separate pass over the fields is needed.
+#include <cstdlib>
+
 #include "field.h"
 #include "kernels.h"
 
 namespace crk {
 
 namespace {
-
-template <class C> struct Half { C h[6]; };
 
 // Spin projection of psi onto the half spinor of (1 - sign*gamma_mu).
 template <int MU, int SIGN, class C>
@@ -113,12 +113,15 @@ template <int FORM, int R>
 __global__ __launch_bounds__(256) void wilson_kernel(FineView<FORM> in, FineView<FORM> out, GaugeView<FORM> U,
                                                      const int* __restrict__ nbr, int64_t V, int nrhs, int ngroups,
                                                      typename Prec<FORM>::real diag, float4 hw_f, double4 hw_d,
-                                                     double* __restrict__ partial) {
+                                                     double* __restrict__ partial, int64_t nsb, int order,
+                                                     int swz) {
   using C = typename Prec<FORM>::cx;
   using T = typename Prec<FORM>::real;
-  const uint32_t L = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int64_t sb = L / ngroups;
-  const int g = L % ngroups;
+  const uint32_t L = swz ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
+  // order 0: the RHS groups of one site block are consecutive (links reused in L2);
+  // order 1: all site blocks of one RHS group are consecutive (halos reused in L2)
+  const int64_t sb = order == 0 ? L / ngroups : L % nsb;
+  const int g = order == 0 ? int(L % ngroups) : int(L / nsb);
   const int64_t s = sb * blockDim.x + threadIdx.x;
   const int r0 = g * R;
   const bool live = s < V;
@@ -193,6 +196,114 @@ __global__ __launch_bounds__(256) void wilson_kernel(FineView<FORM> in, FineView
   }
 }
 
+// Variant that keeps the eight links of a site in registers and loops over all
+// right-hand sides inside the thread.  Links are read from memory once per
+// site instead of once per RHS group, and since every workgroup of the grid
+// walks the RHS in the same order, the workgroups resident on one XCD touch
+// the same RHS at the same time: the neighbour (halo) spinors they share are
+// then reused from that XCD's L2 instead of being fetched again.
+template <int FORM, int MU, int SIGN>
+__device__ __forceinline__ void hop_reg(const FineView<FORM>& in, int64_t r, int64_t y,
+                                        const typename GaugeView<FORM>::S (&u)[9],
+                                        typename Prec<FORM>::cx (&acc)[12], typename Prec<FORM>::real coef) {
+  using C = typename Prec<FORM>::cx;
+  C uc[9], psi[12], h[6], g[6];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    if constexpr (FORM == CRK_FORM_FP16S) uc[e] = __half22float2(u[e]);
+    else uc[e] = u[e];
+  }
+  in.load(r, y, psi);
+  project<MU, SIGN>(psi, h);
+  link_mul<SIGN>(uc, h, g);
+  accumulate<MU, SIGN>(acc, g, coef);
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void wilson_rhsloop_kernel(FineView<FORM> in, FineView<FORM> out, GaugeView<FORM> U,
+                                                             const int* __restrict__ nbr, int64_t V, int nrhs,
+                                                             typename Prec<FORM>::real diag, float4 hw,
+                                                             double* __restrict__ partial, int swz) {
+  using C = typename Prec<FORM>::cx;
+  using T = typename Prec<FORM>::real;
+  using S = typename GaugeView<FORM>::S;
+  const int64_t sb = swz ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int64_t s = sb * blockDim.x + threadIdx.x;
+  const bool live = s < V;
+  const int64_t sl = live ? s : 0;  // dead lanes compute on site 0 and store nothing
+  int y[8];
+  S u[8][9];
+#pragma unroll
+  for (int d = 0; d < 8; ++d) y[d] = nbr[int64_t(d) * V + sl];
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    const S* p = U.data + aidx(d >> 1, 0, (d & 1) ? int64_t(y[d]) : sl, U.Vp, 9);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[d][e] = p[e * kVL];
+  }
+  const T hw0 = hw.x, hw1 = hw.y, hw2 = hw.z, hw3 = hw.w;
+  __shared__ double red[3][4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int r = 0; r < nrhs; ++r) {
+    C acc[12];
+    {
+      C psi[12];
+      in.load(r, sl, psi);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = cscale(psi[c], diag);
+    }
+    hop_reg<FORM, 0, +1>(in, r, y[0], u[0], acc, hw0);
+    hop_reg<FORM, 0, -1>(in, r, y[1], u[1], acc, hw0);
+    hop_reg<FORM, 1, +1>(in, r, y[2], u[2], acc, hw1);
+    hop_reg<FORM, 1, -1>(in, r, y[3], u[3], acc, hw1);
+    hop_reg<FORM, 2, +1>(in, r, y[4], u[4], acc, hw2);
+    hop_reg<FORM, 2, -1>(in, r, y[5], u[5], acc, hw2);
+    hop_reg<FORM, 3, +1>(in, r, y[6], u[6], acc, hw3);
+    hop_reg<FORM, 3, -1>(in, r, y[7], u[7], acc, hw3);
+    if (live) out.store(r, s, acc);
+    if (partial != nullptr) {
+      double v0 = 0, v1 = 0, v2 = 0;
+      if (live) {
+        C psi[12];
+        in.load(r, s, psi);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const C q = acc[c];
+          v0 += double(q.x) * psi[c].x + double(q.y) * psi[c].y;
+          v1 += double(q.x) * psi[c].y - double(q.y) * psi[c].x;
+          v2 += double(q.x) * q.x + double(q.y) * q.y;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        v0 += __shfl_xor(v0, o);
+        v1 += __shfl_xor(v1, o);
+        v2 += __shfl_xor(v2, o);
+      }
+      __syncthreads();  // previous RHS's reduction has been read
+      if (lane == 0) { red[0][wid] = v0; red[1][wid] = v1; red[2][wid] = v2; }
+      __syncthreads();
+      if (threadIdx.x < 3) {
+        const int nw = blockDim.x >> 6;
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += red[threadIdx.x][w];
+        partial[(sb * nrhs + r) * 3 + threadIdx.x] = t;
+      }
+    }
+  }
+}
+
+template <int FORM>
+void launch_wilson_rhsloop(const WilsonArgs& a, hipStream_t st) {
+  const int64_t nsb = (a.V + 255) / 256;
+  FineView<FORM> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
+  GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), pad_sites(a.V)};
+  const float4 hw = make_float4(float(a.hw[0]), float(a.hw[1]), float(a.hw[2]), float(a.hw[3]));
+  hipLaunchKernelGGL((wilson_rhsloop_kernel<FORM>), dim3(unsigned(nsb)), dim3(256), 0, st, in, out, U, a.nbr, a.V,
+                     a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle);
+  CRK_LAUNCH_CHECK();
+}
+
 template <int FORM, int R>
 void launch_wilson(const WilsonArgs& a, hipStream_t st) {
   const int ngroups = (a.nrhs + R - 1) / R;
@@ -200,11 +311,12 @@ void launch_wilson(const WilsonArgs& a, hipStream_t st) {
   const int64_t nblk = nsb * ngroups;
   if (nblk > 0x7fffffff) fail(CRK_EINVAL, "dslash grid too large");
   FineView<FORM> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
-  GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), a.V};
+  GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), pad_sites(a.V)};
   float4 hwf = make_float4(float(a.hw[0]), float(a.hw[1]), float(a.hw[2]), float(a.hw[3]));
   double4 hwd = make_double4(a.hw[0], a.hw[1], a.hw[2], a.hw[3]);
   hipLaunchKernelGGL((wilson_kernel<FORM, R>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U, a.nbr, a.V,
-                     a.nrhs, ngroups, typename Prec<FORM>::real(a.diag), hwf, hwd, a.partial);
+                     a.nrhs, ngroups, typename Prec<FORM>::real(a.diag), hwf, hwd, a.partial, nsb, a.order,
+                     a.swizzle);
   CRK_LAUNCH_CHECK();
 }
 
@@ -212,22 +324,33 @@ void launch_wilson(const WilsonArgs& a, hipStream_t st) {
 
 int64_t wilson_partial_blocks(int64_t V) { return (V + 255) / 256; }
 
-void wilson_apply(const WilsonArgs& a, hipStream_t st) {
-  if (a.nrhs <= 0 || a.V <= 0) return;
-  CRK_REQUIRE(a.in != a.out, "dslash: in and out must not alias");
+void wilson_apply(const WilsonArgs& a_in, hipStream_t st) {
+  if (a_in.nrhs <= 0 || a_in.V <= 0) return;
+  CRK_REQUIRE(a_in.in != a_in.out, "dslash: in and out must not alias");
+  WilsonArgs a = a_in;
+  // launch-shape knobs (RHS per thread, grid order, XCD mapping) for tuning sweeps
+  if (const char* e = getenv("CRK_DSLASH_R")) a.rhs_per_thread = atoi(e);
+  if (const char* e = getenv("CRK_DSLASH_ORDER")) a.order = atoi(e);
+  if (const char* e = getenv("CRK_DSLASH_SWZ")) a.swizzle = atoi(e);
+  if (const char* e = getenv("CRK_DSLASH_LOOP")) a.rhs_loop = atoi(e);
+  const int R = a.rhs_per_thread < a.nrhs ? a.rhs_per_thread : a.nrhs;
+  if (a.rhs_loop && a.form == CRK_FORM_FP32) { launch_wilson_rhsloop<CRK_FORM_FP32>(a, st); return; }
   switch (a.form) {
     case CRK_FORM_FP64:
-      if (a.rhs_per_thread >= 2 && a.nrhs >= 2) launch_wilson<CRK_FORM_FP64, 2>(a, st);
+      if (R >= 4) launch_wilson<CRK_FORM_FP64, 4>(a, st);
+      else if (R >= 2) launch_wilson<CRK_FORM_FP64, 2>(a, st);
       else launch_wilson<CRK_FORM_FP64, 1>(a, st);
       break;
     case CRK_FORM_FP32:
-      if (a.rhs_per_thread >= 4 && a.nrhs >= 4) launch_wilson<CRK_FORM_FP32, 4>(a, st);
-      else if (a.rhs_per_thread >= 2 && a.nrhs >= 2) launch_wilson<CRK_FORM_FP32, 2>(a, st);
+      if (R >= 8) launch_wilson<CRK_FORM_FP32, 8>(a, st);
+      else if (R >= 4) launch_wilson<CRK_FORM_FP32, 4>(a, st);
+      else if (R >= 2) launch_wilson<CRK_FORM_FP32, 2>(a, st);
       else launch_wilson<CRK_FORM_FP32, 1>(a, st);
       break;
     case CRK_FORM_FP16S:
-      if (a.rhs_per_thread >= 4 && a.nrhs >= 4) launch_wilson<CRK_FORM_FP16S, 4>(a, st);
-      else if (a.rhs_per_thread >= 2 && a.nrhs >= 2) launch_wilson<CRK_FORM_FP16S, 2>(a, st);
+      if (R >= 8) launch_wilson<CRK_FORM_FP16S, 8>(a, st);
+      else if (R >= 4) launch_wilson<CRK_FORM_FP16S, 4>(a, st);
+      else if (R >= 2) launch_wilson<CRK_FORM_FP16S, 2>(a, st);
       else launch_wilson<CRK_FORM_FP16S, 1>(a, st);
       break;
     default:

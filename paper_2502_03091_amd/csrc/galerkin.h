@@ -24,4 +24,18 @@ struct GalerkinArgs {
 // coarse neighbour table nbr_c [8][Vc] (device positions).
 void galerkin_fine(const GalerkinArgs& A, const int* nbr_c, int64_t Vc, hipStream_t st);
 
+struct GalerkinCoarseArgs {
+  const double2* P;      // [2*ncoarse][k][nr] prolongator blocks of this level (row c'*nb + l)
+  const double2* links;  // this level's links [V][9][N][N] column-major, device order (block-major)
+  const int* nbr;        // this level's neighbours [8][V]
+  int64_t V;
+  int N;                 // components per site on this level (2h)
+  int nb, nr, k;         // sites per block, h*nb, kept vectors
+  int64_t ncoarse;
+  const int* pos_c;      // next level device position of lexicographic block j
+  double2* out;          // next level links [Vc][9][2k][2k]
+};
+
+void galerkin_coarse(const GalerkinCoarseArgs& A, const int* nbr_c, int64_t Vc, hipStream_t st);
+
 }  // namespace crk

@@ -12,6 +12,7 @@
 // contracted with P(x)^dag into per-thread register tiles of the 2k x 2k output.
 // Coarse links are stored per coarse site as 9 column-major 2k x 2k blocks:
 // index 0 = X, 1 + 2mu = Y_{+mu}, 2 + 2mu = Y_{-mu}.
+#include "field.h"
 #include "galerkin.h"
 
 namespace crk {
@@ -70,14 +71,15 @@ __device__ __forceinline__ void load_pcol(const GalerkinArgs& A, int64_t y, int 
   const int k = A.k, beta = col / k, i = col % k;
   const int64_t jy = y / A.nb, ly = y % A.nb;
   const double2* p = A.P + ((2 * jy + beta) * k + i) * int64_t(A.nr) + ly;
-#pragma unroll
-  for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) s[sp][b] = make_double2(0, 0);
+  const double2 z = make_double2(0, 0);
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) s[2 * beta + sp][b] = p[int64_t(3 * sp + b) * A.nb];
+    for (int b = 0; b < 3; ++b) {
+      const double2 v = p[int64_t(3 * sp + b) * A.nb];
+      s[sp][b] = beta == 0 ? v : z;       // constant indices only: no local-memory arrays
+      s[2 + sp][b] = beta == 0 ? z : v;
+    }
 }
 
 template <int MU, int SIGN>
@@ -86,16 +88,16 @@ __device__ __forceinline__ void add_hop(const GalerkinArgs& A, int64_t x, int64_
   double2 s[4][3], h[2][3];
   load_pcol(A, y, col, s);
   project_col<MU, SIGN>(s, h);
-  const double2* U = A.gauge + int64_t(MU) * 9 * A.V;
+  const int64_t Vp = pad_sites(A.V);
   double2 g0 = make_double2(0, 0), g1 = make_double2(0, 0);
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
     if constexpr (SIGN > 0) {
-      const double2 u = U[int64_t(3 * a + b) * A.V + x];
+      const double2 u = A.gauge[aidx(MU, 3 * a + b, x, Vp, 9)];
       cfma(g0, u, h[0][b]);
       cfma(g1, u, h[1][b]);
     } else {
-      const double2 u = U[int64_t(3 * b + a) * A.V + y];
+      const double2 u = A.gauge[aidx(MU, 3 * b + a, y, Vp, 9)];
       cfmac(g0, u, h[0][b]);
       cfmac(g1, u, h[1][b]);
     }
@@ -141,13 +143,19 @@ __global__ __launch_bounds__(kT) void galerkin_kernel(GalerkinArgs A) {
     for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) {
       const int col = e / 3, a = e % 3;
       double2 t[4];
+#pragma unroll
       for (int sp = 0; sp < 4; ++sp) t[sp] = make_double2(0, 0);
       if (part == 0) {
         // site term: (m0 + sum w) P(x)
         const int beta = col / k, i = col % k;
         const double2* p = A.P + ((2 * j + beta) * k + i) * int64_t(A.nr) + l;
-        t[2 * beta] = cscale(p[int64_t(a) * A.nb], A.diag);
-        t[2 * beta + 1] = cscale(p[int64_t(3 + a) * A.nb], A.diag);
+        const double2 v0 = cscale(p[int64_t(a) * A.nb], A.diag);
+        const double2 v1 = cscale(p[int64_t(3 + a) * A.nb], A.diag);
+        const double2 z = make_double2(0, 0);
+        t[0] = beta == 0 ? v0 : z;
+        t[1] = beta == 0 ? v1 : z;
+        t[2] = beta == 0 ? z : v0;
+        t[3] = beta == 0 ? z : v1;
       }
       maybe_hop<0, +1>(A, x, j, col, a, part, t);
       maybe_hop<0, -1>(A, x, j, col, a, part, t);
@@ -218,6 +226,113 @@ void galerkin_fine(const GalerkinArgs& A, const int* nbr_c, int64_t Vc, hipStrea
   }
   CRK_LAUNCH_CHECK();
   hipLaunchKernelGGL(backward_links_kernel, dim3(unsigned(Vc * 4)), dim3(kT), 0, st, A.links, nbr_c, Vc, N, A.k);
+  CRK_LAUNCH_CHECK();
+}
+
+}  // namespace crk
+
+// ---------------------------------------------------------------- coarse levels
+// Galerkin product of a coarse stencil operator (level l >= 1, N = 2h
+// components per site, links [V][9][N][N] column-major) with its prolongator:
+// the same X / Y_{+mu} formulas with the Wilson hops replaced by the stored
+// link blocks, P(x) being chirality-sparse (rows alpha*h.. of column alpha*k+i).
+namespace crk {
+namespace {
+
+template <int TI>
+__global__ __launch_bounds__(256) void galerkin_coarse_kernel(GalerkinCoarseArgs A) {
+  constexpr int NC = 16 * TI;  // 2k of the new level
+  extern __shared__ double2 sm[];
+  const int N = A.N, h = N / 2, k = A.k;
+  double2* T = sm;             // [N][NC]  sum of link * P(y)
+  double2* Pc = T + N * NC;    // [h][NC]  P(x) compressed to its chirality's h rows
+  const int64_t j = blockIdx.x / 5;
+  const int part = blockIdx.x % 5;
+  const int rg = threadIdx.x / 16, cg = threadIdx.x % 16;
+  double2 acc[TI][TI];
+#pragma unroll
+  for (int x = 0; x < TI; ++x)
+#pragma unroll
+    for (int y = 0; y < TI; ++y) acc[x][y] = make_double2(0, 0);
+  for (int l = 0; l < A.nb; ++l) {
+    const int64_t x = j * A.nb + l;
+    if (part > 0) {
+      const int64_t y = A.nbr[int64_t(2 * (part - 1)) * A.V + x];
+      if (y / A.nb == j) continue;  // uniform across the workgroup
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < h * NC; e += blockDim.x) {
+      const int c = e / NC, col = e % NC, beta = col / k, i = col % k;
+      Pc[c * NC + col] = A.P[((2 * j + beta) * k + i) * int64_t(A.nr) + int64_t(c) * A.nb + l];
+    }
+    // T[row][col] = sum over the selected links Y (incl. X for part 0) of
+    //               sum_c' Y[row][beta*h + c'] P(y)[beta*h + c'][col]
+    for (int e = threadIdx.x; e < N * NC; e += blockDim.x) {
+      const int row = e / NC, col = e % NC, beta = col / k, i = col % k;
+      double2 t = make_double2(0, 0);
+      for (int nbi = 0; nbi < 9; ++nbi) {
+        int64_t y;
+        if (nbi == 0) {
+          if (part != 0) continue;
+          y = x;
+        } else {
+          y = A.nbr[int64_t(nbi - 1) * A.V + x];
+          const bool inside = (y / A.nb) == j;
+          if (part == 0 ? !inside : (nbi != 1 + 2 * (part - 1) || inside)) continue;
+        }
+        const double2* Y = A.links + (x * 9 + nbi) * int64_t(N) * N;  // column-major
+        const int64_t jy = y / A.nb, ly = y % A.nb;
+        const double2* py = A.P + ((2 * jy + beta) * k + i) * int64_t(A.nr) + ly;
+        for (int c = 0; c < h; ++c) cfma(t, Y[int64_t(beta * h + c) * N + row], py[int64_t(c) * A.nb]);
+      }
+      T[row * NC + col] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int xr = 0; xr < TI; ++xr) {
+      const int r = rg * TI + xr;
+      const int ar = r / k;
+      for (int c = 0; c < h; ++c) {
+        const double2 pr = Pc[c * NC + r];
+#pragma unroll
+        for (int yc = 0; yc < TI; ++yc) cfmac(acc[xr][yc], pr, T[(ar * h + c) * NC + cg * TI + yc]);
+      }
+    }
+  }
+  const int64_t jpos = A.pos_c ? A.pos_c[j] : j;
+  const int nbidx = part == 0 ? 0 : 1 + 2 * (part - 1);
+  double2* out = A.out + (jpos * 9 + nbidx) * int64_t(NC) * NC;
+#pragma unroll
+  for (int xr = 0; xr < TI; ++xr)
+#pragma unroll
+    for (int yc = 0; yc < TI; ++yc) {
+      const int r = rg * TI + xr, c = cg * TI + yc;
+      out[int64_t(c) * NC + r] = acc[xr][yc];
+    }
+}
+
+}  // namespace
+
+void galerkin_coarse(const GalerkinCoarseArgs& A, const int* nbr_c, int64_t Vc, hipStream_t st) {
+  const int NC = 2 * A.k;
+  CRK_REQUIRE(NC % 16 == 0 && NC <= 64, "2k must be 16, 32, 48 or 64");
+  const dim3 g = dim3(unsigned(A.ncoarse * 5));
+  const size_t lds = sizeof(double2) * size_t(A.N + A.N / 2) * NC;
+  CRK_REQUIRE(lds <= 160 * 1024, "coarse Galerkin: LDS above 160 KiB");
+  auto launch = [&](auto kern) {
+    if (lds > 64 * 1024)
+      CRK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(lds)));
+    hipLaunchKernelGGL(kern, g, dim3(256), lds, st, A);
+  };
+  switch (NC / 16) {
+    case 1: launch(galerkin_coarse_kernel<1>); break;
+    case 2: launch(galerkin_coarse_kernel<2>); break;
+    case 3: launch(galerkin_coarse_kernel<3>); break;
+    default: launch(galerkin_coarse_kernel<4>); break;
+  }
+  CRK_LAUNCH_CHECK();
+  hipLaunchKernelGGL(backward_links_kernel, dim3(unsigned(Vc * 4)), dim3(256), 0, st, A.out, nbr_c, Vc, NC, A.k);
   CRK_LAUNCH_CHECK();
 }
 

@@ -76,7 +76,7 @@ __global__ void gauge_kernel(const double2* __restrict__ src, typename Prec<FORM
   typename Prec<FORM>::store v;
   if constexpr (FORM == CRK_FORM_FP16S) v = __float22half2_rn(make_float2(float(u.x), float(u.y)));
   else v = ccast<typename Prec<FORM>::store>(u);
-  dst[(int64_t(mu) * 9 + e) * V + p] = v;
+  dst[aidx(mu, e, p, pad_sites(V), 9)] = v;
 }
 
 // One thread per (rhs, site): gathers the ncomp components of one site.
@@ -88,18 +88,19 @@ __global__ void import_kernel(const double2* __restrict__ src, void* dst, const 
   if (i >= V * nrhs) return;
   const int64_t r = i / V, s = i % V;
   const int64_t p = pos ? pos[s] : s;
+  const int64_t Vp = pad_sites(V);
   const double2* in = src + (r * V + s) * ncomp;
-  S* out = static_cast<S*>(dst) + r * ncomp * V + p;
+  S* out = static_cast<S*>(dst) + aidx(r, 0, p, Vp, ncomp);
   if constexpr (FORM == CRK_FORM_FP16S) {
     float m = 0.f;
     for (int c = 0; c < ncomp; ++c) m = fmaxf(m, fmaxf(fabsf(float(in[c].x)), fabsf(float(in[c].y))));
     const float inv = m > 0.f ? 1.f / m : 0.f;
-    float* sc = reinterpret_cast<float*>(static_cast<S*>(dst) + int64_t(nrhs) * ncomp * V);
-    sc[r * V + p] = m;
+    float* sc = reinterpret_cast<float*>(static_cast<S*>(dst) + int64_t(nrhs) * ncomp * Vp);
+    sc[r * Vp + p] = m;
     for (int c = 0; c < ncomp; ++c)
-      out[c * V] = __float22half2_rn(make_float2(float(in[c].x) * inv, float(in[c].y) * inv));
+      out[c * kVL] = __float22half2_rn(make_float2(float(in[c].x) * inv, float(in[c].y) * inv));
   } else {
-    for (int c = 0; c < ncomp; ++c) out[c * V] = ccast<S>(in[c]);
+    for (int c = 0; c < ncomp; ++c) out[c * kVL] = ccast<S>(in[c]);
   }
 }
 
@@ -111,17 +112,18 @@ __global__ void export_kernel(const void* src, double2* __restrict__ dst, const 
   if (i >= V * nrhs) return;
   const int64_t r = i / V, s = i % V;
   const int64_t p = pos ? pos[s] : s;
-  const S* in = static_cast<const S*>(src) + r * ncomp * V + p;
+  const int64_t Vp = pad_sites(V);
+  const S* in = static_cast<const S*>(src) + aidx(r, 0, p, Vp, ncomp);
   double2* out = dst + (r * V + s) * ncomp;
   if constexpr (FORM == CRK_FORM_FP16S) {
-    const float* sc = reinterpret_cast<const float*>(static_cast<const S*>(src) + int64_t(nrhs) * ncomp * V);
-    const float m = sc[r * V + p];
+    const float* sc = reinterpret_cast<const float*>(static_cast<const S*>(src) + int64_t(nrhs) * ncomp * Vp);
+    const float m = sc[r * Vp + p];
     for (int c = 0; c < ncomp; ++c) {
-      float2 f = __half22float2(in[c * V]);
+      float2 f = __half22float2(in[c * kVL]);
       out[c] = make_double2(double(f.x * m), double(f.y * m));
     }
   } else {
-    for (int c = 0; c < ncomp; ++c) out[c] = ccast<double2>(in[c * V]);
+    for (int c = 0; c < ncomp; ++c) out[c] = ccast<double2>(in[c * kVL]);
   }
 }
 
@@ -130,37 +132,40 @@ __global__ void convert_kernel(const void* src, void* dst, int64_t V, int ncomp,
   using SS = typename Prec<SF>::store;
   using DS = typename Prec<DF>::store;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= V * nrhs) return;
-  const int64_t r = i / V, s = i % V;
-  const SS* in = static_cast<const SS*>(src) + r * ncomp * V + s;
-  DS* out = static_cast<DS*>(dst) + r * ncomp * V + s;
+  const int64_t Vp = pad_sites(V);
+  if (i >= Vp * nrhs) return;
+  const int64_t r = i / Vp, s = i % Vp;
+  if (s >= V) return;  // padding sites are never read
+  const SS* in = static_cast<const SS*>(src) + aidx(r, 0, s, Vp, ncomp);
+  DS* out = static_cast<DS*>(dst) + aidx(r, 0, s, Vp, ncomp);
+  const int64_t V_ = Vp;  // scales are [nrhs][Vp]
   float m = 1.f, inv = 1.f;
   if constexpr (SF == CRK_FORM_FP16S) {
-    m = reinterpret_cast<const float*>(static_cast<const SS*>(src) + int64_t(nrhs) * ncomp * V)[r * V + s];
+    m = reinterpret_cast<const float*>(static_cast<const SS*>(src) + int64_t(nrhs) * ncomp * Vp)[r * V_ + s];
   }
   if constexpr (DF == CRK_FORM_FP16S) {
     float mx = 0.f;
     for (int c = 0; c < ncomp; ++c) {
       float2 f;
-      if constexpr (SF == CRK_FORM_FP16S) { f = __half22float2(in[c * V]); f.x *= m; f.y *= m; }
-      else f = ccast<float2>(in[c * V]);
+      if constexpr (SF == CRK_FORM_FP16S) { f = __half22float2(in[c * kVL]); f.x *= m; f.y *= m; }
+      else f = ccast<float2>(in[c * kVL]);
       mx = fmaxf(mx, fmaxf(fabsf(f.x), fabsf(f.y)));
     }
     inv = mx > 0.f ? 1.f / mx : 0.f;
-    reinterpret_cast<float*>(static_cast<DS*>(dst) + int64_t(nrhs) * ncomp * V)[r * V + s] = mx;
+    reinterpret_cast<float*>(static_cast<DS*>(dst) + int64_t(nrhs) * ncomp * Vp)[r * V_ + s] = mx;
   }
   for (int c = 0; c < ncomp; ++c) {
     if constexpr (SF == CRK_FORM_FP16S) {
-      float2 f = __half22float2(in[c * V]);
+      float2 f = __half22float2(in[c * kVL]);
       f.x *= m; f.y *= m;
-      if constexpr (DF == CRK_FORM_FP16S) out[c * V] = __float22half2_rn(make_float2(f.x * inv, f.y * inv));
-      else out[c * V] = ccast<DS>(f);
+      if constexpr (DF == CRK_FORM_FP16S) out[c * kVL] = __float22half2_rn(make_float2(f.x * inv, f.y * inv));
+      else out[c * kVL] = ccast<DS>(f);
     } else {
       if constexpr (DF == CRK_FORM_FP16S) {
-        float2 f = ccast<float2>(in[c * V]);
-        out[c * V] = __float22half2_rn(make_float2(f.x * inv, f.y * inv));
+        float2 f = ccast<float2>(in[c * kVL]);
+        out[c * kVL] = __float22half2_rn(make_float2(f.x * inv, f.y * inv));
       } else {
-        out[c * V] = ccast<DS>(in[c * V]);
+        out[c * kVL] = ccast<DS>(in[c * kVL]);
       }
     }
   }
@@ -234,7 +239,7 @@ void field_export(int form, const void* src, double2* dst, const int* pos, int64
 }
 
 void field_convert(int sf, const void* src, int df, void* dst, int64_t V, int ncomp, int nrhs, hipStream_t st) {
-  const dim3 g(ceil_div(V * nrhs, 256));
+  const dim3 g(ceil_div(pad_sites(V) * nrhs, 256));
   if (V * nrhs == 0) return;
 #define CRK_CONV(A, B) \
   if (sf == A && df == B) { hipLaunchKernelGGL((convert_kernel<A, B>), g, dim3(256), 0, st, src, dst, V, ncomp, nrhs); CRK_LAUNCH_CHECK(); return; }

@@ -21,7 +21,7 @@ Lattice* lattice_create(const int32_t dims[4], double m0, double xi) {
     CRK_HIP(hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking));
     L->geo.build(L->dims, nullptr, L->stream);
     L->U64.alloc(sizeof(double2) * 36 * V);
-    for (int f = 0; f < 3; ++f) L->gauge[f].alloc(store_bytes(f) * 36 * V);
+    for (int f = 0; f < 3; ++f) L->gauge[f].alloc(gauge_bytes(f, V));
     CRK_HIP(hipStreamSynchronize(L->stream));
   } catch (...) {
     if (L->stream) (void)hipStreamDestroy(L->stream);

@@ -41,6 +41,7 @@ int64_t prod4(const int d[4]) { return int64_t(d[0]) * d[1] * d[2] * d[3]; }
 void validate(const Lattice* L, const crk_mg_params& p) {
   CRK_REQUIRE(p.n_levels == 2 || p.n_levels == 3, "n_levels must be 2 or 3");
   CRK_REQUIRE(p.setup_form == CRK_FORM_FP64 || p.setup_form == CRK_FORM_FP32, "setup_form must be FP64 or FP32");
+  CRK_REQUIRE(L->V % kVL == 0, "the fine lattice volume must be a multiple of 64 for a hierarchy");
   int dims[4];
   std::memcpy(dims, L->dims, sizeof(dims));
   int N = 12;
@@ -103,8 +104,8 @@ static TransferGeom transfer_geom(Hierarchy* H, int l, int nrhs) {
   g.k = t.k;
   g.nblocks = t.nblocks;
   const int64_t V = H->V(l);
-  if (l == 0) { g.vr = 12 * V; g.vc = V; g.vs = 1; }
-  else { g.vr = 1; g.vc = nrhs; g.vs = int64_t(H->N(l)) * nrhs; }
+  if (l == 0) { g.aosoa = 1; g.ncomp = 12; g.Vp = pad_sites(V); g.vr = g.vc = g.vs = 0; }
+  else { g.aosoa = 0; g.ncomp = H->N(l); g.Vp = V; g.vr = 1; g.vc = nrhs; g.vs = int64_t(H->N(l)) * nrhs; }
   g.pos_c = H->coarse[l].geo.pos.as<int>();
   return g;
 }
@@ -235,8 +236,8 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
 
   // ---- chiral split + block SVD truncation -> P, sigma
   ChiralSrc src{};
-  if (!inner) { src.si = n; src.sc = V; src.ss = 1; }
-  else { src.si = 1; src.sc = m; src.ss = int64_t(N) * m; }
+  if (!inner) { src.aosoa = 1; src.ncomp = 12; src.Vp = pad_sites(V); src.si = src.sc = src.ss = 0; }
+  else { src.aosoa = 0; src.ncomp = N; src.Vp = V; src.si = 1; src.sc = m; src.ss = int64_t(N) * m; }
   src.h = N / 2;
   src.nb = t.nb;
   src.m = m;
@@ -271,7 +272,19 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
     g.links = c.links[0].as<double2>();
     galerkin_fine(g, c.geo.nbr.as<int>(), c.V, st);
   } else {
-    fail(CRK_EINVAL, "three-level hierarchies are not available in this build");
+    GalerkinCoarseArgs g{};
+    g.P = t.P64.as<double2>();
+    g.links = H->coarse[l - 1].links[0].as<double2>();
+    g.nbr = H->coarse[l - 1].geo.nbr.as<int>();
+    g.V = V;
+    g.N = N;
+    g.nb = t.nb;
+    g.nr = t.nr;
+    g.k = t.k;
+    g.ncoarse = t.nblocks;
+    g.pos_c = c.geo.pos.as<int>();
+    g.out = c.links[0].as<double2>();
+    galerkin_coarse(g, c.geo.nbr.as<int>(), c.V, st);
   }
   c.links[1].alloc(coarse_links_bytes(CRK_FORM_FP32, c.V, c.N));
   c.links[2].alloc(coarse_links_bytes(CRK_FORM_FP16S, c.V, c.N));
@@ -300,7 +313,7 @@ Hierarchy* mg_setup(Lattice* L, const crk_mg_params& p) {
     hipStream_t st = H->stream;
     H->fine_geo.build(L->dims, p.block[0], st);
     for (int f = 0; f < 3; ++f) {
-      H->fine_gauge[f].alloc(store_bytes(f) * 36 * L->V);
+      H->fine_gauge[f].alloc(gauge_bytes(f, L->V));
       gauge_convert(f, L->U64.as<double2>(), H->fine_gauge[f].p, H->fine_geo.pos.as<int>(), L->V, st);
     }
     int dims[4];

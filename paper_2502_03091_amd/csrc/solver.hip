@@ -59,8 +59,8 @@ struct GcrScalars {
   }
 };
 
-struct LevelWork {      // coarse level l >= 1: inner solve buffers
-  DevBuf x, r, b, Z, W;
+struct LevelWork {      // coarse level l >= 1: inner solve buffers (+ post-smoother fields)
+  DevBuf x, r, b, Z, W, rho, q;
   int maxit = 0;
   GcrScalars s;
 };
@@ -74,6 +74,8 @@ struct OuterWork {      // FP64 outer FGCR
   int nslots = 0;
   GcrScalars s;
 };
+
+constexpr int kPollEvery = 4;
 
 int64_t partial_doubles(int64_t n, int nrhs) {
   const int64_t a = gcr_partial_rows(n) * nrhs * 2 * kMaxBasis;
@@ -131,6 +133,7 @@ Workspace& workspace(Hierarchy* H, int nrhs, int form, const crk_solve_info& p) 
     lw.maxit = l == H->nlev - 1 ? p.coarsest_maxit : p.inner_maxit;
     const size_t cv = vec_bytes(form) * size_t(H->N(l)) * H->V(l) * nrhs;
     lw.x.alloc(cv); lw.r.alloc(cv); lw.b.alloc(cv);
+    if (l < H->nlev - 1) { lw.rho.alloc(cv); lw.q.alloc(cv); w.bytes += 2 * cv; }
     lw.Z.alloc(cv * lw.maxit); lw.W.alloc(cv * lw.maxit);
     lw.s.alloc(nrhs, partial_doubles(int64_t(H->N(l)) * H->V(l), nrhs));
     w.bytes += cv * (3 + 2 * size_t(lw.maxit));
@@ -175,9 +178,13 @@ void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, hipS
     gcr_scalars(s.sums3, s.active, nrhs, s.inv, s.a, s.breakdown, st);
     gcr_update(prec, zi, wi, lw.x.p, lw.r.p, s.inv, s.a, s.active, f, s.partial, nullptr, st);
     gcr_check(s.partial, f, tol2, s.b2, s.breakdown, s.active, s.iters, s.rn2, s.n_active, s.level_iters, st);
-    CRK_HIP(hipMemcpyAsync(&n_active, s.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
-    CRK_HIP(hipStreamSynchronize(st));
-    if (n_active == 0) break;
+    // Converged RHS are frozen on the device; the host only polls every few
+    // iterations to stop launching once every RHS is done.
+    if ((i + 1) % kPollEvery == 0 || i + 1 == lw.maxit) {
+      CRK_HIP(hipMemcpyAsync(&n_active, s.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+      CRK_HIP(hipStreamSynchronize(st));
+      if (n_active == 0) break;
+    }
   }
 }
 
@@ -193,9 +200,8 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, const vo
   const FieldShape f = shape(H, l, nrhs);
   const size_t fb = vec_bytes(form) * size_t(f.total());
   void *rho, *q;
-  DevBuf tr, tq;
   if (l == 0) { rho = w.fw.rho.p; q = w.fw.q.p; }
-  else { tr.alloc(fb); tq.alloc(fb); rho = tr.p; q = tq.p; }
+  else { rho = w.lv[l].rho.p; q = w.lv[l].q.p; }
   GcrScalars& s = l == 0 ? w.ow.s : w.lv[l].s;
   // the scalars of level l are idle while its K-cycle runs (the cycle is called
   // between the solver's kernel phases); only sums3/partial/a are reused here.
@@ -213,7 +219,6 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, const vo
     mr_alpha(s.sums3, nrhs, s.a, st);
     mr_update(prec, eout, rho, q, s.a, f.n, nrhs, l > 0, st);
   }
-  if (l > 0) CRK_HIP(hipStreamSynchronize(st));  // temporaries freed at scope exit
 }
 
 }  // namespace

@@ -10,6 +10,9 @@ namespace crk {
 // device order; chirality alpha takes components [alpha*h, (alpha+1)*h).
 struct ChiralSrc {
   int64_t si, sc, ss;
+  int aosoa;    // 1: site-vectorised fine layout (entries at aidx(i, c, site, Vp, ncomp)), strides unused
+  int ncomp;
+  int64_t Vp;
   int h;        // components per chirality (6 fine, k coarse)
   int nb;       // sites per block
   int m;        // columns (test vectors)

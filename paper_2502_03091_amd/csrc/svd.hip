@@ -20,6 +20,7 @@
 //
 // Row order inside a block on the device: rho = c'*|Lambda| + l (component c'
 // of the chirality, local site l), which is contiguous in the field layouts.
+#include "field.h"
 #include "kernels.h"
 #include "svd.h"
 
@@ -42,12 +43,13 @@ __device__ void load_block_rows(const ChiralSrc& src, const T2* base, const doub
   const int total = nrows * m;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     int rr, i;
-    if (src.si == 1) { i = e % m; rr = e / m; }       // columns contiguous in memory
+    if (src.si == 1 && !src.aosoa) { i = e % m; rr = e / m; }  // columns contiguous in memory
     else { rr = e % nrows; i = e / nrows; }           // rows contiguous in memory
     const int rho = r0 + rr;
     const int c = rho / src.nb, l = rho % src.nb;
     const int64_t site = int64_t(j) * src.nb + l;
-    const int64_t idx = int64_t(i) * src.si + int64_t(alpha * src.h + c) * src.sc + site * src.ss;
+    const int64_t idx = src.aosoa ? aidx(i, alpha * src.h + c, site, src.Vp, src.ncomp)
+                                  : int64_t(i) * src.si + int64_t(alpha * src.h + c) * src.sc + site * src.ss;
     double2 v = ld2(base, idx);
     const double s = inv_norm ? inv_norm[i] : 1.0;
     lds[rr * ldm + i] = make_double2(v.x * s, v.y * s);

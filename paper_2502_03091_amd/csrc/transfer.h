@@ -11,6 +11,9 @@ struct TransferGeom {
   int k;              // kept vectors per chirality (coarse side has 2k components)
   int64_t nblocks;    // coarse sites
   int64_t vr, vc, vs; // fine-side strides (rhs, component, site) in complex entries
+  int aosoa;          // 1: fine side is the site-vectorised fine layout (strides unused)
+  int ncomp;          // components per fine site (aosoa)
+  int64_t Vp;         // padded fine sites (aosoa)
   const int* pos_c;   // coarse device position of lexicographic block j (NULL = identity)
 };
 

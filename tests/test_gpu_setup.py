@@ -179,3 +179,38 @@ def test_setup_rejects_bad_parameters(crk):
         crk.Hierarchy(lat, m_prime=[16], k=[8], block=[[3, 2, 2, 2]], n_smooth=[2])   # block does not divide
     with pytest.raises(crk.CrkError):
         crk.Hierarchy(lat, m_prime=[8], k=[16], block=[[2, 2, 2, 2]], n_smooth=[2])   # k > m'
+
+
+def test_three_level_setup_matches_oracle(crk):
+    """4^4 -> 2^4 blocks -> 2^4 blocks: level-2 coarse operator of the recursion (sigma_3 chirality)."""
+    dims = [4, 4, 4, 4]
+    U = synth.gauge_field(dims, 0.3, 0, config=61)
+    iv0 = synth.gaussian_vectors(16, 256, 12, config=61, level=0)
+    iv1 = synth.gaussian_vectors(24, 16, 16, config=61, level=1)
+    lat = crk.Lattice(dims, -0.4, 1.0)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[16, 24], k=[8, 16], block=[[2, 2, 2, 2], [2, 2, 2, 2]], n_smooth=[10, 10],
+                      setup_form=0, init_vectors=[iv0, iv1])
+    op = WilsonOp(U, dims, -0.4, 1.0)
+    ref = omg.mg_setup(op, [16, 24], [8, 16], [[2, 2, 2, 2], [2, 2, 2, 2]], [10, 10],
+                       [as_columns(iv0), as_columns(iv1)], keep_vectors=True)
+    # level-1 smoothed vectors and singular values
+    v1 = H.vectors(1)
+    vo = as_fields(ref[1].vectors)
+    err = (np.abs(v1 - vo).max(axis=(1, 2)) / np.abs(vo).max(axis=(1, 2))).max()
+    assert err <= 1e-11, err
+    assert np.abs(H.sigma(1) - ref[1].sigma).max() <= 1e-11 * ref[1].sigma.max()
+    # level-2 operator: spectrum (basis independent) and sigma3-hermiticity
+    from oracle.stencil import StencilOp
+    X, Yp, Ym = H.coarse_links(1)
+    D2 = StencilOp(ref[2].op.dims, X, Yp, Ym).dense()
+    D2o = ref[2].op.dense()
+    sc = np.abs(D2o).max()
+    assert _spec_dist(np.linalg.eigvals(D2), np.linalg.eigvals(D2o)) <= 1e-10 * sc
+    s3 = np.diag([1.0] * 16 + [-1.0] * 16)
+    assert np.abs(D2.conj().T - s3 @ D2 @ s3).max() <= 1e-12 * sc
+    # level-1 -> level-2 Galerkin identity on the GPU operators
+    vc = synth.gaussian_vectors(3, 1, 32, config=62, level=0)
+    lhs = H.coarse_apply(2, vc)
+    rhs = H.restrict(1, H.coarse_apply(1, H.prolong(1, vc)))
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()

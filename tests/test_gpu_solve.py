@@ -93,3 +93,23 @@ def test_max_iter_reports_noconv(crk, c1):
     b = synth.gaussian_rhs(1, 256, config=6)
     x, info = H.solve(b, raise_on_noconv=False, form=0, max_iter=1)
     assert not info["converged"] and info["iters"] == 1 and np.isfinite(x).all()
+
+
+def test_three_level_solve_matches_oracle(crk):
+    dims = [4, 4, 4, 4]
+    U = synth.gauge_field(dims, 0.3, 0, config=8)
+    iv = omg.init_vectors_for([dims, [2, 2, 2, 2]], [12, 16], [16, 24], 8, synth.gaussian_vectors)
+    lat = crk.Lattice(dims, -0.4, 1.0)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[16, 24], k=[8, 16], block=[[2, 2, 2, 2], [2, 2, 2, 2]], n_smooth=[20, 20],
+                      setup_form=0, init_vectors=[as_fields(iv[0]), as_fields(iv[1])])
+    ref = omg.mg_setup(WilsonOp(U, dims, -0.4, 1.0), [16, 24], [8, 16], [[2, 2, 2, 2], [2, 2, 2, 2]], [20, 20], iv)
+    b = synth.gaussian_rhs(1, 256, config=8)
+    x, info = H.solve(b, form=0)
+    xo, io = omg.mg_solve(ref, as_columns(b), tol=1e-10)
+    print("gpu", info, "oracle", io, flush=True)
+    assert info["converged"] and info["true_rel_resid"] <= 1e-10
+    assert abs(info["iters"] - io["iters"]) <= 1
+    for form in (1, 2):
+        x, info = H.solve(b, form=form)
+        assert info["converged"] and info["true_rel_resid"] <= 1e-10
