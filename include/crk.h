@@ -211,6 +211,68 @@ int64_t crk_mg_footprint_bytes(crk_mg_t mg, int32_t nrhs, int32_t form);
 
 void crk_mg_destroy(crk_mg_t mg);
 
+/* ------------------------------------------------------------------ serving
+ * Continuously batched solve server (not in the paper: a serving loop around
+ * the solve above).  Hierarchies stay resident; every registered lattice has a
+ * FIFO of requests and up to max_lanes lanes.  A lane is one outer MG-GCR
+ * solver with slots_per_lane RHS slots, its own buffers, HIP stream and host
+ * thread.  Between two outer iterations a lane hands back finished RHS and
+ * admits queued requests into its free slots while its other RHS keep
+ * iterating.  A lane is opened when queued RHS exceed the free slots of the
+ * lattice's lanes and the lane's buffers fit in the HBM budget; idle lanes
+ * beyond a lattice's last close after idle_ms and return their memory.  Each
+ * RHS follows exactly the iteration it would follow alone (every kernel treats
+ * each RHS on its own), so results do not depend on the traffic mix.
+ *
+ * Threading: every call is thread-safe.  The caller keeps b and x of a request
+ * alive and untouched until crk_server_wait has returned for it.  A hierarchy
+ * registered with a server must not be solved through crk_mg_solve* at the
+ * same time; the server holds a reference on it, so crk_mg_destroy may be
+ * called at any time. */
+typedef struct crk_server_s* crk_server_t;
+
+typedef struct {
+  int64_t hbm_budget_bytes; /* device memory the lanes may use; <= 0: 80% of the free memory at creation */
+  int32_t slots_per_lane;   /* RHS slots per lane = the largest request size, 1..64 (default 12) */
+  int32_t max_lanes;        /* lanes per lattice, 1..16 (default 4) */
+  int32_t idle_ms;          /* an idle lane that is not its lattice's last closes after this long (default 200) */
+  crk_solve_info solve;     /* tol, max_iter, form, restart, tau, inner_maxit, coarsest_maxit, nu_post */
+} crk_server_params;
+
+typedef struct {
+  int32_t status;           /* CRK_OK, CRK_ENOCONV or the error of the lane that ran it */
+  int32_t lattice, nrhs;
+  int32_t lane;             /* lane id within the lattice */
+  int32_t joined;           /* 1 if admitted while other RHS were iterating in that lane */
+  int32_t iters;            /* outer iterations (max over the request's RHS) */
+  int32_t level_iters[CRK_MAX_LEVELS];
+  double true_rel_resid;    /* max over the request's RHS, FP64 */
+  double t_submit, t_admit, t_done; /* seconds since the server was created (steady clock) */
+} crk_request_info;
+
+typedef struct {
+  int64_t submitted, completed, failed, joins;
+  int64_t lanes_opened, lanes_closed, max_concurrent_lanes;
+  int64_t bytes_in_use, peak_bytes, budget_bytes;
+} crk_server_stats;
+
+void crk_server_params_default(crk_server_params* p);
+int crk_server_create(const crk_server_params* p, crk_server_t* out);
+/* Register a hierarchy; *lattice_id receives its index.  CRK_ENOMEM if one lane does not fit the budget. */
+int crk_server_add(crk_server_t srv, crk_mg_t mg, int32_t* lattice_id);
+/* Queue nrhs right-hand sides b (complex128 host layout [nrhs][V][12]); x receives the solutions.
+ * Returns at once; *request_id identifies the request. */
+int crk_server_submit(crk_server_t srv, int32_t lattice_id, const double* b, double* x, int32_t nrhs,
+                      uint64_t* request_id);
+/* Wait for a request (timeout_s < 0: no limit).  CRK_EBUSY on timeout (the request stays queued),
+ * otherwise the request's status; info is filled and the request id is released. */
+int crk_server_wait(crk_server_t srv, uint64_t request_id, double timeout_s, crk_request_info* info);
+int crk_server_get_stats(crk_server_t srv, crk_server_stats* out);
+/* Device bytes one lane of a registered lattice takes from the budget (solver buffers + staging). */
+int64_t crk_server_lane_bytes(crk_server_t srv, int32_t lattice_id);
+/* Finish every queued request, stop the lanes and free the server. */
+void crk_server_destroy(crk_server_t srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,44 @@ class SolveInfo(C.Structure):
         }
 
 
+class ServerParams(C.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", C.c_int64),
+        ("slots_per_lane", C.c_int32),
+        ("max_lanes", C.c_int32),
+        ("idle_ms", C.c_int32),
+        ("solve", SolveInfo),
+    ]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32),
+        ("lattice", C.c_int32),
+        ("nrhs", C.c_int32),
+        ("lane", C.c_int32),
+        ("joined", C.c_int32),
+        ("iters", C.c_int32),
+        ("level_iters", C.c_int32 * MAX_LEVELS),
+        ("true_rel_resid", C.c_double),
+        ("t_submit", C.c_double),
+        ("t_admit", C.c_double),
+        ("t_done", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: (list(getattr(self, k)) if k == "level_iters" else getattr(self, k)) for k, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "failed", "joins", "lanes_opened",
+                                          "lanes_closed", "max_concurrent_lanes", "bytes_in_use", "peak_bytes",
+                                          "budget_bytes")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -125,6 +163,14 @@ def _load():
         "crk_mg_prolong": (i32, [vp, i32, i32, vp, vp, i32]),
         "crk_mg_footprint_bytes": (i64, [vp, i32, i32]),
         "crk_mg_destroy": (None, [vp]),
+        "crk_server_params_default": (None, [C.POINTER(ServerParams)]),
+        "crk_server_create": (i32, [C.POINTER(ServerParams), C.POINTER(vp)]),
+        "crk_server_add": (i32, [vp, vp, C.POINTER(i32)]),
+        "crk_server_submit": (i32, [vp, i32, vp, vp, i32, C.POINTER(C.c_uint64)]),
+        "crk_server_wait": (i32, [vp, C.c_uint64, dbl, C.POINTER(RequestInfo)]),
+        "crk_server_get_stats": (i32, [vp, C.POINTER(ServerStats)]),
+        "crk_server_lane_bytes": (i64, [vp, i32]),
+        "crk_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -419,3 +465,95 @@ class Hierarchy:
 
     def footprint_bytes(self, nrhs, form=FORM_FP32):
         return int(_load().crk_mg_footprint_bytes(self.handle, int(nrhs), int(form)))
+
+
+class Server:
+    """Continuously batched solve server over resident hierarchies (see crk.h).
+
+    ``submit`` returns at once; the library's lane threads run the solves.  The
+    host arrays of a request are kept alive here until ``wait`` returns.
+    """
+
+    def __init__(self, hbm_budget_bytes=0, slots_per_lane=12, max_lanes=4, idle_ms=200, **solve):
+        p = ServerParams()
+        _load().crk_server_params_default(C.byref(p))
+        p.hbm_budget_bytes = int(hbm_budget_bytes)
+        p.slots_per_lane = int(slots_per_lane)
+        p.max_lanes = int(max_lanes)
+        p.idle_ms = int(idle_ms)
+        for k_, v_ in solve.items():
+            if k_ == "form" and isinstance(v_, str):
+                v_ = FORMS[v_]
+            setattr(p.solve, k_, v_)
+        h = C.c_void_p()
+        _check(_load().crk_server_create(C.byref(p), C.byref(h)))
+        self._h = h
+        self._held = {}
+        self._volumes = []
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise CrkError(EINVAL, "server is closed")
+        return self._h
+
+    def add(self, hierarchy):
+        lid = C.c_int32()
+        _check(_load().crk_server_add(self.handle, hierarchy.handle, C.byref(lid)))
+        self._volumes.append(hierarchy.volume(0))
+        return lid.value
+
+    def submit(self, lattice, b):
+        """Queue b (complex128 [nrhs, V, 12]); returns the request id."""
+        b = _as_c128(b)
+        if b.ndim == 2:
+            b = b[None]
+        if b.shape[1:] != (self._volumes[lattice], 12):
+            raise CrkError(EINVAL, f"b has shape {b.shape}, lattice {lattice} needs [nrhs, {self._volumes[lattice]}, 12]")
+        x = np.zeros_like(b)
+        rid = C.c_uint64()
+        _check(_load().crk_server_submit(self.handle, int(lattice), _cptr(b), _cptr(x), b.shape[0], C.byref(rid)))
+        self._held[rid.value] = (b, x)
+        return rid.value
+
+    def wait(self, rid, timeout=-1.0, raise_on_noconv=True):
+        """Block until request rid is done; returns (x, info dict).  None on timeout."""
+        info = RequestInfo()
+        rc = _load().crk_server_wait(self.handle, C.c_uint64(rid), float(timeout), C.byref(info))
+        if rc == EBUSY:
+            return None
+        b, x = self._held.pop(rid)
+        if rc != OK and (rc != ENOCONV or raise_on_noconv):
+            _check(rc)
+        d = info.as_dict()
+        d["converged"] = rc == OK
+        return x, d
+
+    def lane_bytes(self, lattice):
+        v = int(_load().crk_server_lane_bytes(self.handle, int(lattice)))
+        if v < 0:
+            _check(v)
+        return v
+
+    def stats(self):
+        s = ServerStats()
+        _check(_load().crk_server_get_stats(self.handle, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if self._h is not None:
+            _load().crk_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -30,6 +30,7 @@ SOURCES = [
     "lattice.cpp",
     "capi.cpp",
     "capi_mg.cpp",
+    "server.cpp",
 ]
 
 ARCH = os.environ.get("CRK_OFFLOAD_ARCH", "gfx950")
@@ -77,7 +78,7 @@ def build(verbose=False, jobs=None, extra=()):
             if verbose and msg.strip():
                 print(f"[{futs[f]}]\n{msg}", file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-pthread", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

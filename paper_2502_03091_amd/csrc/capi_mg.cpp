@@ -5,6 +5,7 @@
 
 #include "coarse.h"
 #include "mg.h"
+#include "server.h"
 
 namespace crk {
 void mg_export_coarse(Hierarchy* H, int level, const void* src, int src_double, double2* dst_dev, int m,
@@ -15,6 +16,7 @@ void mg_import_coarse(Hierarchy* H, int level, const double2* src_dev, void* dst
 
 struct crk_lattice_s { crk::Lattice* L; };
 struct crk_mg_s { crk::Hierarchy* H; };
+struct crk_server_s { crk::Server* S; };
 
 using namespace crk;
 
@@ -361,6 +363,119 @@ void crk_mg_destroy(crk_mg_t mg) {
   if (!mg) return;
   try { mg_destroy(mg->H); } catch (...) {}
   delete mg;
+}
+
+
+void crk_server_params_default(crk_server_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->hbm_budget_bytes = 0;
+  p->slots_per_lane = 12;
+  p->max_lanes = 4;
+  p->idle_ms = 200;
+  crk_solve_info_default(&p->solve);
+  p->solve.form = CRK_FORM_FP32;
+}
+
+int crk_server_create(const crk_server_params* p, crk_server_t* out) {
+  return guarded_mg([&] {
+    crk_clear_error_();
+    CRK_REQUIRE(p != nullptr && out != nullptr, "params and out must not be NULL");
+    *out = nullptr;
+    auto* h = new crk_server_s{nullptr};
+    try {
+      h->S = new Server(*p);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return CRK_OK;
+  });
+}
+
+int crk_server_add(crk_server_t srv, crk_mg_t mg, int32_t* lattice_id) {
+  return guarded_mg([&] {
+    crk_clear_error_();
+    CRK_REQUIRE(srv && srv->S, "server handle is NULL");
+    const int id = srv->S->add(hier(mg));
+    if (lattice_id) *lattice_id = id;
+    return CRK_OK;
+  });
+}
+
+int crk_server_submit(crk_server_t srv, int32_t lattice_id, const double* b, double* x, int32_t nrhs,
+                      uint64_t* request_id) {
+  return guarded_mg([&] {
+    crk_clear_error_();
+    CRK_REQUIRE(srv && srv->S, "server handle is NULL");
+    const uint64_t id = srv->S->submit(lattice_id, b, x, nrhs);
+    if (request_id) *request_id = id;
+    return CRK_OK;
+  });
+}
+
+int crk_server_wait(crk_server_t srv, uint64_t request_id, double timeout_s, crk_request_info* info) {
+  return guarded_mg([&] {
+    crk_clear_error_();
+    CRK_REQUIRE(srv && srv->S, "server handle is NULL");
+    Request r;
+    if (!srv->S->wait(request_id, timeout_s, r)) {
+      crk_set_error_("request not finished within the timeout");
+      return int(CRK_EBUSY);
+    }
+    if (info) {
+      info->status = r.status;
+      info->lattice = r.lattice;
+      info->nrhs = r.nrhs;
+      info->lane = r.lane;
+      info->joined = r.joined ? 1 : 0;
+      info->iters = r.iters;
+      for (int l = 0; l < CRK_MAX_LEVELS; ++l) info->level_iters[l] = r.level_iters[l];
+      info->true_rel_resid = r.resid;
+      info->t_submit = r.t_submit;
+      info->t_admit = r.t_admit;
+      info->t_done = r.t_done;
+    }
+    if (r.status != CRK_OK) crk_set_error_(r.error);
+    return r.status;
+  });
+}
+
+int crk_server_get_stats(crk_server_t srv, crk_server_stats* out) {
+  return guarded_mg([&] {
+    crk_clear_error_();
+    CRK_REQUIRE(srv && srv->S && out, "server handle or out is NULL");
+    const ServerStats s = srv->S->stats();
+    out->submitted = s.submitted;
+    out->completed = s.completed;
+    out->failed = s.failed;
+    out->joins = s.joins;
+    out->lanes_opened = s.lanes_opened;
+    out->lanes_closed = s.lanes_closed;
+    out->max_concurrent_lanes = s.max_concurrent_lanes;
+    out->bytes_in_use = s.bytes_in_use;
+    out->peak_bytes = s.peak_bytes;
+    out->budget_bytes = int64_t(srv->S->budget());
+    return CRK_OK;
+  });
+}
+
+int64_t crk_server_lane_bytes(crk_server_t srv, int32_t lattice_id) {
+  int64_t out = -1;
+  const int rc = guarded_mg([&] {
+    crk_clear_error_();
+    CRK_REQUIRE(srv && srv->S, "server handle is NULL");
+    out = int64_t(srv->S->lane_bytes(lattice_id));
+    return CRK_OK;
+  });
+  return rc == CRK_OK ? out : rc;
+}
+
+void crk_server_destroy(crk_server_t srv) {
+  if (!srv) return;
+  try { delete srv->S; } catch (...) {}
+  delete srv;
 }
 
 }  // extern "C"

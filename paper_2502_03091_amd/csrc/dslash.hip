@@ -12,8 +12,6 @@
 // site order (lexicographic or block-major) uses the same kernel.  Optionally
 // the kernel also emits per-workgroup partial sums <Dr, r> and <Dr, Dr> for
 // the minimal-residual smoother, so no separate pass over the fields is needed.
-#include <cstdlib>
-
 #include "field.h"
 #include "kernels.h"
 
@@ -327,12 +325,7 @@ int64_t wilson_partial_blocks(int64_t V) { return (V + 255) / 256; }
 void wilson_apply(const WilsonArgs& a_in, hipStream_t st) {
   if (a_in.nrhs <= 0 || a_in.V <= 0) return;
   CRK_REQUIRE(a_in.in != a_in.out, "dslash: in and out must not alias");
-  WilsonArgs a = a_in;
-  // launch-shape knobs (RHS per thread, grid order, XCD mapping) for tuning sweeps
-  if (const char* e = getenv("CRK_DSLASH_R")) a.rhs_per_thread = atoi(e);
-  if (const char* e = getenv("CRK_DSLASH_ORDER")) a.order = atoi(e);
-  if (const char* e = getenv("CRK_DSLASH_SWZ")) a.swizzle = atoi(e);
-  if (const char* e = getenv("CRK_DSLASH_LOOP")) a.rhs_loop = atoi(e);
+  const WilsonArgs& a = a_in;
   const int R = a.rhs_per_thread < a.nrhs ? a.rhs_per_thread : a.nrhs;
   if (a.rhs_loop && a.form == CRK_FORM_FP32) { launch_wilson_rhsloop<CRK_FORM_FP32>(a, st); return; }
   switch (a.form) {

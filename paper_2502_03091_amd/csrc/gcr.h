@@ -25,7 +25,8 @@ int64_t gcr_partial_rows(int64_t n);
 
 void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* w, const FieldShape& f, double* partial,
                   const uint32_t* valid, double2* coef, hipStream_t st);
-void gcr_multiaxpy(int prec, const void* Z, const void* W, int64_t fstride, int nj, void* z, void* w,
+// Sums the stored directions cyclically from slot j_first (the oldest one).
+void gcr_multiaxpy(int prec, const void* Z, const void* W, int64_t fstride, int nj, int j_first, void* z, void* w,
                    const double2* coef, const FieldShape& f, hipStream_t st);
 void gcr_scalars(const double* sums3, const int* active, int nrhs, double* inv, double2* a, int* breakdown,
                  hipStream_t st);

@@ -81,12 +81,14 @@ __global__ __launch_bounds__(kT) void multidot_reduce_kernel(const double* __res
   }
 }
 
-// z -= sum_j coef_j Z_j ; w -= sum_j coef_j W_j
+// z -= sum_j coef_j Z_j ; w -= sum_j coef_j W_j, summed from stored slot j_first
+// onwards (cyclically), i.e. oldest direction first: the rounding of an RHS's
+// update then depends only on its own directions, not on where in a ring they sit.
 template <class C>
 __global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb, const C* __restrict__ Wb,
-                                                       int64_t fstride, int nj, C* __restrict__ z, C* __restrict__ w,
-                                                       const double2* __restrict__ coef, int64_t n, int nrhs,
-                                                       int64_t rs, int64_t es) {
+                                                       int64_t fstride, int nj, int j_first, C* __restrict__ z,
+                                                       C* __restrict__ w, const double2* __restrict__ coef, int64_t n,
+                                                       int nrhs, int64_t rs, int64_t es) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n * nrhs) return;
   const int r = es == 1 ? int(t / n) : int(t % nrhs);
@@ -94,7 +96,8 @@ __global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb,
   const int64_t idx = int64_t(r) * rs + e * es;
   using T = decltype(C::x);
   C zz = z[idx], ww = w[idx];
-  for (int j = 0; j < nj; ++j) {
+  for (int t = 0; t < nj; ++t) {
+    const int j = t + j_first < nj ? t + j_first : t + j_first - nj;
     const double2 cd = coef[r * kMaxCoef + j];
     if (cd.x == 0.0 && cd.y == 0.0) continue;
     const C c = mk<C>(T(-cd.x), T(-cd.y));
@@ -252,18 +255,21 @@ void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* 
   }
 }
 
-void gcr_multiaxpy(int prec, const void* Z, const void* W, int64_t fstride, int nj, void* z, void* w,
+void gcr_multiaxpy(int prec, const void* Z, const void* W, int64_t fstride, int nj, int j_first, void* z, void* w,
                    const double2* coef, const FieldShape& f, hipStream_t st) {
   if (nj <= 0) return;
   CRK_REQUIRE(nj <= kMaxCoef, "GCR basis above 64 vectors");
+  CRK_REQUIRE(j_first >= 0 && j_first < nj, "GCR ring start out of range");
   const dim3 g(ceil_div(f.n * f.nrhs, kT));
   if (prec == CRK_FORM_FP64)
     hipLaunchKernelGGL(multiaxpy_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(Z),
-                       static_cast<const double2*>(W), fstride, nj, static_cast<double2*>(z), static_cast<double2*>(w),
+                       static_cast<const double2*>(W), fstride, nj, j_first, static_cast<double2*>(z),
+                       static_cast<double2*>(w),
                        coef, f.n, f.nrhs, f.rs, f.es);
   else
     hipLaunchKernelGGL(multiaxpy_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(Z),
-                       static_cast<const float2*>(W), fstride, nj, static_cast<float2*>(z), static_cast<float2*>(w),
+                       static_cast<const float2*>(W), fstride, nj, j_first, static_cast<float2*>(z),
+                       static_cast<float2*>(w),
                        coef, f.n, f.nrhs, f.rs, f.es);
   CRK_LAUNCH_CHECK();
 }

@@ -6,11 +6,12 @@
 // block-major order of the blocking that leads to the next level, so block
 // operations read contiguous ranges; the coarsest level is lexicographic.
 //
-// Field layouts: level 0 is rhs-outer [nrhs][12][V] (site fastest); coarse
+// Field layouts: level 0 is rhs-outer and site-vectorised (field.h); coarse
 // levels are rhs-inner [V][N][nrhs] so that the MFMA coarse operator reads
 // 16 right-hand sides of one component contiguously.
 #pragma once
 
+#include <atomic>
 #include <map>
 #include <memory>
 #include <vector>
@@ -62,6 +63,7 @@ struct Hierarchy {
   std::unique_ptr<Workspace> ws;
   std::vector<int> last_iters;
   std::vector<double> last_resid;
+  std::atomic<int> refs{1};          // handle + every server that holds the hierarchy
 
   Hierarchy();
   ~Hierarchy();
@@ -72,7 +74,7 @@ struct Hierarchy {
 };
 
 Hierarchy* mg_setup(Lattice* L, const crk_mg_params& p);
-void mg_destroy(Hierarchy* H);
+void mg_destroy(Hierarchy* H);   // drops one reference; frees at zero
 
 // Operators used by setup and solver (device fields in level layout, stream ordered).
 void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int nrhs, hipStream_t st,

@@ -357,6 +357,7 @@ Hierarchy* mg_setup(Lattice* L, const crk_mg_params& p) {
 
 void mg_destroy(Hierarchy* H) {
   if (!H) return;
+  if (--H->refs > 0) return;
   if (H->stream) {
     (void)hipStreamSynchronize(H->stream);
     (void)hipStreamDestroy(H->stream);

@@ -12,68 +12,45 @@
 // All right-hand sides advance together; per-RHS scalars, active flags and a
 // ring of stored directions with per-RHS valid windows reproduce, RHS by RHS,
 // the single-RHS recursion.
+#include "solver.h"
+
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
 #include "blas.h"
 #include "coarse.h"
-#include "gcr.h"
-#include "mg.h"
 
 namespace crk {
 
+void GcrScalars::alloc(int nrhs, int64_t partial_doubles) {
+  const size_t nr = size_t(nrhs);
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off += (b + 255) & ~size_t(255); return o; };
+  const size_t o_s3 = take(sizeof(double) * 3 * nr), o_b2 = take(sizeof(double) * nr),
+               o_rn = take(sizeof(double) * nr), o_inv = take(sizeof(double) * nr),
+               o_a = take(sizeof(double2) * nr), o_coef = take(sizeof(double2) * nr * kMaxCoef),
+               o_act = take(sizeof(int) * nr), o_it = take(sizeof(int) * nr), o_bd = take(sizeof(int) * nr),
+               o_na = take(sizeof(int)), o_li = take(sizeof(int) * nr), o_val = take(sizeof(uint32_t) * nr),
+               o_part = take(sizeof(double) * size_t(partial_doubles));
+  buf.alloc(off);
+  char* c = static_cast<char*>(buf.p);
+  sums3 = reinterpret_cast<double*>(c + o_s3);
+  b2 = reinterpret_cast<double*>(c + o_b2);
+  rn2 = reinterpret_cast<double*>(c + o_rn);
+  inv = reinterpret_cast<double*>(c + o_inv);
+  a = reinterpret_cast<double2*>(c + o_a);
+  coef = reinterpret_cast<double2*>(c + o_coef);
+  active = reinterpret_cast<int*>(c + o_act);
+  iters = reinterpret_cast<int*>(c + o_it);
+  breakdown = reinterpret_cast<int*>(c + o_bd);
+  n_active = reinterpret_cast<int*>(c + o_na);
+  level_iters = reinterpret_cast<int*>(c + o_li);
+  valid = reinterpret_cast<uint32_t*>(c + o_val);
+  partial = reinterpret_cast<double*>(c + o_part);
+}
+
 namespace {
-
-// Device scalars of one GCR instance.
-struct GcrScalars {
-  DevBuf buf;
-  double *sums3, *b2, *rn2, *inv, *partial;
-  double2 *a, *coef;
-  int *active, *iters, *breakdown, *n_active, *level_iters;
-  uint32_t* valid;
-  void alloc(int nrhs, int64_t partial_doubles) {
-    const size_t nr = size_t(nrhs);
-    size_t off = 0;
-    auto take = [&](size_t b) { size_t o = off; off += (b + 255) & ~size_t(255); return o; };
-    const size_t o_s3 = take(sizeof(double) * 3 * nr), o_b2 = take(sizeof(double) * nr),
-                 o_rn = take(sizeof(double) * nr), o_inv = take(sizeof(double) * nr),
-                 o_a = take(sizeof(double2) * nr), o_coef = take(sizeof(double2) * nr * kMaxCoef),
-                 o_act = take(sizeof(int) * nr), o_it = take(sizeof(int) * nr), o_bd = take(sizeof(int) * nr),
-                 o_na = take(sizeof(int)), o_li = take(sizeof(int) * nr), o_val = take(sizeof(uint32_t) * nr),
-                 o_part = take(sizeof(double) * size_t(partial_doubles));
-    buf.alloc(off);
-    char* c = static_cast<char*>(buf.p);
-    sums3 = reinterpret_cast<double*>(c + o_s3);
-    b2 = reinterpret_cast<double*>(c + o_b2);
-    rn2 = reinterpret_cast<double*>(c + o_rn);
-    inv = reinterpret_cast<double*>(c + o_inv);
-    a = reinterpret_cast<double2*>(c + o_a);
-    coef = reinterpret_cast<double2*>(c + o_coef);
-    active = reinterpret_cast<int*>(c + o_act);
-    iters = reinterpret_cast<int*>(c + o_it);
-    breakdown = reinterpret_cast<int*>(c + o_bd);
-    n_active = reinterpret_cast<int*>(c + o_na);
-    level_iters = reinterpret_cast<int*>(c + o_li);
-    valid = reinterpret_cast<uint32_t*>(c + o_val);
-    partial = reinterpret_cast<double*>(c + o_part);
-  }
-};
-
-struct LevelWork {      // coarse level l >= 1: inner solve buffers (+ post-smoother fields)
-  DevBuf x, r, b, Z, W, rho, q;
-  int maxit = 0;
-  GcrScalars s;
-};
-
-struct FineWork {       // level-0 K-cycle fields in the vector precision
-  DevBuf rin, e, rho, q;
-};
-
-struct OuterWork {      // FP64 outer FGCR
-  DevBuf b, x, r, tmp, Z, W;
-  int nslots = 0;
-  GcrScalars s;
-};
 
 constexpr int kPollEvery = 4;
 
@@ -84,73 +61,23 @@ int64_t partial_doubles(int64_t n, int nrhs) {
   return std::max(a, std::max(b, c));
 }
 
-}  // namespace
-
-struct Workspace {
-  int nrhs = -1, form = -1, restart = -1, inner = -1, coarsest = -1;
-  std::vector<LevelWork> lv;  // index l (0 unused)
-  FineWork fw;
-  OuterWork ow;
-  size_t bytes = 0;
-};
-
-namespace {
-
 int vec_prec(int form) { return form == CRK_FORM_FP64 ? CRK_FORM_FP64 : CRK_FORM_FP32; }
 size_t vec_bytes(int form) { return form == CRK_FORM_FP64 ? sizeof(double2) : sizeof(float2); }
 // Operator storage used on the fine level in a form (vectors there are FP32 for FP16S).
 int fine_op_form(int form) { return form == CRK_FORM_FP64 ? CRK_FORM_FP64 : CRK_FORM_FP32; }
-
-Workspace& workspace(Hierarchy* H, int nrhs, int form, const crk_solve_info& p) {
-  if (!H->ws) H->ws = std::make_unique<Workspace>();
-  Workspace& w = *H->ws;
-  const int nslots = std::max(1, std::min(p.restart, p.max_iter));
-  if (w.nrhs == nrhs && w.form == form && w.restart == nslots && w.inner == p.inner_maxit &&
-      w.coarsest == p.coarsest_maxit)
-    return w;
-  w = Workspace();
-  w.nrhs = nrhs;
-  w.form = form;
-  w.restart = nslots;
-  w.inner = p.inner_maxit;
-  w.coarsest = p.coarsest_maxit;
-  const int64_t V0 = H->V(0);
-  const size_t f64 = sizeof(double2) * 12 * size_t(V0) * nrhs;
-  OuterWork& o = w.ow;
-  o.nslots = nslots;
-  o.b.alloc(f64); o.x.alloc(f64); o.r.alloc(f64); o.tmp.alloc(f64);
-  o.Z.alloc(f64 * nslots); o.W.alloc(f64 * nslots);
-  o.s.alloc(nrhs, partial_doubles(12 * V0, nrhs));
-  w.bytes += f64 * (4 + 2 * size_t(nslots));
-  if (H->nlev > 1) {
-    const size_t fv = vec_bytes(form) * 12 * size_t(V0) * nrhs;
-    w.fw.rin.alloc(fv); w.fw.e.alloc(fv); w.fw.rho.alloc(fv); w.fw.q.alloc(fv);
-    w.bytes += 4 * fv;
-  }
-  w.lv.resize(H->nlev);
-  for (int l = 1; l < H->nlev; ++l) {
-    LevelWork& lw = w.lv[l];
-    lw.maxit = l == H->nlev - 1 ? p.coarsest_maxit : p.inner_maxit;
-    const size_t cv = vec_bytes(form) * size_t(H->N(l)) * H->V(l) * nrhs;
-    lw.x.alloc(cv); lw.r.alloc(cv); lw.b.alloc(cv);
-    if (l < H->nlev - 1) { lw.rho.alloc(cv); lw.q.alloc(cv); w.bytes += 2 * cv; }
-    lw.Z.alloc(cv * lw.maxit); lw.W.alloc(cv * lw.maxit);
-    lw.s.alloc(nrhs, partial_doubles(int64_t(H->N(l)) * H->V(l), nrhs));
-    w.bytes += cv * (3 + 2 * size_t(lw.maxit));
-  }
-  return w;
-}
+int ring_slots(const crk_solve_info& p) { return std::max(1, std::min(p.restart, p.max_iter)); }
 
 FieldShape shape(Hierarchy* H, int l, int nrhs) {
   return l == 0 ? fine_shape(H->V(0), nrhs) : coarse_shape(H->V(l), H->N(l), nrhs);
 }
 
-void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, const void* rin, void* eout, hipStream_t st);
+void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs, const void* rin, void* eout,
+            hipStream_t st);
 
-// Inner flexible GCR on coarse level l: solves D_l x = b (lw.b) from x = 0.
-void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, hipStream_t st) {
+// Inner flexible GCR on coarse level l over the first nrhs RHS: solves D_l x = b (lw.b) from x = 0.
+void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs, hipStream_t st) {
   LevelWork& lw = w.lv[l];
-  const int nrhs = w.nrhs, form = w.form, prec = vec_prec(form);
+  const int form = w.form, prec = vec_prec(form);
   const FieldShape f = shape(H, l, nrhs);
   const int64_t fs = f.total();  // complex entries per stored field
   const size_t fb = vec_bytes(form) * size_t(fs);
@@ -167,12 +94,12 @@ void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, hipS
   for (int i = 0; i < lw.maxit; ++i) {
     void* zi = Z + fb * i;
     void* wi = W + fb * i;
-    if (precond) kcycle(H, w, l, p, lw.r.p, zi, st);
+    if (precond) kcycle(H, w, l, p, nrhs, lw.r.p, zi, st);
     else CRK_HIP(hipMemcpyAsync(zi, lw.r.p, fb, hipMemcpyDeviceToDevice, st));
     level_apply(H, l, form, zi, wi, nrhs, st);
     if (i > 0) {
       gcr_multidot(prec, W, fs, i, wi, f, s.partial, nullptr, s.coef, st);
-      gcr_multiaxpy(prec, Z, W, fs, i, zi, wi, s.coef, f, st);
+      gcr_multiaxpy(prec, Z, W, fs, i, 0, zi, wi, s.coef, f, st);
     }
     rhs_dot(prec, wi, lw.r.p, f.n, nrhs, f.rs, f.es, s.partial, s.sums3, st);
     gcr_scalars(s.sums3, s.active, nrhs, s.inv, s.a, s.breakdown, st);
@@ -188,12 +115,13 @@ void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, hipS
   }
 }
 
-void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, const void* rin, void* eout, hipStream_t st) {
-  const int nrhs = w.nrhs, form = w.form, prec = vec_prec(form);
+void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs, const void* rin, void* eout,
+            hipStream_t st) {
+  const int form = w.form, prec = vec_prec(form);
   const int opf = l == 0 ? fine_op_form(form) : form;
   LevelWork& nx = w.lv[l + 1];
   level_restrict(H, l, form, rin, nx.b.p, nrhs, st);
-  inner_fgcr(H, w, l + 1, p, st);
+  inner_fgcr(H, w, l + 1, p, nrhs, st);
   level_prolong(H, l, form, nx.x.p, eout, nrhs, false, st);
   if (p.nu_post <= 0) return;
   // MR on D_l e = r, starting from e:  rho = r - D e ; q = D rho ; e += alpha rho ; rho -= alpha q
@@ -221,14 +149,277 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, const vo
   }
 }
 
+void validate(Hierarchy* H, const crk_solve_info& p) {
+  CRK_REQUIRE(p.tol > 0 && std::isfinite(p.tol), "tol must be > 0");
+  CRK_REQUIRE(p.max_iter >= 1, "max_iter must be >= 1");
+  CRK_REQUIRE(p.restart >= 1 && p.restart <= kMaxBasis, "restart must be in [1, 32]");
+  CRK_REQUIRE(p.inner_maxit >= 1 && p.inner_maxit <= kMaxBasis, "inner_maxit must be in [1, 32]");
+  CRK_REQUIRE(p.coarsest_maxit >= 1 && p.coarsest_maxit <= 64, "coarsest_maxit must be in [1, 64]");
+  CRK_REQUIRE(p.form == CRK_FORM_FP64 || p.form == CRK_FORM_FP32 || p.form == CRK_FORM_FP16S, "unknown form");
+  CRK_REQUIRE(p.tau > 0 && p.nu_post >= 0, "tau must be > 0 and nu_post >= 0");
+  (void)H;
+}
+
 }  // namespace
+
+bool workspace_fits(const Workspace& w, int cap, int form, const crk_solve_info& p) {
+  return w.cap >= cap && w.form == form && w.restart == ring_slots(p) && w.inner == p.inner_maxit &&
+         w.coarsest == p.coarsest_maxit;
+}
+
+std::unique_ptr<Workspace> make_workspace(Hierarchy* H, int cap, int form, const crk_solve_info& p, hipStream_t st) {
+  validate(H, p);
+  CRK_REQUIRE(cap >= 1 && cap <= 64, "right-hand-side capacity must be in [1, 64]");
+  auto wp = std::make_unique<Workspace>();
+  Workspace& w = *wp;
+  const int nslots = ring_slots(p);
+  w.cap = cap;
+  w.form = form;
+  w.restart = nslots;
+  w.inner = p.inner_maxit;
+  w.coarsest = p.coarsest_maxit;
+  const int64_t V0 = H->V(0);
+  const size_t f64 = sizeof(double2) * 12 * size_t(V0) * cap;
+  OuterWork& o = w.ow;
+  o.nslots = nslots;
+  o.b.alloc(f64); o.x.alloc(f64); o.r.alloc(f64); o.tmp.alloc(f64);
+  o.Z.alloc(f64 * nslots); o.W.alloc(f64 * nslots);
+  o.mask.alloc(sizeof(int) * cap);
+  o.s.alloc(cap, partial_doubles(12 * V0, cap));
+  // Slots may start at any ring position: every stored direction a slot's
+  // kernels touch must hold finite values from the start.
+  CRK_HIP(hipMemsetAsync(o.Z.p, 0, f64 * nslots, st));
+  CRK_HIP(hipMemsetAsync(o.W.p, 0, f64 * nslots, st));
+  CRK_HIP(hipMemsetAsync(o.x.p, 0, f64, st));
+  CRK_HIP(hipMemsetAsync(o.r.p, 0, f64, st));
+  CRK_HIP(hipMemsetAsync(o.b.p, 0, f64, st));
+  w.bytes += f64 * (4 + 2 * size_t(nslots));
+  if (H->nlev > 1) {
+    const size_t fv = vec_bytes(form) * 12 * size_t(V0) * cap;
+    w.fw.rin.alloc(fv); w.fw.e.alloc(fv); w.fw.rho.alloc(fv); w.fw.q.alloc(fv);
+    w.bytes += 4 * fv;
+  }
+  w.lv.resize(H->nlev);
+  for (int l = 1; l < H->nlev; ++l) {
+    LevelWork& lw = w.lv[l];
+    lw.maxit = l == H->nlev - 1 ? p.coarsest_maxit : p.inner_maxit;
+    CRK_REQUIRE(lw.maxit <= 64, "coarsest basis too large");
+    const size_t cv = vec_bytes(form) * size_t(H->N(l)) * H->V(l) * cap;
+    lw.x.alloc(cv); lw.r.alloc(cv); lw.b.alloc(cv);
+    if (l < H->nlev - 1) { lw.rho.alloc(cv); lw.q.alloc(cv); w.bytes += 2 * cv; }
+    lw.Z.alloc(cv * lw.maxit); lw.W.alloc(cv * lw.maxit);
+    lw.s.alloc(cap, partial_doubles(int64_t(H->N(l)) * H->V(l), cap));
+    CRK_HIP(hipMemsetAsync(lw.s.level_iters, 0, sizeof(int) * cap, st));
+    w.bytes += cv * (3 + 2 * size_t(lw.maxit));
+  }
+  CRK_HIP(hipStreamSynchronize(st));
+  return wp;
+}
+
+// ------------------------------------------------------------------ outer solver
+
+OuterSolver::OuterSolver(Hierarchy* H, Workspace* w, const crk_solve_info& p, hipStream_t st)
+    : H_(H), w_(w), p_(p), st_(st), cap_(w->cap), nslots_(w->ow.nslots) {
+  validate(H, p);
+  CRK_REQUIRE(workspace_fits(*w, 1, p.form, p), "workspace does not match the solve parameters");
+  state_.assign(cap_, kSlotFree);
+  iters_.assign(cap_, 0);
+  nbasis_.assign(cap_, 0);
+  bn_.assign(cap_, 0.0);
+  tres_.assign(cap_, 0.0);
+}
+
+int OuterSolver::free_slots() const { return int(std::count(state_.begin(), state_.end(), int(kSlotFree))); }
+
+int OuterSolver::first_free() const {
+  for (int s = 0; s < cap_; ++s)
+    if (state_[s] == kSlotFree) return s;
+  return -1;
+}
+
+int OuterSolver::running() const { return int(std::count(state_.begin(), state_.end(), int(kSlotRunning))); }
+
+int OuterSolver::width() const {
+  for (int s = cap_ - 1; s >= 0; --s)
+    if (state_[s] != kSlotFree) return s + 1;
+  return 0;
+}
+
+void OuterSolver::upload_active() {
+  std::vector<int> a(cap_);
+  for (int s = 0; s < cap_; ++s) a[s] = state_[s] == kSlotRunning;
+  CRK_HIP(hipMemcpyAsync(w_->ow.s.active, a.data(), sizeof(int) * cap_, hipMemcpyHostToDevice, st_));
+  CRK_HIP(hipStreamSynchronize(st_));  // the host vector goes out of scope
+}
+
+void OuterSolver::admit(int s0, int n, const void* b_dev) {
+  CRK_REQUIRE(n >= 1 && s0 >= 0 && s0 + n <= cap_, "slot range out of bounds");
+  for (int s = s0; s < s0 + n; ++s) CRK_REQUIRE(state_[s] == kSlotFree, "slot is in use");
+  OuterWork& o = w_->ow;
+  GcrScalars& s = o.s;
+  const int64_t V = H_->V(0);
+  const int64_t per = 12 * V;  // complex entries per RHS
+  double2* b = o.b.as<double2>() + per * s0;
+  double2* x = o.x.as<double2>() + per * s0;
+  double2* r = o.r.as<double2>() + per * s0;
+  const size_t bytes = sizeof(double2) * size_t(per) * n;
+  field_import(CRK_FORM_FP64, static_cast<const double2*>(b_dev), b, H_->fine_geo.pos.as<int>(), V, 12, n, st_);
+  CRK_HIP(hipMemsetAsync(x, 0, bytes, st_));
+  CRK_HIP(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, st_));
+  for (int l = 1; l < H_->nlev; ++l)
+    CRK_HIP(hipMemsetAsync(w_->lv[l].s.level_iters + s0, 0, sizeof(int) * n, st_));
+  rhs_dot(CRK_FORM_FP64, b, nullptr, per, n, per, 1, s.partial, s.sums3, st_);
+  std::vector<double> h3(3 * size_t(n));
+  CRK_HIP(hipMemcpyAsync(h3.data(), s.sums3, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, st_));
+  CRK_HIP(hipStreamSynchronize(st_));
+  for (int i = 0; i < n; ++i) {
+    const int q = s0 + i;
+    bn_[q] = std::sqrt(h3[3 * i + 2]);
+    CRK_REQUIRE(std::isfinite(bn_[q]), "right-hand side is not finite");
+    iters_[q] = 0;
+    nbasis_[q] = 0;
+    tres_[q] = 0.0;
+    state_[q] = bn_[q] > 0 ? kSlotRunning : kSlotConverged;  // b = 0: x = 0 is exact
+  }
+  upload_active();
+}
+
+void OuterSolver::true_residual(int wd) {
+  OuterWork& o = w_->ow;
+  GcrScalars& s = o.s;
+  const FieldShape f = fine_shape(H_->V(0), wd);
+  level_apply(H_, 0, CRK_FORM_FP64, o.x.p, o.tmp.p, wd, st_);
+  field_axpby(CRK_FORM_FP64, o.b.p, o.tmp.p, 1.0, -1.0, f.total(), st_);
+  rhs_dot(CRK_FORM_FP64, o.tmp.p, nullptr, f.n, wd, f.rs, f.es, s.partial, s.sums3, st_);
+}
+
+int OuterSolver::step() {
+  const int wd = width();
+  if (running() == 0) return 0;
+  Workspace& w = *w_;
+  OuterWork& o = w.ow;
+  GcrScalars& s = o.s;
+  const int64_t V = H_->V(0);
+  const FieldShape f = fine_shape(V, wd);
+  const int64_t fcap = 12 * V * cap_;  // complex entries between stored directions
+  const size_t fbcap = sizeof(double2) * size_t(fcap);
+  char* Z = static_cast<char*>(o.Z.p);
+  char* W = static_cast<char*>(o.W.p);
+  void* zi = Z + fbcap * ring_;
+  void* wi = W + fbcap * ring_;
+  if (H_->nlev > 1) {
+    void* rin = o.r.p;
+    if (p_.form != CRK_FORM_FP64) {
+      field_convert(CRK_FORM_FP64, o.r.p, CRK_FORM_FP32, w.fw.rin.p, V, 12, wd, st_);
+      rin = w.fw.rin.p;
+    }
+    void* e = p_.form == CRK_FORM_FP64 ? zi : w.fw.e.p;
+    kcycle(H_, w, 0, p_, wd, rin, e, st_);
+    if (p_.form != CRK_FORM_FP64) field_convert(CRK_FORM_FP32, w.fw.e.p, CRK_FORM_FP64, zi, V, 12, wd, st_);
+  } else {
+    CRK_HIP(hipMemcpyAsync(zi, o.r.p, sizeof(double2) * size_t(f.total()), hipMemcpyDeviceToDevice, st_));
+  }
+  level_apply(H_, 0, CRK_FORM_FP64, zi, wi, wd, st_);
+  used_ = std::min(used_ + 1, nslots_);
+  if (used_ > 1) {
+    std::vector<uint32_t> valid(wd, 0);
+    for (int r = 0; r < wd; ++r)
+      for (int a = 1; a <= nbasis_[r]; ++a) valid[r] |= 1u << ((ring_ - a + nslots_) % nslots_);
+    CRK_HIP(hipMemcpyAsync(s.valid, valid.data(), sizeof(uint32_t) * wd, hipMemcpyHostToDevice, st_));
+    gcr_multidot(CRK_FORM_FP64, W, fcap, used_, wi, f, s.partial, s.valid, s.coef, st_);
+    gcr_multiaxpy(CRK_FORM_FP64, Z, W, fcap, used_, (ring_ + 1) % used_, zi, wi, s.coef, f, st_);
+    CRK_HIP(hipStreamSynchronize(st_));  // valid lives on the host stack
+  }
+  rhs_dot(CRK_FORM_FP64, wi, o.r.p, f.n, wd, f.rs, f.es, s.partial, s.sums3, st_);
+  gcr_scalars(s.sums3, s.active, wd, s.inv, s.a, s.breakdown, st_);
+  gcr_update(CRK_FORM_FP64, zi, wi, o.x.p, o.r.p, s.inv, s.a, s.active, f, s.partial, s.rn2, st_);
+  std::vector<double> rn2(wd);
+  std::vector<int> bd(wd);
+  CRK_HIP(hipMemcpyAsync(rn2.data(), s.rn2, sizeof(double) * wd, hipMemcpyDeviceToHost, st_));
+  CRK_HIP(hipMemcpyAsync(bd.data(), s.breakdown, sizeof(int) * wd, hipMemcpyDeviceToHost, st_));
+  CRK_HIP(hipStreamSynchronize(st_));
+  bool need_true = false;
+  std::vector<int> claim(wd, 0), restart(wd, 0);
+  for (int r = 0; r < wd; ++r) {
+    if (state_[r] != kSlotRunning) continue;
+    iters_[r] += 1;
+    if (bd[r]) { state_[r] = kSlotStopped; continue; }  // breakdown: keep the best x
+    nbasis_[r] += 1;
+    if (std::sqrt(rn2[r]) <= p_.tol * bn_[r]) { claim[r] = 1; need_true = true; }
+    else if (nbasis_[r] >= nslots_) { restart[r] = 1; need_true = true; }
+  }
+  if (need_true) {
+    true_residual(wd);
+    std::vector<double> h3(3 * size_t(wd));
+    CRK_HIP(hipMemcpyAsync(h3.data(), s.sums3, sizeof(double) * 3 * wd, hipMemcpyDeviceToHost, st_));
+    CRK_HIP(hipStreamSynchronize(st_));
+    std::vector<int> mask(wd, 0);
+    for (int r = 0; r < wd; ++r) {
+      if (claim[r]) {
+        const double t = std::sqrt(h3[3 * r + 2]);
+        if (t <= p_.tol * bn_[r]) { state_[r] = kSlotConverged; tres_[r] = t / bn_[r]; }
+        else { mask[r] = 1; nbasis_[r] = 0; }
+      } else if (restart[r]) {
+        mask[r] = 1;
+        nbasis_[r] = 0;
+      }
+    }
+    CRK_HIP(hipMemcpyAsync(o.mask.p, mask.data(), sizeof(int) * wd, hipMemcpyHostToDevice, st_));
+    field_masked_copy(CRK_FORM_FP64, o.tmp.p, o.r.p, o.mask.as<int>(), f, st_);
+    CRK_HIP(hipStreamSynchronize(st_));
+  }
+  for (int r = 0; r < wd; ++r)
+    if (state_[r] == kSlotRunning && iters_[r] >= p_.max_iter) state_[r] = kSlotStopped;
+  upload_active();
+  ring_ = (ring_ + 1) % nslots_;
+  return running();
+}
+
+void OuterSolver::refresh_residuals() {
+  const int wd = width();
+  if (wd == 0) return;
+  true_residual(wd);
+  std::vector<double> h3(3 * size_t(wd));
+  CRK_HIP(hipMemcpyAsync(h3.data(), w_->ow.s.sums3, sizeof(double) * 3 * wd, hipMemcpyDeviceToHost, st_));
+  CRK_HIP(hipStreamSynchronize(st_));
+  for (int r = 0; r < wd; ++r)
+    if (state_[r] != kSlotFree) tres_[r] = bn_[r] > 0 ? std::sqrt(h3[3 * r + 2]) / bn_[r] : 0.0;
+}
+
+void OuterSolver::export_x(int s0, int n, void* x_dev) {
+  CRK_REQUIRE(n >= 1 && s0 >= 0 && s0 + n <= cap_, "slot range out of bounds");
+  const int64_t V = H_->V(0);
+  field_export(CRK_FORM_FP64, w_->ow.x.as<double2>() + 12 * V * s0, static_cast<double2*>(x_dev),
+               H_->fine_geo.pos.as<int>(), V, 12, n, st_);
+}
+
+void OuterSolver::level_iters(int s0, int n, std::vector<std::vector<int>>& out) {
+  out.assign(CRK_MAX_LEVELS, std::vector<int>(n, 0));
+  for (int l = 1; l < H_->nlev && l < CRK_MAX_LEVELS; ++l)
+    CRK_HIP(hipMemcpyAsync(out[l].data(), w_->lv[l].s.level_iters + s0, sizeof(int) * n, hipMemcpyDeviceToHost, st_));
+  CRK_HIP(hipStreamSynchronize(st_));
+  for (int i = 0; i < n; ++i) out[0][i] = iters_[s0 + i];
+}
+
+void OuterSolver::release(int s) {
+  CRK_REQUIRE(s >= 0 && s < cap_, "slot out of bounds");
+  if (state_[s] == kSlotFree) return;
+  // A free slot inside the running width is still swept by the kernels: give it
+  // a zero residual so that its inner solves stop at once.
+  const int64_t per = 12 * H_->V(0);
+  CRK_HIP(hipMemsetAsync(w_->ow.r.as<double2>() + per * s, 0, sizeof(double2) * size_t(per), st_));
+  state_[s] = kSlotFree;
+  upload_active();
+}
+
+// ------------------------------------------------------------------ entry points
 
 Hierarchy::Hierarchy() = default;
 Hierarchy::~Hierarchy() = default;
 
 size_t mg_solve_footprint(Hierarchy* H, int nrhs, int form, const crk_solve_info& p) {
   const int64_t V0 = H->V(0);
-  const int nslots = std::max(1, std::min(p.restart, p.max_iter));
+  const int nslots = ring_slots(p);
   size_t b = sizeof(double2) * 12 * size_t(V0) * nrhs * (4 + 2 * size_t(nslots));
   if (H->nlev > 1) b += 4 * vec_bytes(form) * 12 * size_t(V0) * nrhs;
   for (int l = 1; l < H->nlev; ++l) {
@@ -240,140 +431,25 @@ size_t mg_solve_footprint(Hierarchy* H, int nrhs, int form, const crk_solve_info
 
 int mg_solve_dev(Hierarchy* H, const void* b_dev, void* x_dev, int nrhs, hipStream_t st, crk_solve_info* info) {
   const crk_solve_info& p = *info;
-  CRK_REQUIRE(p.tol > 0 && std::isfinite(p.tol), "tol must be > 0");
-  CRK_REQUIRE(p.max_iter >= 1, "max_iter must be >= 1");
-  CRK_REQUIRE(p.restart >= 1 && p.restart <= kMaxBasis, "restart must be in [1, 32]");
-  CRK_REQUIRE(p.inner_maxit >= 1 && p.inner_maxit <= kMaxBasis, "inner_maxit must be in [1, 32]");
-  CRK_REQUIRE(p.coarsest_maxit >= 1 && p.coarsest_maxit <= 64, "coarsest_maxit must be in [1, 64]");
-  CRK_REQUIRE(p.form == CRK_FORM_FP64 || p.form == CRK_FORM_FP32 || p.form == CRK_FORM_FP16S, "unknown form");
-  CRK_REQUIRE(p.tau > 0 && p.nu_post >= 0, "tau must be > 0 and nu_post >= 0");
+  validate(H, p);
   CRK_REQUIRE(nrhs >= 1 && nrhs <= 64, "nrhs must be in [1, 64]");
-  Workspace& w = workspace(H, nrhs, p.form, p);
-  // the coarsest GCR keeps up to coarsest_maxit directions
-  CRK_REQUIRE(H->nlev == 1 || w.lv[H->nlev - 1].maxit <= 64, "coarsest basis too large");
-  OuterWork& o = w.ow;
-  GcrScalars& s = o.s;
-  const int64_t V = H->V(0);
-  const FieldShape f = fine_shape(V, nrhs);
-  const int64_t fs = f.total();
-  const size_t fb = sizeof(double2) * size_t(fs);
-  const int* pos = H->fine_geo.pos.as<int>();
+  if (!H->ws || !workspace_fits(*H->ws, nrhs, p.form, p)) {
+    H->ws.reset();
+    H->ws = make_workspace(H, nrhs, p.form, p, st);
+  }
   hipEvent_t t0, t1;
   CRK_HIP(hipEventCreate(&t0));
   CRK_HIP(hipEventCreate(&t1));
   CRK_HIP(hipEventRecord(t0, st));
-
-  // b (host layout, lexicographic) -> native FP64 block-major
-  field_import(CRK_FORM_FP64, static_cast<const double2*>(b_dev), o.b.p, pos, V, 12, nrhs, st);
-  CRK_HIP(hipMemsetAsync(o.x.p, 0, fb, st));
-  CRK_HIP(hipMemcpyAsync(o.r.p, o.b.p, fb, hipMemcpyDeviceToDevice, st));
-  for (int l = 1; l < H->nlev; ++l) CRK_HIP(hipMemsetAsync(w.lv[l].s.level_iters, 0, sizeof(int) * nrhs, st));
-  rhs_dot(CRK_FORM_FP64, o.b.p, nullptr, f.n, nrhs, f.rs, f.es, s.partial, s.sums3, st);
-  std::vector<double> h3(3 * size_t(nrhs));
-  CRK_HIP(hipMemcpyAsync(h3.data(), s.sums3, sizeof(double) * 3 * nrhs, hipMemcpyDeviceToHost, st));
-  CRK_HIP(hipStreamSynchronize(st));
-  std::vector<double> bn(nrhs);
-  std::vector<int> active(nrhs), iters(nrhs, 0), nbasis(nrhs, 0), conv(nrhs, 0), mask(nrhs, 0);
-  std::vector<uint32_t> valid(nrhs, 0);
-  std::vector<int> slot_of_age;  // unused placeholder for clarity
-  for (int r = 0; r < nrhs; ++r) {
-    bn[r] = std::sqrt(h3[3 * r + 2]);
-    active[r] = bn[r] > 0;
-    conv[r] = bn[r] == 0;
+  OuterSolver os(H, H->ws.get(), p, st);
+  os.admit(0, nrhs, b_dev);
+  while (os.step() > 0) {
   }
-  CRK_HIP(hipMemcpyAsync(s.active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
-  const int nslots = o.nslots;
-  char* Z = static_cast<char*>(o.Z.p);
-  char* W = static_cast<char*>(o.W.p);
-  std::vector<double> rn2(nrhs), tn2(nrhs);
-  int slot = 0, used = 0;
-  for (int it = 0; it < p.max_iter; ++it) {
-    bool any = false;
-    for (int r = 0; r < nrhs; ++r) any |= active[r] != 0;
-    if (!any) break;
-    void* zi = Z + fb * slot;
-    void* wi = W + fb * slot;
-    if (H->nlev > 1) {
-      void* rin = o.r.p;
-      if (p.form != CRK_FORM_FP64) {
-        field_convert(CRK_FORM_FP64, o.r.p, CRK_FORM_FP32, w.fw.rin.p, V, 12, nrhs, st);
-        rin = w.fw.rin.p;
-      }
-      void* e = p.form == CRK_FORM_FP64 ? zi : w.fw.e.p;
-      kcycle(H, w, 0, p, rin, e, st);
-      if (p.form != CRK_FORM_FP64) field_convert(CRK_FORM_FP32, w.fw.e.p, CRK_FORM_FP64, zi, V, 12, nrhs, st);
-    } else {
-      CRK_HIP(hipMemcpyAsync(zi, o.r.p, fb, hipMemcpyDeviceToDevice, st));
-    }
-    level_apply(H, 0, CRK_FORM_FP64, zi, wi, nrhs, st);
-    used = std::min(used + 1, nslots);
-    if (used > 1) {
-      for (int r = 0; r < nrhs; ++r) {
-        uint32_t m = 0;
-        for (int a = 1; a <= nbasis[r]; ++a) m |= 1u << ((slot - a + nslots) % nslots);
-        valid[r] = m;
-      }
-      CRK_HIP(hipMemcpyAsync(s.valid, valid.data(), sizeof(uint32_t) * nrhs, hipMemcpyHostToDevice, st));
-      gcr_multidot(CRK_FORM_FP64, W, fs, used, wi, f, s.partial, s.valid, s.coef, st);
-      gcr_multiaxpy(CRK_FORM_FP64, Z, W, fs, used, zi, wi, s.coef, f, st);
-    }
-    rhs_dot(CRK_FORM_FP64, wi, o.r.p, f.n, nrhs, f.rs, f.es, s.partial, s.sums3, st);
-    gcr_scalars(s.sums3, s.active, nrhs, s.inv, s.a, s.breakdown, st);
-    gcr_update(CRK_FORM_FP64, zi, wi, o.x.p, o.r.p, s.inv, s.a, s.active, f, s.partial, s.rn2, st);
-    std::vector<int> bd(nrhs);
-    CRK_HIP(hipMemcpyAsync(rn2.data(), s.rn2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-    CRK_HIP(hipMemcpyAsync(bd.data(), s.breakdown, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
-    CRK_HIP(hipStreamSynchronize(st));
-    bool need_true = false;
-    std::vector<int> claim(nrhs, 0), restart(nrhs, 0);
-    for (int r = 0; r < nrhs; ++r) {
-      if (!active[r]) continue;
-      iters[r] += 1;
-      if (bd[r]) { active[r] = 0; continue; }  // breakdown: keep best x
-      nbasis[r] += 1;
-      if (std::sqrt(rn2[r]) <= p.tol * bn[r]) { claim[r] = 1; need_true = true; }
-      else if (nbasis[r] >= nslots) { restart[r] = 1; need_true = true; }
-    }
-    if (need_true) {
-      // tmp = b - D x  (true residual, FP64)
-      level_apply(H, 0, CRK_FORM_FP64, o.x.p, o.tmp.p, nrhs, st);
-      field_axpby(CRK_FORM_FP64, o.b.p, o.tmp.p, 1.0, -1.0, fs, st);
-      rhs_dot(CRK_FORM_FP64, o.tmp.p, nullptr, f.n, nrhs, f.rs, f.es, s.partial, s.sums3, st);
-      CRK_HIP(hipMemcpyAsync(h3.data(), s.sums3, sizeof(double) * 3 * nrhs, hipMemcpyDeviceToHost, st));
-      CRK_HIP(hipStreamSynchronize(st));
-      for (int r = 0; r < nrhs; ++r) {
-        mask[r] = 0;
-        if (claim[r]) {
-          if (std::sqrt(h3[3 * r + 2]) <= p.tol * bn[r]) { conv[r] = 1; active[r] = 0; }
-          else { mask[r] = 1; nbasis[r] = 0; }
-        } else if (restart[r]) {
-          mask[r] = 1;
-          nbasis[r] = 0;
-        }
-      }
-      DevBuf dm(sizeof(int) * nrhs);
-      CRK_HIP(hipMemcpyAsync(dm.p, mask.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
-      field_masked_copy(CRK_FORM_FP64, o.tmp.p, o.r.p, dm.as<int>(), f, st);
-      CRK_HIP(hipMemcpyAsync(s.active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
-      CRK_HIP(hipStreamSynchronize(st));
-    } else {
-      CRK_HIP(hipMemcpyAsync(s.active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
-    }
-    slot = (slot + 1) % nslots;
-  }
-  // final true residual of every RHS
-  level_apply(H, 0, CRK_FORM_FP64, o.x.p, o.tmp.p, nrhs, st);
-  field_axpby(CRK_FORM_FP64, o.b.p, o.tmp.p, 1.0, -1.0, fs, st);
-  rhs_dot(CRK_FORM_FP64, o.tmp.p, nullptr, f.n, nrhs, f.rs, f.es, s.partial, s.sums3, st);
-  field_export(CRK_FORM_FP64, o.x.p, static_cast<double2*>(x_dev), pos, V, 12, nrhs, st);
+  os.refresh_residuals();  // final true residual of every RHS
+  os.export_x(0, nrhs, x_dev);
   CRK_HIP(hipEventRecord(t1, st));
-  CRK_HIP(hipMemcpyAsync(h3.data(), s.sums3, sizeof(double) * 3 * nrhs, hipMemcpyDeviceToHost, st));
-  std::vector<std::vector<int>> li(H->nlev);
-  for (int l = 1; l < H->nlev; ++l) {
-    li[l].resize(nrhs);
-    CRK_HIP(hipMemcpyAsync(li[l].data(), w.lv[l].s.level_iters, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
-  }
-  CRK_HIP(hipStreamSynchronize(st));
+  std::vector<std::vector<int>> li;
+  os.level_iters(0, nrhs, li);
   float ms = 0;
   CRK_HIP(hipEventElapsedTime(&ms, t0, t1));
   (void)hipEventDestroy(t0);
@@ -386,14 +462,14 @@ int mg_solve_dev(Hierarchy* H, const void* b_dev, void* x_dev, int nrhs, hipStre
   H->last_resid.assign(nrhs, 0);
   bool all_conv = true;
   for (int r = 0; r < nrhs; ++r) {
-    const double rr = bn[r] > 0 ? std::sqrt(h3[3 * r + 2]) / bn[r] : 0.0;
-    H->last_iters[r] = iters[r];
+    const double rr = os.true_rel(r);
+    H->last_iters[r] = os.iters(r);
     H->last_resid[r] = rr;
-    info->iters = std::max(info->iters, iters[r]);
+    info->iters = std::max(info->iters, os.iters(r));
     info->true_rel_resid = std::max(info->true_rel_resid, rr);
     all_conv &= rr <= p.tol;
-    info->level_iters[0] = std::max(info->level_iters[0], iters[r]);
-    for (int l = 1; l < H->nlev && l < CRK_MAX_LEVELS; ++l) info->level_iters[l] = std::max(info->level_iters[l], li[l][r]);
+    for (int l = 0; l < H->nlev && l < CRK_MAX_LEVELS; ++l)
+      info->level_iters[l] = std::max(info->level_iters[l], li[l][r]);
   }
   return all_conv ? CRK_OK : CRK_ENOCONV;
 }
