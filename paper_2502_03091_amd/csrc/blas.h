@@ -5,9 +5,15 @@
 
 namespace crk {
 
+// Reductions over rhs-inner fields (element e of rhs r at e*nrhs + r) use
+// workgroup chunks of kInnerChunk elements of one RHS (one per thread): one
+// partial per (chunk, rhs), so an RHS's sums do not depend on how many RHS
+// share the field.
+constexpr int kInnerChunk = 256;
+
 // Number of partial rows rhs_dot needs per RHS for vectors of n entries
-// (partial buffer: rhs_dot_partials(n) * nrhs * 3 doubles).
-int64_t rhs_dot_partials(int64_t n);
+// (partial buffer: rhs_dot_partials(n, inner) * nrhs * 3 doubles).
+int64_t rhs_dot_partials(int64_t n, bool inner);
 
 // out3[r] = (Re, Im) of sum_e conj(a) b, and sum_e |a|^2, for every rhs r;
 // entry e of rhs r at index r*rs + e*es.  b may be NULL (then b = a).

@@ -167,12 +167,16 @@ int64_t chunk_for(int64_t n) {
 
 }  // namespace
 
-int64_t rhs_dot_partials(int64_t n) { return (n + chunk_for(n) - 1) / chunk_for(n); }
+int64_t rhs_dot_partials(int64_t n, bool inner) {
+  const int64_t c = inner ? int64_t(kInnerChunk) : chunk_for(n);
+  return (n + c - 1) / c;
+}
 
 void rhs_dot(int prec, const void* a, const void* b, int64_t n, int nrhs, int64_t rs, int64_t es, double* partial,
              double* out3, hipStream_t st) {
   if (nrhs <= 0 || n <= 0) return;
-  const int64_t chunk = chunk_for(n);
+  // rhs-inner (coarse) fields: one element per thread, many small workgroups
+  const int64_t chunk = es != 1 ? int64_t(kInnerChunk) : chunk_for(n);
   const int64_t nch = (n + chunk - 1) / chunk;
   const dim3 g = dim3(unsigned(nch), unsigned(nrhs));
   if (prec == CRK_FORM_FP64)

@@ -38,32 +38,38 @@ template <> struct Mfma<double> {
   }
 };
 
-// One wavefront per (coarse site, 16-RHS tile, 16-row tile): 2k/16 wavefronts per
-// site and tile share the B operands through the cache, which gives the small
-// coarse lattices enough wavefronts to fill the chip.
-template <class T>
-__global__ __launch_bounds__(64) void coarse_mfma_kernel(const typename cplx_t<T>::type* __restrict__ links,
-                                                         const typename cplx_t<T>::type* __restrict__ in,
-                                                         typename cplx_t<T>::type* __restrict__ out,
-                                                         const int* __restrict__ nbr, int64_t Vc, int nrhs,
-                                                         int ntiles, int N, T sign) {
+// One workgroup of three wavefronts per (coarse site, 16-RHS tile, 16-row
+// tile); wavefront w accumulates links 3w .. 3w+2 (X and the eight hops), the
+// partial tiles are added in LDS in a fixed order.  2k/16 row tiles of one site
+// and RHS tile share the B operands through the cache; splitting the nine
+// links gives the small coarse lattices enough wavefronts to keep loads in
+// flight.
+constexpr int kLinkWaves = 3;
+
+template <class T, int MT>
+__global__ __launch_bounds__(64 * kLinkWaves) void coarse_mfma_kernel(const typename cplx_t<T>::type* __restrict__ links,
+                                                                      const typename cplx_t<T>::type* __restrict__ in,
+                                                                      typename cplx_t<T>::type* __restrict__ out,
+                                                                      const int* __restrict__ nbr, int64_t Vc, int nrhs,
+                                                                      int ntiles, T sign) {
   using C = typename cplx_t<T>::type;
   using A = typename Mfma<T>::acc;
-  const int MT = N / 16;
+  constexpr int N = 16 * MT;
+  __shared__ T part[kLinkWaves - 1][8][64];
   const int mt = blockIdx.x % MT;
   const int64_t rest = blockIdx.x / MT;
   const int tile = int(rest % ntiles);
   const int64_t j = rest / ntiles;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int n = tile * 16 + (lane & 15);
   const int kq = lane >> 4;
   const bool live = n < nrhs;
   A are = A{0, 0, 0, 0}, aim = A{0, 0, 0, 0};
-  for (int nb = 0; nb < 9; ++nb) {
+  for (int nb = 3 * wv; nb < 3 * wv + 3; ++nb) {
     const int64_t s = nb == 0 ? j : int64_t(nbr[int64_t(nb - 1) * Vc + j]);
     const C* Lb = links + (j * 9 + nb) * int64_t(N) * N + mt * 16 + (lane & 15);
     const C* vb = in + s * int64_t(N) * nrhs + n;
-#pragma unroll 4
+#pragma unroll
     for (int ks = 0; ks < N / 4; ++ks) {
       const int kk = ks * 4 + kq;
       const C bv = live ? vb[int64_t(kk) * nrhs] : C{0, 0};
@@ -74,7 +80,22 @@ __global__ __launch_bounds__(64) void coarse_mfma_kernel(const typename cplx_t<T
       aim = Mfma<T>::op(av.y, bv.x, aim);
     }
   }
-  if (!live) return;
+  if (wv > 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      part[wv - 1][i][lane] = are[i];
+      part[wv - 1][4 + i][lane] = aim[i];
+    }
+  }
+  __syncthreads();
+  if (wv > 0 || !live) return;
+#pragma unroll
+  for (int w = 0; w < kLinkWaves - 1; ++w)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      are[i] += part[w][i][lane];
+      aim[i] += part[w][4 + i][lane];
+    }
   C* ob = out + j * int64_t(N) * nrhs + n;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -195,8 +216,16 @@ void launch_mfma(int N, const void* links, const void* in, void* out, const int*
   CRK_REQUIRE(N % 16 == 0 && N >= 16 && N <= 64, "coarse operator: 2k must be 16, 32, 48 or 64");
   const int ntiles = (nrhs + 15) / 16;
   const dim3 g = dim3(unsigned(Vc * ntiles * (N / 16)));
-  hipLaunchKernelGGL((coarse_mfma_kernel<T>), g, dim3(64), 0, st, static_cast<const C*>(links),
-                     static_cast<const C*>(in), static_cast<C*>(out), nbr, Vc, nrhs, ntiles, N, sign);
+  const dim3 b(64 * kLinkWaves);
+  const C* L = static_cast<const C*>(links);
+  const C* x = static_cast<const C*>(in);
+  C* y = static_cast<C*>(out);
+  switch (N / 16) {
+    case 1: hipLaunchKernelGGL((coarse_mfma_kernel<T, 1>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
+    case 2: hipLaunchKernelGGL((coarse_mfma_kernel<T, 2>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
+    case 3: hipLaunchKernelGGL((coarse_mfma_kernel<T, 3>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
+    default: hipLaunchKernelGGL((coarse_mfma_kernel<T, 4>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
+  }
   CRK_LAUNCH_CHECK();
 }
 

@@ -19,6 +19,8 @@ namespace crk {
 
 namespace {
 
+constexpr int kDirMaxRhs = 64;  // right-hand sides of one direction-split launch (partial sums in LDS)
+
 // Spin projection of psi onto the half spinor of (1 - sign*gamma_mu).
 template <int MU, int SIGN, class C>
 __device__ __forceinline__ void project(const C* s, C* h) {
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(256) void wilson_kernel(FineView<FORM> in, FineView
       }
     }
   }
-  __shared__ double red[3 * R][4];
+  // one partial row per wavefront (64 sites): no workgroup reduction needed
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -182,15 +184,12 @@ __global__ __launch_bounds__(256) void wilson_kernel(FineView<FORM> in, FineView
       v1 += __shfl_xor(v1, o);
       v2 += __shfl_xor(v2, o);
     }
-    if (lane == 0) { red[3 * r][wid] = v0; red[3 * r + 1][wid] = v1; red[3 * r + 2][wid] = v2; }
-  }
-  __syncthreads();
-  if (threadIdx.x < 3 * R) {
-    const int r = threadIdx.x / 3, v = threadIdx.x % 3;
-    const int nw = blockDim.x / 64;
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += red[threadIdx.x][w];
-    if (r0 + r < nrhs) partial[(sb * nrhs + (r0 + r)) * 3 + v] = t;
+    if (lane == 0 && r0 + r < nrhs && (sb * 4 + wid) * kVL < V) {
+      double* p = partial + ((sb * 4 + wid) * nrhs + (r0 + r)) * 3;
+      p[0] = v0;
+      p[1] = v1;
+      p[2] = v2;
+    }
   }
 }
 
@@ -240,7 +239,6 @@ __global__ __launch_bounds__(256) void wilson_rhsloop_kernel(FineView<FORM> in, 
     for (int e = 0; e < 9; ++e) u[d][e] = p[e * kVL];
   }
   const T hw0 = hw.x, hw1 = hw.y, hw2 = hw.z, hw3 = hw.w;
-  __shared__ double red[3][4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int r = 0; r < nrhs; ++r) {
     C acc[12];
@@ -278,14 +276,12 @@ __global__ __launch_bounds__(256) void wilson_rhsloop_kernel(FineView<FORM> in, 
         v1 += __shfl_xor(v1, o);
         v2 += __shfl_xor(v2, o);
       }
-      __syncthreads();  // previous RHS's reduction has been read
-      if (lane == 0) { red[0][wid] = v0; red[1][wid] = v1; red[2][wid] = v2; }
-      __syncthreads();
-      if (threadIdx.x < 3) {
-        const int nw = blockDim.x >> 6;
-        double t = 0.0;
-        for (int w = 0; w < nw; ++w) t += red[threadIdx.x][w];
-        partial[(sb * nrhs + r) * 3 + threadIdx.x] = t;
+      // one partial row per wavefront (64 sites)
+      if (lane == 0 && (sb * 4 + wid) * kVL < V) {
+        double* p = partial + ((sb * 4 + wid) * nrhs + r) * 3;
+        p[0] = v0;
+        p[1] = v1;
+        p[2] = v2;
       }
     }
   }
@@ -298,6 +294,130 @@ void launch_wilson_rhsloop(const WilsonArgs& a, hipStream_t st) {
   GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), pad_sites(a.V)};
   const float4 hw = make_float4(float(a.hw[0]), float(a.hw[1]), float(a.hw[2]), float(a.hw[3]));
   hipLaunchKernelGGL((wilson_rhsloop_kernel<FORM>), dim3(unsigned(nsb)), dim3(256), 0, st, in, out, U, a.nbr, a.V,
+                     a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle);
+  CRK_LAUNCH_CHECK();
+}
+
+// Both hops along MU for one RHS: the spin-MU components of the partial result
+// are returned in mine[], the other nine go to their owners' exchange slots.
+template <int FORM, int MU>
+__device__ __forceinline__ void hop_pair(const FineView<FORM>& in, int r, int64_t yf, int64_t yb,
+                                         const typename Prec<FORM>::cx (&uf)[9],
+                                         const typename Prec<FORM>::cx (&ub)[9], typename Prec<FORM>::real coef,
+                                         typename Prec<FORM>::cx (*xch)[3][kVL], int lane,
+                                         typename Prec<FORM>::cx (&mine)[3]) {
+  using C = typename Prec<FORM>::cx;
+  C acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = czero<C>();
+  C psi[12], h[6], g[6];
+  in.load(r, yf, psi);
+  project<MU, +1>(psi, h);
+  link_mul<+1>(uf, h, g);
+  accumulate<MU, +1>(acc, g, coef);
+  in.load(r, yb, psi);
+  project<MU, -1>(psi, h);
+  link_mul<-1>(ub, h, g);
+  accumulate<MU, -1>(acc, g, coef);
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (o == MU) mine[c] = acc[3 * o + c];
+      else xch[3 * MU + (o < MU ? o : o - 1)][c][lane] = acc[3 * o + c];
+    }
+  }
+}
+
+// Direction-split variant: a workgroup covers 64 sites with four wavefronts,
+// wavefront mu handling the two hops along mu for all 64 sites.  Its two
+// links stay in registers for the whole right-hand-side loop (18 complex per
+// thread instead of 72), which keeps several wavefronts per SIMD in flight.
+// Per RHS wavefront mu keeps the three components of spin mu of its partial
+// result and hands the other nine to their owners through LDS; after a barrier
+// it adds the diagonal term and the four partials of spin mu in a fixed order
+// and stores them.  A second barrier frees the LDS slots for the next RHS.
+template <int FORM>
+__global__ __launch_bounds__(256) void wilson_dir_kernel(FineView<FORM> in, FineView<FORM> out, GaugeView<FORM> U,
+                                                         const int* __restrict__ nbr, int64_t V, int nrhs,
+                                                         typename Prec<FORM>::real diag, double4 hw_d,
+                                                         double* __restrict__ partial, int swz) {
+  using C = typename Prec<FORM>::cx;
+  using T = typename Prec<FORM>::real;
+  using S = typename Prec<FORM>::store;
+  // xch[3*src + slot][c][site]: spin `owner` components of wavefront src's partial,
+  // slot = owner with src skipped (owner != src)
+  __shared__ C xch[12][3][kVL];
+  __shared__ double red[4][kDirMaxRhs][3];
+  const int64_t blk = swz ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int mu = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t s = blk * kVL + lane;
+  const bool live = s < V;
+  const int64_t sl = live ? s : 0;  // dead lanes compute on site 0 and store nothing
+  const int64_t yf = nbr[int64_t(2 * mu) * V + sl], yb = nbr[int64_t(2 * mu + 1) * V + sl];
+  C uf[9], ub[9];
+  {
+    const S* pf = U.data + aidx(mu, 0, sl, U.Vp, 9);
+    const S* pb = U.data + aidx(mu, 0, yb, U.Vp, 9);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      uf[e] = pf[e * kVL];
+      ub[e] = pb[e * kVL];
+    }
+  }
+  const T coef = T(mu == 0 ? hw_d.x : mu == 1 ? hw_d.y : mu == 2 ? hw_d.z : hw_d.w);
+  for (int r = 0; r < nrhs; ++r) {
+    C mine[3];
+    switch (mu) {
+      case 0: hop_pair<FORM, 0>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
+      case 1: hop_pair<FORM, 1>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
+      case 2: hop_pair<FORM, 2>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
+      default: hop_pair<FORM, 3>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
+    }
+    __syncthreads();
+    // spin mu of site s: diagonal + the partials of wavefronts 0..3 (fixed order)
+    const S* pin = in.data + aidx(r, 3 * mu, sl, in.Vp, 12);
+    S* pout = out.data + aidx(r, 3 * mu, sl, out.Vp, 12);
+    double v0 = 0, v1 = 0, v2 = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const C x = pin[c * kVL];
+      C q = cscale(x, diag);
+#pragma unroll
+      for (int src = 0; src < 4; ++src)
+        q = q + (src == mu ? mine[c] : xch[3 * src + (mu < src ? mu : mu - 1)][c][lane]);
+      if (live) {
+        pout[c * kVL] = q;
+        v0 += double(q.x) * x.x + double(q.y) * x.y;
+        v1 += double(q.x) * x.y - double(q.y) * x.x;
+        v2 += double(q.x) * q.x + double(q.y) * q.y;
+      }
+    }
+    if (partial != nullptr) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        v0 += __shfl_xor(v0, o);
+        v1 += __shfl_xor(v1, o);
+        v2 += __shfl_xor(v2, o);
+      }
+      if (lane == 0) { red[mu][r][0] = v0; red[mu][r][1] = v1; red[mu][r][2] = v2; }
+    }
+    __syncthreads();  // the exchange slots are rewritten by the next RHS
+  }
+  if (partial == nullptr) return;
+  for (int t = threadIdx.x; t < 3 * nrhs; t += blockDim.x) {
+    const int r = t / 3, v = t % 3;
+    partial[(blk * nrhs + r) * 3 + v] = red[0][r][v] + red[1][r][v] + red[2][r][v] + red[3][r][v];
+  }
+}
+
+template <int FORM>
+void launch_wilson_dir(const WilsonArgs& a, hipStream_t st) {
+  const int64_t nblk = (a.V + kVL - 1) / kVL;
+  FineView<FORM> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
+  GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), pad_sites(a.V)};
+  const double4 hw = make_double4(a.hw[0], a.hw[1], a.hw[2], a.hw[3]);
+  hipLaunchKernelGGL((wilson_dir_kernel<FORM>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U, a.nbr, a.V,
                      a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle);
   CRK_LAUNCH_CHECK();
 }
@@ -320,14 +440,15 @@ void launch_wilson(const WilsonArgs& a, hipStream_t st) {
 
 }  // namespace
 
-int64_t wilson_partial_blocks(int64_t V) { return (V + 255) / 256; }
+int64_t wilson_partial_blocks(int64_t V) { return (V + kVL - 1) / kVL; }
 
 void wilson_apply(const WilsonArgs& a_in, hipStream_t st) {
   if (a_in.nrhs <= 0 || a_in.V <= 0) return;
   CRK_REQUIRE(a_in.in != a_in.out, "dslash: in and out must not alias");
   const WilsonArgs& a = a_in;
   const int R = a.rhs_per_thread < a.nrhs ? a.rhs_per_thread : a.nrhs;
-  if (a.rhs_loop && a.form == CRK_FORM_FP32) { launch_wilson_rhsloop<CRK_FORM_FP32>(a, st); return; }
+  if (a.form == CRK_FORM_FP32) { launch_wilson_rhsloop<CRK_FORM_FP32>(a, st); return; }
+  if (a.nrhs <= kDirMaxRhs && a.form == CRK_FORM_FP64) { launch_wilson_dir<CRK_FORM_FP64>(a, st); return; }
   switch (a.form) {
     case CRK_FORM_FP64:
       if (R >= 4) launch_wilson<CRK_FORM_FP64, 4>(a, st);

@@ -20,8 +20,9 @@ struct FieldShape {
 inline FieldShape fine_shape(int64_t V, int nrhs) { return FieldShape{12 * V, nrhs, 12 * V, 1}; }
 inline FieldShape coarse_shape(int64_t V, int N, int nrhs) { return FieldShape{int64_t(N) * V, nrhs, 1, nrhs}; }
 
-// Rows of the partial buffers (times nrhs * 2*kMaxBasis doubles for multidot).
-int64_t gcr_partial_rows(int64_t n);
+// Rows of the partial buffers (times nrhs * 2*kMaxBasis doubles for multidot);
+// inner: rhs-inner (coarse) layout.
+int64_t gcr_partial_rows(int64_t n, bool inner);
 
 void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* w, const FieldShape& f, double* partial,
                   const uint32_t* valid, double2* coef, hipStream_t st);

@@ -29,6 +29,12 @@ int64_t chunk_of(int64_t n) {
   return c < 2048 ? 2048 : c;
 }
 
+// Elements per workgroup chunk: rhs-outer fields use long chunks (coalesced
+// runs of one RHS); rhs-inner fields use one element per thread so that the
+// small coarse fields still spread over many workgroups.  Either way the chunk
+// depends on n only, so an RHS's sums do not depend on the number of RHS.
+int64_t chunk_for_shape(int64_t n, bool inner) { return inner ? int64_t(kInnerChunk) : chunk_of(n); }
+
 // partial[chunk][r][2*j + {0,1}] = chunk sum of conj(W_j) w
 template <class C>
 __global__ __launch_bounds__(kT) void multidot_kernel(const C* __restrict__ Wb, int64_t fstride, int nj,
@@ -65,17 +71,62 @@ __global__ __launch_bounds__(kT) void multidot_kernel(const C* __restrict__ Wb, 
     partial[(int64_t(blockIdx.x) * nrhs + r) * (2 * kMaxBasis) + q] = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
 }
 
-// coef[r][j0 + j] = valid(r, j0 + j) ? sum over chunks : 0
+// Rhs-inner fields: one wavefront per (chunk of kInnerChunk elements, rhs);
+// lane l sums elements l, l + 64, ... of the chunk in order, then the lanes'
+// sums are transposed through LDS and lane q adds value q of lanes 0..63 in
+// order (64 LDS reads instead of a shuffle tree per value).
+template <class C>
+__global__ __launch_bounds__(64) void multidot_inner_kernel(const C* __restrict__ Wb, int64_t fstride, int nj,
+                                                            const C* __restrict__ w, int64_t n, int nrhs,
+                                                            int64_t rs, int64_t es, double* __restrict__ partial) {
+  __shared__ double sh[64][2 * kMaxBasis + 1];
+  const int r = blockIdx.y, l = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  double acc[2 * kMaxBasis];
+#pragma unroll
+  for (int q = 0; q < 2 * kMaxBasis; ++q) acc[q] = 0;
+  for (int i = 0; i < kInnerChunk / 64; ++i) {
+    const int64_t e = c * kInnerChunk + l + 64 * i;
+    if (e >= n) break;
+    const int64_t idx = int64_t(r) * rs + e * es;
+    const C y = w[idx];
+#pragma unroll
+    for (int j = 0; j < kMaxBasis; ++j) {
+      if (j < nj) {
+        const C x = Wb[j * fstride + idx];
+        acc[2 * j] += double(x.x) * y.x + double(x.y) * y.y;
+        acc[2 * j + 1] += double(x.x) * y.y - double(x.y) * y.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2 * kMaxBasis; ++q)
+    if (q < 2 * nj) sh[l][q] = acc[q];
+  __syncthreads();
+  if (l < 2 * nj) {
+    double t = 0;
+    for (int k = 0; k < 64; ++k) t += sh[k][l];
+    partial[(c * nrhs + r) * (2 * kMaxBasis) + l] = t;
+  }
+}
+
+// coef[r][j0 + j] = valid(r, j0 + j) ? sum over chunks : 0.  One workgroup per
+// rhs; wavefront g sums chunks g, g + 4, ... in order for every value q (lane q),
+// then the four wavefront sums are added in a fixed order.
 __global__ __launch_bounds__(kT) void multidot_reduce_kernel(const double* __restrict__ partial, int64_t nch, int nrhs,
                                                              int j0, int nj, const uint32_t* __restrict__ valid,
                                                              double2* __restrict__ coef) {
+  __shared__ double sh[kT / 64][2 * kMaxBasis];
   const int r = blockIdx.x;
+  const int q = threadIdx.x & 63, g = threadIdx.x >> 6;
+  double acc = 0;
+  if (q < 2 * nj)
+    for (int64_t c = g; c < nch; c += kT / 64) acc += partial[(c * nrhs + r) * (2 * kMaxBasis) + q];
+  sh[g][q] = acc;
+  __syncthreads();
   for (int j = threadIdx.x; j < nj; j += blockDim.x) {
-    double re = 0, im = 0;
-    for (int64_t c = 0; c < nch; ++c) {
-      re += partial[(c * nrhs + r) * (2 * kMaxBasis) + 2 * j];
-      im += partial[(c * nrhs + r) * (2 * kMaxBasis) + 2 * j + 1];
-    }
+    const double re = ((sh[0][2 * j] + sh[1][2 * j]) + sh[2][2 * j]) + sh[3][2 * j];
+    const double im = ((sh[0][2 * j + 1] + sh[1][2 * j + 1]) + sh[2][2 * j + 1]) + sh[3][2 * j + 1];
     const bool ok = valid ? ((valid[r] >> (j0 + j)) & 1u) : true;
     coef[r * kMaxCoef + j0 + j] = ok ? make_double2(re, im) : make_double2(0, 0);
   }
@@ -159,27 +210,37 @@ __global__ __launch_bounds__(kT) void update_kernel(C* __restrict__ z, C* __rest
   if (threadIdx.x == 0) partial[int64_t(blockIdx.x) * nrhs + r] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// rn2[r] = sum of partials; convergence bookkeeping of an inner solve.
-__global__ void check_kernel(const double* __restrict__ partial, int64_t nch, int nrhs, double tol2,
-                             const double* __restrict__ b2, const int* __restrict__ breakdown, int* __restrict__ active,
-                             int* __restrict__ iters, double* __restrict__ rn2, int* __restrict__ n_active,
-                             int* __restrict__ level_iters) {
+// rn2[r] = sum of partials (wavefront g adds chunks g, g + 4, ... in order, then
+// the four sums in a fixed order); convergence bookkeeping of an inner solve.
+__global__ __launch_bounds__(kT) void check_kernel(const double* __restrict__ partial, int64_t nch, int nrhs,
+                                                   double tol2, const double* __restrict__ b2,
+                                                   const int* __restrict__ breakdown, int* __restrict__ active,
+                                                   int* __restrict__ iters, double* __restrict__ rn2,
+                                                   int* __restrict__ n_active, int* __restrict__ level_iters) {
+  __shared__ double sh[kT / 64][64];
   __shared__ int cnt;
+  const int q = threadIdx.x & 63, g = threadIdx.x >> 6;
   if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
-  for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
-    double s = 0;
-    for (int64_t c = 0; c < nch; ++c) s += partial[c * nrhs + r];
-    rn2[r] = s;
-    if (active[r]) {
-      iters[r] += 1;
-      if (level_iters) level_iters[r] += 1;
-      const bool bd = breakdown ? breakdown[r] != 0 : false;
-      if (bd || !(s > tol2 * b2[r])) active[r] = 0;
+  for (int r0 = 0; r0 < nrhs; r0 += 64) {
+    const int r = r0 + q;
+    double acc = 0;
+    if (r < nrhs)
+      for (int64_t c = g; c < nch; c += kT / 64) acc += partial[c * nrhs + r];
+    sh[g][q] = acc;
+    __syncthreads();
+    if (g == 0 && r < nrhs) {
+      const double s = ((sh[0][q] + sh[1][q]) + sh[2][q]) + sh[3][q];
+      rn2[r] = s;
+      if (active[r]) {
+        iters[r] += 1;
+        if (level_iters) level_iters[r] += 1;
+        const bool bd = breakdown ? breakdown[r] != 0 : false;
+        if (bd || !(s > tol2 * b2[r])) active[r] = 0;
+      }
+      if (active[r]) atomicAdd(&cnt, 1);
     }
-    if (active[r]) atomicAdd(&cnt, 1);
+    __syncthreads();
   }
-  __syncthreads();
   if (threadIdx.x == 0) *n_active = cnt;
 }
 
@@ -229,27 +290,42 @@ __global__ __launch_bounds__(kT) void masked_copy_kernel(const C* __restrict__ x
 
 }  // namespace
 
-int64_t gcr_partial_rows(int64_t n) { return (n + chunk_of(n) - 1) / chunk_of(n); }
+int64_t gcr_partial_rows(int64_t n, bool inner) {
+  const int64_t c = chunk_for_shape(n, inner);
+  return (n + c - 1) / c;
+}
+
+namespace {
+// Chunks of the per-RHS partial sums of a field shape (see the kernels).
+int64_t shape_chunks(const FieldShape& f) { return gcr_partial_rows(f.n, f.es != 1); }
+}  // namespace
 
 void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* w, const FieldShape& f, double* partial,
                   const uint32_t* valid, double2* coef, hipStream_t st) {
   if (nj <= 0) return;
   CRK_REQUIRE(nj <= kMaxCoef, "GCR basis above 64 vectors");
   CRK_REQUIRE(valid == nullptr || nj <= 32, "masked GCR basis above 32 vectors");
-  const int64_t chunk = chunk_of(f.n), nch = (f.n + chunk - 1) / chunk;
+  const int64_t chunk = chunk_for_shape(f.n, f.es != 1), nch = shape_chunks(f);
   const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
   const size_t esz = prec == CRK_FORM_FP64 ? sizeof(double2) : sizeof(float2);
+  const dim3 gi = dim3(unsigned(nch), unsigned(f.nrhs));
   for (int j0 = 0; j0 < nj; j0 += kMaxBasis) {
     const int nc = nj - j0 < kMaxBasis ? nj - j0 : kMaxBasis;
     const void* Wj = static_cast<const char*>(W) + esz * size_t(j0) * size_t(fstride);
-    if (prec == CRK_FORM_FP64)
+    if (f.es != 1 && prec == CRK_FORM_FP64)
+      hipLaunchKernelGGL(multidot_inner_kernel<double2>, gi, dim3(64), 0, st, static_cast<const double2*>(Wj), fstride,
+                         nc, static_cast<const double2*>(w), f.n, f.nrhs, f.rs, f.es, partial);
+    else if (f.es != 1)
+      hipLaunchKernelGGL(multidot_inner_kernel<float2>, gi, dim3(64), 0, st, static_cast<const float2*>(Wj), fstride,
+                         nc, static_cast<const float2*>(w), f.n, f.nrhs, f.rs, f.es, partial);
+    else if (prec == CRK_FORM_FP64)
       hipLaunchKernelGGL(multidot_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(Wj), fstride, nc,
                          static_cast<const double2*>(w), f.n, f.nrhs, f.rs, f.es, chunk, partial);
     else
       hipLaunchKernelGGL(multidot_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(Wj), fstride, nc,
                          static_cast<const float2*>(w), f.n, f.nrhs, f.rs, f.es, chunk, partial);
     CRK_LAUNCH_CHECK();
-    hipLaunchKernelGGL(multidot_reduce_kernel, dim3(unsigned(f.nrhs)), dim3(64), 0, st, partial, nch, f.nrhs, j0, nc,
+    hipLaunchKernelGGL(multidot_reduce_kernel, dim3(unsigned(f.nrhs)), dim3(kT), 0, st, partial, nch, f.nrhs, j0, nc,
                        valid, coef);
     CRK_LAUNCH_CHECK();
   }
@@ -282,7 +358,7 @@ void gcr_scalars(const double* sums3, const int* active, int nrhs, double* inv, 
 
 void gcr_update(int prec, void* z, void* w, void* x, void* r, const double* inv, const double2* a, const int* active,
                 const FieldShape& f, double* partial, double* rn2, hipStream_t st) {
-  const int64_t chunk = chunk_of(f.n), nch = (f.n + chunk - 1) / chunk;
+  const int64_t chunk = chunk_for_shape(f.n, f.es != 1), nch = shape_chunks(f);
   const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
   if (prec == CRK_FORM_FP64)
     hipLaunchKernelGGL(update_kernel<double2>, g, dim3(kT), 0, st, static_cast<double2*>(z), static_cast<double2*>(w),
@@ -298,8 +374,8 @@ void gcr_update(int prec, void* z, void* w, void* x, void* r, const double* inv,
 
 void gcr_check(const double* partial, const FieldShape& f, double tol2, const double* b2, const int* breakdown,
                int* active, int* iters, double* rn2, int* n_active, int* level_iters, hipStream_t st) {
-  const int64_t chunk = chunk_of(f.n), nch = (f.n + chunk - 1) / chunk;
-  hipLaunchKernelGGL(check_kernel, dim3(1), dim3(64), 0, st, partial, nch, f.nrhs, tol2, b2, breakdown, active, iters,
+  const int64_t nch = shape_chunks(f);
+  hipLaunchKernelGGL(check_kernel, dim3(1), dim3(kT), 0, st, partial, nch, f.nrhs, tol2, b2, breakdown, active, iters,
                      rn2, n_active, level_iters);
   CRK_LAUNCH_CHECK();
 }

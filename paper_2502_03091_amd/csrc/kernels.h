@@ -36,11 +36,10 @@ struct WilsonArgs {
   int nrhs;
   double diag;      // m0 + sum_mu w_mu
   double hw[4];     // -w_mu / 2
-  double* partial;  // optional [nblocks][nrhs][3]: <Dr, r> (re, im), <Dr, Dr>
+  double* partial;  // optional [V/64][nrhs][3]: <Dr, r> (re, im), <Dr, Dr> per 64 sites
   int rhs_per_thread;
   int order = 0;    // 0: RHS groups of a site block consecutive; 1: site blocks of a RHS group consecutive
   int swizzle = 1;  // XCD-contiguous workgroup mapping
-  int rhs_loop = 1; // FP32/FP16S: links in registers, loop over all RHS in the thread
 };
 void wilson_apply(const WilsonArgs& a, hipStream_t st);
 int64_t wilson_partial_blocks(int64_t V);

@@ -186,7 +186,7 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
   // ---- MR smoother on D psi ~ 0:  r = -D psi; repeat q = D r, alpha, psi += alpha r, r -= alpha q
   DevBuf r(esz * n * m), q(esz * n * m);
   const int64_t nsb = wilson_partial_blocks(V);
-  const int64_t ndp = rhs_dot_partials(n);
+  const int64_t ndp = rhs_dot_partials(n, inner);
   DevBuf partial(sizeof(double) * 3 * m * (nsb > ndp ? nsb : ndp));
   DevBuf sums(sizeof(double) * 3 * m), alpha(sizeof(double2) * m);
   level_apply(H, l, form, psi.p, r.p, m, st, nullptr, /*negate=*/true);

@@ -54,9 +54,9 @@ namespace {
 
 constexpr int kPollEvery = 4;
 
-int64_t partial_doubles(int64_t n, int nrhs) {
-  const int64_t a = gcr_partial_rows(n) * nrhs * 2 * kMaxBasis;
-  const int64_t b = rhs_dot_partials(n) * nrhs * 3;
+int64_t partial_doubles(int64_t n, int nrhs, bool inner) {
+  const int64_t a = gcr_partial_rows(n, inner) * nrhs * 2 * kMaxBasis;
+  const int64_t b = rhs_dot_partials(n, inner) * nrhs * 3;
   const int64_t c = wilson_partial_blocks(n / 12 + 1) * nrhs * 3;
   return std::max(a, std::max(b, c));
 }
@@ -185,7 +185,7 @@ std::unique_ptr<Workspace> make_workspace(Hierarchy* H, int cap, int form, const
   o.b.alloc(f64); o.x.alloc(f64); o.r.alloc(f64); o.tmp.alloc(f64);
   o.Z.alloc(f64 * nslots); o.W.alloc(f64 * nslots);
   o.mask.alloc(sizeof(int) * cap);
-  o.s.alloc(cap, partial_doubles(12 * V0, cap));
+  o.s.alloc(cap, partial_doubles(12 * V0, cap, false));
   // Slots may start at any ring position: every stored direction a slot's
   // kernels touch must hold finite values from the start.
   CRK_HIP(hipMemsetAsync(o.Z.p, 0, f64 * nslots, st));
@@ -208,7 +208,7 @@ std::unique_ptr<Workspace> make_workspace(Hierarchy* H, int cap, int form, const
     lw.x.alloc(cv); lw.r.alloc(cv); lw.b.alloc(cv);
     if (l < H->nlev - 1) { lw.rho.alloc(cv); lw.q.alloc(cv); w.bytes += 2 * cv; }
     lw.Z.alloc(cv * lw.maxit); lw.W.alloc(cv * lw.maxit);
-    lw.s.alloc(cap, partial_doubles(int64_t(H->N(l)) * H->V(l), cap));
+    lw.s.alloc(cap, partial_doubles(int64_t(H->N(l)) * H->V(l), cap, true));
     CRK_HIP(hipMemsetAsync(lw.s.level_iters, 0, sizeof(int) * cap, st));
     w.bytes += cv * (3 + 2 * size_t(lw.maxit));
   }

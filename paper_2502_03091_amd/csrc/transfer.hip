@@ -5,9 +5,8 @@
 //   (R v)(j)[alpha*k + i] = sum_{c', l} conj(P_{j,alpha}[i][c'*nb + l]) v(j*nb + l)[alpha*h + c']
 //   (P w)(j*nb + l)[alpha*h + c'] = sum_i P_{j,alpha}[i][c'*nb + l] w(j)[alpha*k + i]
 //
-// One workgroup per (block, chirality).  Restriction splits the block's rows
-// over 32 lanes and the k outputs over 8 lane groups, accumulating per-thread
-// tiles in registers and summing the row slices with cross-lane shuffles;
+// One workgroup per (block, chirality).  Restriction stages row chunks of P
+// and of the input in LDS and accumulates each output over the rows in order;
 // prolongation keeps the block's k x nrhs coarse values in LDS and lets each
 // thread produce one fine row for up to 16 right-hand sides, so every entry of
 // P is read from memory once per call (per 16 right-hand sides).  The fine side is addressed through
@@ -22,68 +21,59 @@ namespace {
 
 constexpr int kT = 256;
 
-// Restriction with register tiles: thread (i-group ig, row slice rs) accumulates
-// TI x RC outputs over rows rs, rs+32, ...; the 32 row slices of an i-group are
-// one half-wavefront and are summed with cross-lane shuffles.  P is read once,
-// coalesced along the rows; each input entry is read by the 8 i-groups from cache.
-template <class T, int TI, int RC>
-__global__ __launch_bounds__(kT) void restrict_tiled_kernel(TransferGeom g,
-                                                            const typename cplx_t<T>::type* __restrict__ P,
-                                                            const typename cplx_t<T>::type* __restrict__ v,
-                                                            typename cplx_t<T>::type* __restrict__ out, int nrhs) {
+// Restriction as a blocked product out = P_{j,alpha}^dag v over row chunks of
+// 64: the workgroup stages the chunk of P (k x 64) and of v (64 x 16 RHS) in
+// LDS with coalesced loads, then thread (i-pair, rhs) accumulates its two
+// outputs over the chunk.  Rows are summed in order (chunk by chunk), so every
+// output has one fixed summation order.
+constexpr int kRowChunk = 64;
+constexpr int kRhsChunk = 16;
+
+template <class T>
+__global__ __launch_bounds__(kT) void restrict_lds_kernel(TransferGeom g, const typename cplx_t<T>::type* __restrict__ P,
+                                                          const typename cplx_t<T>::type* __restrict__ v,
+                                                          typename cplx_t<T>::type* __restrict__ out, int nrhs) {
   using C = typename cplx_t<T>::type;
+  __shared__ C Ps[32][kRowChunk + 1];
+  __shared__ C Vs[kRowChunk][kRhsChunk];
   const int pair = blockIdx.x;
   const int64_t j = pair >> 1;
   const int alpha = pair & 1;
   const int nr = g.h * g.nb, k = g.k, N = 2 * k;
-  const int ig = threadIdx.x >> 5, rs = threadIdx.x & 31;
   const C* Pp = P + int64_t(pair) * k * nr;
   const int64_t jp = g.pos_c ? g.pos_c[j] : j;
-  for (int r0 = 0; r0 < nrhs; r0 += RC) {
-    C acc[TI][RC];
-#pragma unroll
-    for (int x = 0; x < TI; ++x)
-#pragma unroll
-      for (int q = 0; q < RC; ++q) acc[x][q] = C{0, 0};
-    for (int rho = rs; rho < nr; rho += 32) {
-      const int cp = rho / g.nb, l = rho % g.nb;
-      const int64_t site = j * g.nb + l;
-      C p[TI];
-#pragma unroll
-      for (int x = 0; x < TI; ++x) {
-        const int i = ig * TI + x;
-        p[x] = i < k ? Pp[int64_t(i) * nr + rho] : C{0, 0};
+  const int q = threadIdx.x % kRhsChunk, i0 = threadIdx.x / kRhsChunk, i1 = i0 + 16;
+  for (int r0 = 0; r0 < nrhs; r0 += kRhsChunk) {
+    C a0 = C{0, 0}, a1 = C{0, 0};
+    for (int c0 = 0; c0 < nr; c0 += kRowChunk) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < 32 * kRowChunk; e += kT) {
+        const int i = e / kRowChunk, rr = e % kRowChunk;
+        Ps[i][rr] = (i < k && c0 + rr < nr) ? Pp[int64_t(i) * nr + c0 + rr] : C{0, 0};
       }
-#pragma unroll
-      for (int q = 0; q < RC; ++q) {
-        if (r0 + q < nrhs) {
-          const int r = r0 + q;
-          const C val = v[g.aosoa ? aidx(r, alpha * g.h + cp, site, g.Vp, g.ncomp)
-                                  : int64_t(r) * g.vr + int64_t(alpha * g.h + cp) * g.vc + site * g.vs];
-#pragma unroll
-          for (int x = 0; x < TI; ++x) cfmac(acc[x][q], p[x], val);
+      for (int e = threadIdx.x; e < kRhsChunk * kRowChunk; e += kT) {
+        const int qq = e / kRowChunk, rr = e % kRowChunk, rho = c0 + rr;
+        C val = C{0, 0};
+        if (rho < nr && r0 + qq < nrhs) {
+          const int cp = rho / g.nb, l = rho % g.nb;
+          const int64_t site = j * g.nb + l;
+          const int r = r0 + qq;
+          val = v[g.aosoa ? aidx(r, alpha * g.h + cp, site, g.Vp, g.ncomp)
+                          : int64_t(r) * g.vr + int64_t(alpha * g.h + cp) * g.vc + site * g.vs];
         }
+        Vs[rr][qq] = val;
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int rr = 0; rr < kRowChunk; ++rr) {
+        const C x = Vs[rr][q];
+        cfmac(a0, Ps[i0][rr], x);
+        cfmac(a1, Ps[i1][rr], x);
       }
     }
-#pragma unroll
-    for (int x = 0; x < TI; ++x)
-#pragma unroll
-      for (int q = 0; q < RC; ++q) {
-#pragma unroll
-        for (int o = 16; o > 0; o >>= 1) {
-          acc[x][q].x += __shfl_xor(acc[x][q].x, o);
-          acc[x][q].y += __shfl_xor(acc[x][q].y, o);
-        }
-      }
-    if (rs == 0) {
-#pragma unroll
-      for (int x = 0; x < TI; ++x) {
-        const int i = ig * TI + x;
-        if (i >= k) continue;
-#pragma unroll
-        for (int q = 0; q < RC; ++q)
-          if (r0 + q < nrhs) out[(jp * N + alpha * k + i) * nrhs + r0 + q] = acc[x][q];
-      }
+    if (r0 + q < nrhs) {
+      if (i0 < k) out[(jp * N + alpha * k + i0) * nrhs + r0 + q] = a0;
+      if (i1 < k) out[(jp * N + alpha * k + i1) * nrhs + r0 + q] = a1;
     }
   }
 }
@@ -148,28 +138,12 @@ void transfer_restrict(int prec, const TransferGeom& g, const void* P, const voi
   if (nrhs <= 0) return;
   CRK_REQUIRE(g.k >= 1 && g.k <= 32, "restriction: k must be in [1, 32]");
   const dim3 grid = dim3(unsigned(2 * g.nblocks));
-  const int ti = (g.k + 7) / 8;
-#define CRK_RESTRICT(T, TI, RC)                                                                               \
-  hipLaunchKernelGGL((restrict_tiled_kernel<T, TI, RC>), grid, dim3(kT), 0, st, g,                            \
-                     static_cast<const typename cplx_t<T>::type*>(P),                                         \
-                     static_cast<const typename cplx_t<T>::type*>(fine),                                      \
-                     static_cast<typename cplx_t<T>::type*>(coarse), nrhs)
-  if (prec == CRK_FORM_FP64) {
-    switch (ti) {
-      case 1: CRK_RESTRICT(double, 1, 8); break;
-      case 2: CRK_RESTRICT(double, 2, 8); break;
-      case 3: CRK_RESTRICT(double, 3, 8); break;
-      default: CRK_RESTRICT(double, 4, 8); break;
-    }
-  } else {
-    switch (ti) {
-      case 1: CRK_RESTRICT(float, 1, 16); break;
-      case 2: CRK_RESTRICT(float, 2, 16); break;
-      case 3: CRK_RESTRICT(float, 3, 16); break;
-      default: CRK_RESTRICT(float, 4, 16); break;
-    }
-  }
-#undef CRK_RESTRICT
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(restrict_lds_kernel<double>, grid, dim3(kT), 0, st, g, static_cast<const double2*>(P),
+                       static_cast<const double2*>(fine), static_cast<double2*>(coarse), nrhs);
+  else
+    hipLaunchKernelGGL(restrict_lds_kernel<float>, grid, dim3(kT), 0, st, g, static_cast<const float2*>(P),
+                       static_cast<const float2*>(fine), static_cast<float2*>(coarse), nrhs);
   CRK_LAUNCH_CHECK();
 }
 
