@@ -64,6 +64,23 @@ def dslash_bytes(V, nrhs, form):
     return V * (2 * spinor * nrhs + link)
 
 
+def measured_traffic():
+    """HBM bytes per 48-RHS smoother launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE counters, or None when the kernel source changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "wilson_rhsloop_fp32_16x16x16x32_48rhs.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for name in ("dslash.hip", "field.h"):
+        with open(os.path.join(ROOT, "paper_2502_03091_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["kernel_source_sha256"] else None
+
+
 def cpu_baseline(U, m0, V):
     """Time the oracle (one thread) on a bounded sample of one setup and scale to a full setup."""
     from threadpoolctl import threadpool_limits
@@ -352,7 +369,7 @@ def workload_aniso16(crk, args):
         "roofline": {
             "kernel": "wilson_rhsloop_kernel<FP32> (48 RHS, 16^3x32, MR setup sweep)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
             "algorithmic_bytes_per_launch": alg,
         },
     }
@@ -371,7 +388,7 @@ def workload_aniso16(crk, args):
     lat.close()
     if not args.no_serve:
         hier, _ = serve_hierarchies(crk, SERVE_LATTICES[:1])
-        result["serving_16x32"] = serve_run(crk, hier, 20.0, 5.0, 100)
+        result["serving_16x32"] = serve_run(crk, hier, 2.0, 10.0, 40)
         for H in hier:
             H.close()
         log("serving", json.dumps(result["serving_16x32"]))

@@ -196,8 +196,11 @@ int64_t crk_mg_get_bytes(crk_mg_t mg, int32_t level, int32_t what);
  * inside the smoother, 5 number of those launches. */
 int crk_mg_get_timing(crk_mg_t mg, int32_t level, double* out6);
 
-/* Apply the coarse operator of level l (1..n_levels-1) in a form to host
- * complex128 coarse vectors [nrhs][Vc][2k]. */
+/* Apply the operator of level l in a form to host complex128 vectors
+ * [nrhs][V_l][N_l]: l = 1..n_levels-1 the Galerkin coarse operator (2k
+ * components per coarse site), l = 0 the fine Wilson operator through the
+ * hierarchy's own kernels and block-major site order (FP64 or FP32), i.e.
+ * the operator the smoother and the K-cycle apply. */
 int crk_mg_coarse_apply(crk_mg_t mg, int32_t level, int32_t form, const double* in, double* out,
                         int32_t nrhs);
 

@@ -293,8 +293,9 @@ int crk_mg_coarse_apply(crk_mg_t mg, int32_t level, int32_t form, const double* 
   crk_clear_error_();
   return guarded_mg([&] {
     Hierarchy* H = hier(mg);
-    check_level(H, level, 1, H->nlev - 1);
+    check_level(H, level, 0, H->nlev - 1);
     CRK_REQUIRE(form >= 0 && form <= 2, "unknown form");
+    CRK_REQUIRE(level > 0 || form != CRK_FORM_FP16S, "level 0 applies the fine operator in FP64 or FP32");
     CRK_REQUIRE(nrhs >= 1 && in && out, "bad arguments");
     const size_t vb = (form == CRK_FORM_FP64 ? 16 : 8) * size_t(H->V(level)) * H->N(level) * nrhs;
     DevBuf a(vb), b(vb);

@@ -118,3 +118,25 @@ def test_dslash_full_size_sampled_sites(crk, form):
     ref = op.apply_at(cols, sites)  # [sites, 12, nrhs]
     err = float(_rel(got[:, sites].transpose(1, 2, 0), ref))
     assert err <= TOL[form], err
+
+
+@pytest.mark.parametrize("dims", [[8, 8, 8, 8], [4, 8, 4, 8]])
+def test_hierarchy_fine_operator_4x4_blocks(crk, dims):
+    """The fine operator inside a hierarchy with 4^4 blocks (block-major site order,
+    the kernels the smoother and K-cycle use) against the oracle.  Extent 4 puts a
+    single block along that direction, so its neighbours wrap into the block."""
+    V = int(np.prod(dims))
+    U = synth.gauge_field(dims, 0.3, 1, config=12)
+    lat = crk.Lattice(dims, -0.2, 2.0)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[16], k=[8], block=[[4, 4, 4, 4]], n_smooth=[2], setup_form=crk.FORM_FP32)
+    op = WilsonOp(U, dims, -0.2, 2.0)
+    for nrhs in (1, 12):
+        psi = synth.gaussian_vectors(nrhs, V, 12, config=13, level=nrhs)
+        ref = as_fields(op.apply(as_columns(psi)))
+        for form, tol in ((crk.FORM_FP64, 1e-12), (crk.FORM_FP32, 2e-6)):
+            out = H.coarse_apply(0, psi, form=form)
+            err = np.abs(out - ref).max() / np.abs(ref).max()
+            print(dims, nrhs, form, err, flush=True)
+            assert err <= tol, (dims, nrhs, form, err)
+    H.close()
