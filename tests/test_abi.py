@@ -41,3 +41,34 @@ def test_version_and_error_string_without_gpu():
     lib = crk.lib()
     assert lib.crk_version() >= 10000
     assert isinstance(lib.crk_last_error(), bytes)
+
+
+def test_struct_defaults_without_gpu():
+    """Parameter defaults come from the library (no device call) and match the
+    documented values; the ctypes layouts agree with the C structs' field order."""
+    import paper_2502_03091_amd as crk
+    lib = crk.lib()
+    p = crk.MGParams()
+    lib.crk_mg_params_default(ctypes.byref(p))
+    assert p.n_levels == 2 and p.m_prime[0] == 48 and p.k[0] == 24 and list(p.block[0]) == [4, 4, 4, 4]
+    assert p.normalize == 1 and p.setup_form == crk.FORM_FP32
+    si = crk.SolveInfo()
+    lib.crk_solve_info_default(ctypes.byref(si))
+    assert si.tol == 1e-10 and si.max_iter == 200 and si.restart == 16 and si.form == crk.FORM_FP64
+    assert si.tau == 0.1 and si.inner_maxit == 20 and si.coarsest_maxit == 50 and si.nu_post == 4
+    sp = crk.ServerParams()
+    lib.crk_server_params_default(ctypes.byref(sp))
+    assert sp.slots_per_lane == 12 and sp.max_lanes == 4 and sp.idle_ms == 200 and sp.hbm_budget_bytes == 0
+    assert sp.solve.tol == 1e-10 and sp.solve.form == crk.FORM_FP32 and sp.solve.restart == 16
+
+
+def test_null_handles_fail_cleanly_without_gpu():
+    """Every entry point validates its handles before touching the device."""
+    import paper_2502_03091_amd as crk
+    lib = crk.lib()
+    assert lib.crk_mg_solve(None, None, None, 1, None) == crk.EINVAL
+    assert lib.crk_server_submit(None, 0, None, None, 1, None) == crk.EINVAL
+    assert lib.crk_server_wait(None, 1, 0.0, None) == crk.EINVAL
+    assert b"NULL" in lib.crk_last_error()
+    lib.crk_server_destroy(None)
+    lib.crk_mg_destroy(None)
