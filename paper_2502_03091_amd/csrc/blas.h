@@ -21,6 +21,10 @@ int64_t rhs_dot_partials(int64_t n, bool inner);
 void rhs_dot(int prec, const void* a, const void* b, int64_t n, int nrhs, int64_t rs, int64_t es, double* partial,
              double* out3, hipStream_t st);
 
+// Launch only the partial-sum pass of rhs_dot: partial[chunk][r][3]; returns the number of chunks.
+int64_t rhs_dot_launch(int prec, const void* a, const void* b, int64_t n, int nrhs, int64_t rs, int64_t es,
+                       double* partial, hipStream_t st);
+
 void reduce_partials(const double* partial, int64_t nchunk, int nrhs, int nv, double* out, hipStream_t st);
 
 // alpha[r] = <q,r>/<q,q> from sums3[r] = (Re<q,r>, Im<q,r>, <q,q>), 0 when <q,q> = 0.

@@ -172,6 +172,22 @@ int64_t rhs_dot_partials(int64_t n, bool inner) {
   return (n + c - 1) / c;
 }
 
+int64_t rhs_dot_launch(int prec, const void* a, const void* b, int64_t n, int nrhs, int64_t rs, int64_t es,
+                       double* partial, hipStream_t st) {
+  const int64_t chunk = es != 1 ? int64_t(kInnerChunk) : chunk_for(n);
+  const int64_t nch = (n + chunk - 1) / chunk;
+  if (nrhs <= 0 || n <= 0) return nch;
+  const dim3 g = dim3(unsigned(nch), unsigned(nrhs));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(dot_partial_kernel<double>, g, dim3(kT), 0, st, static_cast<const double2*>(a),
+                       static_cast<const double2*>(b), n, nrhs, rs, es, chunk, partial);
+  else
+    hipLaunchKernelGGL(dot_partial_kernel<float>, g, dim3(kT), 0, st, static_cast<const float2*>(a),
+                       static_cast<const float2*>(b), n, nrhs, rs, es, chunk, partial);
+  CRK_LAUNCH_CHECK();
+  return nch;
+}
+
 void rhs_dot(int prec, const void* a, const void* b, int64_t n, int nrhs, int64_t rs, int64_t es, double* partial,
              double* out3, hipStream_t st) {
   if (nrhs <= 0 || n <= 0) return;

@@ -14,7 +14,8 @@ void coarse_links_convert(const void* links64, int form, void* dst, int64_t Vc, 
 
 // out = (negate ? -1 : 1) * D_c in; fields rhs-inner [Vc][N][nrhs] complex (double2 for FP64,
 // float2 for FP32 and FP16S); nbr [8][Vc] device positions; N in {16, 32, 48, 64}.
+// copy (optional, same layout): receives a copy of in in the same launch.
 void coarse_apply(int form, int N, const void* links, const void* in, void* out, const int* nbr, int64_t Vc, int nrhs,
-                  bool negate, hipStream_t st);
+                  bool negate, hipStream_t st, void* copy = nullptr);
 
 }  // namespace crk

@@ -51,7 +51,8 @@ __global__ __launch_bounds__(64 * kLinkWaves) void coarse_mfma_kernel(const type
                                                                       const typename cplx_t<T>::type* __restrict__ in,
                                                                       typename cplx_t<T>::type* __restrict__ out,
                                                                       const int* __restrict__ nbr, int64_t Vc, int nrhs,
-                                                                      int ntiles, T sign) {
+                                                                      int ntiles, T sign,
+                                                                      typename cplx_t<T>::type* __restrict__ copy) {
   using C = typename cplx_t<T>::type;
   using A = typename Mfma<T>::acc;
   constexpr int N = 16 * MT;
@@ -89,6 +90,15 @@ __global__ __launch_bounds__(64 * kLinkWaves) void coarse_mfma_kernel(const type
   }
   __syncthreads();
   if (wv > 0 || !live) return;
+  if (copy) {  // copy of the input rows of this tile (lets a caller keep z = in without a copy launch)
+    const C* vin = in + j * int64_t(N) * nrhs + n;
+    C* vc = copy + j * int64_t(N) * nrhs + n;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = mt * 16 + kq * 4 + i;
+      vc[int64_t(row) * nrhs] = vin[int64_t(row) * nrhs];
+    }
+  }
 #pragma unroll
   for (int w = 0; w < kLinkWaves - 1; ++w)
 #pragma unroll
@@ -112,7 +122,7 @@ __global__ __launch_bounds__(64) void coarse_mfma_f16_kernel(const __half2* __re
                                                              const float* __restrict__ lscale,
                                                              const float2* __restrict__ in, float2* __restrict__ out,
                                                              const int* __restrict__ nbr, int64_t Vc, int nrhs,
-                                                             int ntiles, float sign) {
+                                                             int ntiles, float sign, float2* __restrict__ copy) {
   constexpr int N = 16 * MT;
   const int64_t j = blockIdx.x / ntiles;
   const int tile = blockIdx.x % ntiles;
@@ -172,6 +182,17 @@ __global__ __launch_bounds__(64) void coarse_mfma_f16_kernel(const __half2* __re
       for (int i = 0; i < 4; ++i) { tre[mt][i] += f * are[mt][i]; tim[mt][i] += f * aim[mt][i]; }
   }
   if (!live) return;
+  if (copy) {
+    const float2* vin = in + j * int64_t(N) * nrhs;
+    float2* vc = copy + j * int64_t(N) * nrhs;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = mt * 16 + kq * 4 + i;
+        vc[int64_t(row) * nrhs + n] = vin[int64_t(row) * nrhs + n];
+      }
+  }
   float2* ob = out + j * int64_t(N) * nrhs;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -211,7 +232,7 @@ __global__ __launch_bounds__(256) void links_to_f16_kernel(const double2* __rest
 
 template <class T>
 void launch_mfma(int N, const void* links, const void* in, void* out, const int* nbr, int64_t Vc, int nrhs, T sign,
-                 hipStream_t st) {
+                 void* copy, hipStream_t st) {
   using C = typename cplx_t<T>::type;
   CRK_REQUIRE(N % 16 == 0 && N >= 16 && N <= 64, "coarse operator: 2k must be 16, 32, 48 or 64");
   const int ntiles = (nrhs + 15) / 16;
@@ -220,28 +241,30 @@ void launch_mfma(int N, const void* links, const void* in, void* out, const int*
   const C* L = static_cast<const C*>(links);
   const C* x = static_cast<const C*>(in);
   C* y = static_cast<C*>(out);
+  C* cp = static_cast<C*>(copy);
   switch (N / 16) {
-    case 1: hipLaunchKernelGGL((coarse_mfma_kernel<T, 1>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
-    case 2: hipLaunchKernelGGL((coarse_mfma_kernel<T, 2>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
-    case 3: hipLaunchKernelGGL((coarse_mfma_kernel<T, 3>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
-    default: hipLaunchKernelGGL((coarse_mfma_kernel<T, 4>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign); break;
+    case 1: hipLaunchKernelGGL((coarse_mfma_kernel<T, 1>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
+    case 2: hipLaunchKernelGGL((coarse_mfma_kernel<T, 2>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
+    case 3: hipLaunchKernelGGL((coarse_mfma_kernel<T, 3>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
+    default: hipLaunchKernelGGL((coarse_mfma_kernel<T, 4>), g, b, 0, st, L, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
   }
   CRK_LAUNCH_CHECK();
 }
 
 void launch_f16(int N, const void* links, const void* in, void* out, const int* nbr, int64_t Vc, int nrhs, float sign,
-                hipStream_t st) {
+                void* copy, hipStream_t st) {
   const int ntiles = (nrhs + 15) / 16;
   const dim3 g = dim3(unsigned(Vc * ntiles));
   const __half2* L = static_cast<const __half2*>(links);
   const float* ls = reinterpret_cast<const float*>(L + Vc * 9 * int64_t(N) * N);
   const float2* x = static_cast<const float2*>(in);
   float2* y = static_cast<float2*>(out);
+  float2* cp = static_cast<float2*>(copy);
   switch (N / 16) {
-    case 1: hipLaunchKernelGGL((coarse_mfma_f16_kernel<1>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign); break;
-    case 2: hipLaunchKernelGGL((coarse_mfma_f16_kernel<2>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign); break;
-    case 3: hipLaunchKernelGGL((coarse_mfma_f16_kernel<3>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign); break;
-    case 4: hipLaunchKernelGGL((coarse_mfma_f16_kernel<4>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign); break;
+    case 1: hipLaunchKernelGGL((coarse_mfma_f16_kernel<1>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
+    case 2: hipLaunchKernelGGL((coarse_mfma_f16_kernel<2>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
+    case 3: hipLaunchKernelGGL((coarse_mfma_f16_kernel<3>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
+    case 4: hipLaunchKernelGGL((coarse_mfma_f16_kernel<4>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
     default: fail(CRK_EINVAL, "coarse operator: 2k must be 16, 32, 48 or 64");
   }
   CRK_LAUNCH_CHECK();
@@ -273,12 +296,12 @@ void coarse_links_convert(const void* links64, int form, void* dst, int64_t Vc, 
 }
 
 void coarse_apply(int form, int N, const void* links, const void* in, void* out, const int* nbr, int64_t Vc, int nrhs,
-                  bool negate, hipStream_t st) {
+                  bool negate, hipStream_t st, void* copy) {
   if (nrhs <= 0 || Vc <= 0) return;
-  CRK_REQUIRE(in != out, "coarse apply: in and out must not alias");
-  if (form == CRK_FORM_FP64) launch_mfma<double>(N, links, in, out, nbr, Vc, nrhs, negate ? -1.0 : 1.0, st);
-  else if (form == CRK_FORM_FP32) launch_mfma<float>(N, links, in, out, nbr, Vc, nrhs, negate ? -1.f : 1.f, st);
-  else launch_f16(N, links, in, out, nbr, Vc, nrhs, negate ? -1.f : 1.f, st);
+  CRK_REQUIRE(in != out && copy != out && copy != in, "coarse apply: in, out and copy must not alias");
+  if (form == CRK_FORM_FP64) launch_mfma<double>(N, links, in, out, nbr, Vc, nrhs, negate ? -1.0 : 1.0, copy, st);
+  else if (form == CRK_FORM_FP32) launch_mfma<float>(N, links, in, out, nbr, Vc, nrhs, negate ? -1.f : 1.f, copy, st);
+  else launch_f16(N, links, in, out, nbr, Vc, nrhs, negate ? -1.f : 1.f, copy, st);
 }
 
 }  // namespace crk

@@ -33,6 +33,11 @@ void gcr_scalars(const double* sums3, const int* active, int nrhs, double* inv, 
                  hipStream_t st);
 void gcr_update(int prec, void* z, void* w, void* x, void* r, const double* inv, const double2* a, const int* active,
                 const FieldShape& f, double* partial, double* rn2, hipStream_t st);
+// gcr_scalars + gcr_update in one launch, the <w, r>, ||w||^2 partials (dpart,
+// dnch chunks, from rhs_dot_launch) reduced inside every workgroup.
+void gcr_update_fused(int prec, void* z, void* w, void* x, void* r, const double* dpart, int64_t dnch,
+                      const int* active, int* breakdown, const FieldShape& f, double* partial, double* rn2,
+                      hipStream_t st);
 void gcr_check(const double* partial, const FieldShape& f, double tol2, const double* b2, const int* breakdown,
                int* active, int* iters, double* rn2, int* n_active, int* level_iters, hipStream_t st);
 void gcr_start(const double* sums3, int nrhs, double* b2, int* active, int* iters, int* n_active, hipStream_t st);

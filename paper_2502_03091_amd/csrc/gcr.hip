@@ -210,6 +210,71 @@ __global__ __launch_bounds__(kT) void update_kernel(C* __restrict__ z, C* __rest
   if (threadIdx.x == 0) partial[int64_t(blockIdx.x) * nrhs + r] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// update with the scalars computed in place: every workgroup of RHS r first adds
+// the <w, r>, ||w||^2 partials of its RHS (lane l takes chunks l, l + 64, ... in
+// order, then a fixed shuffle tree; the same in every workgroup) and derives
+// inv = 1/||w|| and a = <w, r>/||w||, which saves the reduction and scalar launches.
+template <class C>
+__global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ z, C* __restrict__ w, C* __restrict__ x,
+                                                          C* __restrict__ res, const double* __restrict__ dpart,
+                                                          int64_t dnch, const int* __restrict__ active,
+                                                          int* __restrict__ breakdown, int64_t n, int nrhs,
+                                                          int64_t rs, int64_t es, int64_t chunk,
+                                                          double* __restrict__ partial) {
+  __shared__ double sh[4];
+  __shared__ double scal[3];
+  using T = decltype(C::x);
+  const int r = blockIdx.y;
+  if (threadIdx.x < 64) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int64_t c = threadIdx.x; c < dnch; c += 64) {
+      const double* p = dpart + (c * nrhs + r) * 3;
+      s0 += p[0];
+      s1 += p[1];
+      s2 += p[2];
+    }
+    s0 = wsum(s0);
+    s1 = wsum(s1);
+    s2 = wsum(s2);
+    if (threadIdx.x == 0) {
+      scal[0] = s0;
+      scal[1] = s1;
+      scal[2] = s2;
+    }
+  }
+  __syncthreads();
+  const double ww = scal[2], nw = sqrt(ww);
+  const bool act0 = active[r] != 0;
+  const bool ok = act0 && ww > 0.0 && isfinite(nw);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && breakdown) breakdown[r] = act0 && !ok;
+  const T s = T(ok ? 1.0 / nw : 0.0);
+  const bool act = ok;
+  const C ar = ok ? mk<C>(T(scal[0] / nw), T(scal[1] / nw)) : mk<C>(T(0), T(0));
+  const int64_t e0 = int64_t(blockIdx.x) * chunk, e1 = min(n, e0 + chunk);
+  double acc = 0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int64_t idx = int64_t(r) * rs + e * es;
+    const C zn = cscale(z[idx], s), wn = cscale(w[idx], s);
+    z[idx] = zn;
+    w[idx] = wn;
+    C rr = res[idx];
+    if (act) {
+      C xx = x[idx];
+      cfma(xx, ar, zn);
+      x[idx] = xx;
+      const C aw = cmul(ar, wn);
+      rr.x -= aw.x;
+      rr.y -= aw.y;
+      res[idx] = rr;
+    }
+    acc += double(rr.x) * rr.x + double(rr.y) * rr.y;
+  }
+  const double t = wsum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[int64_t(blockIdx.x) * nrhs + r] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
 // rn2[r] = sum of partials (wavefront g adds chunks g, g + 4, ... in order, then
 // the four sums in a fixed order); convergence bookkeeping of an inner solve.
 __global__ __launch_bounds__(kT) void check_kernel(const double* __restrict__ partial, int64_t nch, int nrhs,
@@ -368,6 +433,23 @@ void gcr_update(int prec, void* z, void* w, void* x, void* r, const double* inv,
     hipLaunchKernelGGL(update_kernel<float2>, g, dim3(kT), 0, st, static_cast<float2*>(z), static_cast<float2*>(w),
                        static_cast<float2*>(x), static_cast<float2*>(r), inv, a, active, f.n, f.nrhs, f.rs, f.es,
                        chunk, partial);
+  CRK_LAUNCH_CHECK();
+  if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
+}
+
+void gcr_update_fused(int prec, void* z, void* w, void* x, void* r, const double* dpart, int64_t dnch,
+                      const int* active, int* breakdown, const FieldShape& f, double* partial, double* rn2,
+                      hipStream_t st) {
+  const int64_t chunk = chunk_for_shape(f.n, f.es != 1), nch = shape_chunks(f);
+  const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(update_fused_kernel<double2>, g, dim3(kT), 0, st, static_cast<double2*>(z),
+                       static_cast<double2*>(w), static_cast<double2*>(x), static_cast<double2*>(r), dpart, dnch,
+                       active, breakdown, f.n, f.nrhs, f.rs, f.es, chunk, partial);
+  else
+    hipLaunchKernelGGL(update_fused_kernel<float2>, g, dim3(kT), 0, st, static_cast<float2*>(z),
+                       static_cast<float2*>(w), static_cast<float2*>(x), static_cast<float2*>(r), dpart, dnch, active,
+                       breakdown, f.n, f.nrhs, f.rs, f.es, chunk, partial);
   CRK_LAUNCH_CHECK();
   if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
 }

@@ -78,7 +78,7 @@ void mg_destroy(Hierarchy* H);   // drops one reference; frees at zero
 
 // Operators used by setup and solver (device fields in level layout, stream ordered).
 void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int nrhs, hipStream_t st,
-                 double* partial = nullptr, bool negate = false);
+                 double* partial = nullptr, bool negate = false, void* copy = nullptr);
 void level_restrict(Hierarchy* H, int l, int form, const void* fine, void* coarse, int nrhs, hipStream_t st);
 void level_prolong(Hierarchy* H, int l, int form, const void* coarse, void* fine, int nrhs, bool add, hipStream_t st);
 

@@ -71,8 +71,9 @@ void validate(const Lattice* L, const crk_mg_params& p) {
 
 // ------------------------------------------------------------------ level operators
 void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int nrhs, hipStream_t st, double* partial,
-                 bool negate) {
+                 bool negate, void* copy) {
   if (l == 0) {
+    CRK_REQUIRE(copy == nullptr, "the fine operator has no fused copy");
     Lattice* L = H->lat;
     WilsonArgs a{};
     a.form = form;
@@ -92,7 +93,7 @@ void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int n
   } else {
     const CoarseLevel& c = H->coarse[l - 1];
     CRK_REQUIRE(partial == nullptr, "coarse apply has no fused reduction");
-    coarse_apply(form, c.N, c.links[form].p, in, out, c.geo.nbr.as<int>(), c.V, nrhs, negate, st);
+    coarse_apply(form, c.N, c.links[form].p, in, out, c.geo.nbr.as<int>(), c.V, nrhs, negate, st, copy);
   }
 }
 

@@ -22,7 +22,7 @@ namespace crk {
 // Device scalars of one GCR instance.
 struct GcrScalars {
   DevBuf buf;
-  double *sums3, *b2, *rn2, *inv, *partial;
+  double *sums3, *b2, *rn2, *inv, *partial, *dpart;
   double2 *a, *coef;
   int *active, *iters, *breakdown, *n_active, *level_iters;
   uint32_t* valid;

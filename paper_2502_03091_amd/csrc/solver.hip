@@ -32,7 +32,8 @@ void GcrScalars::alloc(int nrhs, int64_t partial_doubles) {
                o_a = take(sizeof(double2) * nr), o_coef = take(sizeof(double2) * nr * kMaxCoef),
                o_act = take(sizeof(int) * nr), o_it = take(sizeof(int) * nr), o_bd = take(sizeof(int) * nr),
                o_na = take(sizeof(int)), o_li = take(sizeof(int) * nr), o_val = take(sizeof(uint32_t) * nr),
-               o_part = take(sizeof(double) * size_t(partial_doubles));
+               o_part = take(sizeof(double) * size_t(partial_doubles)),
+               o_dpart = take(sizeof(double) * size_t(partial_doubles));
   buf.alloc(off);
   char* c = static_cast<char*>(buf.p);
   sums3 = reinterpret_cast<double*>(c + o_s3);
@@ -48,6 +49,7 @@ void GcrScalars::alloc(int nrhs, int64_t partial_doubles) {
   level_iters = reinterpret_cast<int*>(c + o_li);
   valid = reinterpret_cast<uint32_t*>(c + o_val);
   partial = reinterpret_cast<double*>(c + o_part);
+  dpart = reinterpret_cast<double*>(c + o_dpart);
 }
 
 namespace {
@@ -94,16 +96,19 @@ void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int 
   for (int i = 0; i < lw.maxit; ++i) {
     void* zi = Z + fb * i;
     void* wi = W + fb * i;
-    if (precond) kcycle(H, w, l, p, nrhs, lw.r.p, zi, st);
-    else CRK_HIP(hipMemcpyAsync(zi, lw.r.p, fb, hipMemcpyDeviceToDevice, st));
-    level_apply(H, l, form, zi, wi, nrhs, st);
+    if (precond) {
+      kcycle(H, w, l, p, nrhs, lw.r.p, zi, st);
+      level_apply(H, l, form, zi, wi, nrhs, st);
+    } else {
+      // unpreconditioned: z_i = r, stored by the operator launch that computes w_i = D r
+      level_apply(H, l, form, lw.r.p, wi, nrhs, st, nullptr, false, zi);
+    }
     if (i > 0) {
       gcr_multidot(prec, W, fs, i, wi, f, s.partial, nullptr, s.coef, st);
       gcr_multiaxpy(prec, Z, W, fs, i, 0, zi, wi, s.coef, f, st);
     }
-    rhs_dot(prec, wi, lw.r.p, f.n, nrhs, f.rs, f.es, s.partial, s.sums3, st);
-    gcr_scalars(s.sums3, s.active, nrhs, s.inv, s.a, s.breakdown, st);
-    gcr_update(prec, zi, wi, lw.x.p, lw.r.p, s.inv, s.a, s.active, f, s.partial, nullptr, st);
+    const int64_t dn = rhs_dot_launch(prec, wi, lw.r.p, f.n, nrhs, f.rs, f.es, s.dpart, st);
+    gcr_update_fused(prec, zi, wi, lw.x.p, lw.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, nullptr, st);
     gcr_check(s.partial, f, tol2, s.b2, s.breakdown, s.active, s.iters, s.rn2, s.n_active, s.level_iters, st);
     // Converged RHS are frozen on the device; the host only polls every few
     // iterations to stop launching once every RHS is done.
@@ -330,9 +335,9 @@ int OuterSolver::step() {
     gcr_multiaxpy(CRK_FORM_FP64, Z, W, fcap, used_, (ring_ + 1) % used_, zi, wi, s.coef, f, st_);
     CRK_HIP(hipStreamSynchronize(st_));  // valid lives on the host stack
   }
-  rhs_dot(CRK_FORM_FP64, wi, o.r.p, f.n, wd, f.rs, f.es, s.partial, s.sums3, st_);
-  gcr_scalars(s.sums3, s.active, wd, s.inv, s.a, s.breakdown, st_);
-  gcr_update(CRK_FORM_FP64, zi, wi, o.x.p, o.r.p, s.inv, s.a, s.active, f, s.partial, s.rn2, st_);
+  const int64_t dn = rhs_dot_launch(CRK_FORM_FP64, wi, o.r.p, f.n, wd, f.rs, f.es, s.dpart, st_);
+  gcr_update_fused(CRK_FORM_FP64, zi, wi, o.x.p, o.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, s.rn2,
+                   st_);
   std::vector<double> rn2(wd);
   std::vector<int> bd(wd);
   CRK_HIP(hipMemcpyAsync(rn2.data(), s.rn2, sizeof(double) * wd, hipMemcpyDeviceToHost, st_));
