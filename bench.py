@@ -249,10 +249,11 @@ def workload_volume(crk, args):
     rows = []
     for dims in ([24, 24, 24, 48], [32, 32, 32, 64], [48, 48, 48, 96]):
         V = int(np.prod(dims))
-        U = synth.gauge_field(dims, ISO["eps"], ISO["n_ape"], config=ISO["config"])
+        U = synth.gauge_field_device(dims, ISO["eps"], ISO["n_ape"], config=ISO["config"], progress=log)
         lat = crk.Lattice(dims, m0, ISO["xi"])
         lat.load_gauge(U)
         del U
+        torch.cuda.empty_cache()
         b = torch.from_numpy(synth.gaussian_rhs(1, V, config=ISO["config"]).view(np.float64)).to(dev)
         x = torch.empty_like(b)
         for name, mp, k in (("rank_k", [64, 48], [24, 32]), ("conventional", [24, 32], [24, 32])):

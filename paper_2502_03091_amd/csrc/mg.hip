@@ -220,6 +220,11 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
     }
   }
   for (auto& e : dev_ev) (void)hipEventDestroy(e);
+  // the smoother's residual fields are as large as the test vectors: give them
+  // back before the SVD and Galerkin stages allocate P and the coarse links
+  CRK_HIP(hipStreamSynchronize(st));
+  r.release();
+  q.release();
   tm.dslash_count = inner ? 0 : p.n_smooth[l];
   tm.dslash_avg = p.n_smooth[l] > 0 && !inner ? dsum / p.n_smooth[l] : 0;
 
