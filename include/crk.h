@@ -129,6 +129,10 @@ typedef struct {
   int32_t normalize;                   /* 1: psi_i <- psi_i/||psi_i|| before the SVD */
   uint64_t seed;                       /* device random vectors when init_vectors is NULL */
   const double* init_vectors[CRK_MAX_LEVELS]; /* optional host complex128 [m'][V_l][N_l] */
+  int32_t smooth_chunk;                /* fine-level smoother: vectors per launch, 0 = all m' unless
+                                          device memory is short (then halved until r, q fit) */
+  int32_t svd_batch;                   /* blocks per SVD batch, 0 = all unless the work space would
+                                          exceed a quarter of the free device memory */
 } crk_mg_params;
 
 /* Fill p with defaults (two levels, m'=48, k=24, 4^4 blocks, 20 sweeps, FP32 smoother). */

@@ -50,6 +50,8 @@ class MGParams(C.Structure):
         ("normalize", C.c_int32),
         ("seed", C.c_uint64),
         ("init_vectors", C.c_void_p * MAX_LEVELS),
+        ("smooth_chunk", C.c_int32),
+        ("svd_batch", C.c_int32),
     ]
 
 
@@ -301,7 +303,8 @@ class Hierarchy:
     """Chiral rank-k multigrid hierarchy built on a Lattice (crk_mg_setup)."""
 
     def __init__(self, lattice, m_prime=(48,), k=(24,), block=((4, 4, 4, 4),), n_smooth=(20,),
-                 setup_form=FORM_FP32, normalize=True, seed=0x2502030910, init_vectors=None):
+                 setup_form=FORM_FP32, normalize=True, seed=0x2502030910, init_vectors=None, smooth_chunk=0,
+                 svd_batch=0):
         self.lattice = lattice
         p = MGParams()
         _load().crk_mg_params_default(C.byref(p))
@@ -316,6 +319,8 @@ class Hierarchy:
         p.setup_form = int(setup_form)
         p.normalize = int(bool(normalize))
         p.seed = int(seed)
+        p.smooth_chunk = int(smooth_chunk)
+        p.svd_batch = int(svd_batch)
         keep = []
         if init_vectors is not None:
             for l, v in enumerate(init_vectors):

@@ -25,13 +25,18 @@ struct Error : std::runtime_error {
 
 [[noreturn]] inline void fail(int code, const std::string& msg) { throw Error(code, msg); }
 
+// On failure the runtime's sticky last error is read back (cleared) so that a
+// handled error (e.g. an allocation that did not fit) is not reported again by
+// the next launch check.
 #define CRK_HIP(call)                                                                       \
   do {                                                                                      \
     hipError_t e_ = (call);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
+    if (e_ != hipSuccess) {                                                                 \
+      (void)hipGetLastError();                                                              \
       ::crk::fail(e_ == hipErrorOutOfMemory ? CRK_ENOMEM : CRK_EHIP,                        \
                   std::string(#call) + ": " + hipGetErrorString(e_) + " (" __FILE__ ":" +   \
                       std::to_string(__LINE__) + ")");                                      \
+    }                                                                                       \
   } while (0)
 
 #define CRK_REQUIRE(cond, msg)                                  \

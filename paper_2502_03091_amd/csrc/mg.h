@@ -43,6 +43,7 @@ struct Transfer {            // between level l and l+1
 
 struct StageTiming {
   double total = 0, smoother = 0, svd = 0, galerkin = 0, dslash_avg = 0, dslash_count = 0;
+  int smoother_chunk = 0;  // vectors per smoother launch (all m' unless memory forced chunks)
 };
 
 struct Workspace;  // solver buffers (solver.cpp)

@@ -41,6 +41,7 @@ int64_t prod4(const int d[4]) { return int64_t(d[0]) * d[1] * d[2] * d[3]; }
 void validate(const Lattice* L, const crk_mg_params& p) {
   CRK_REQUIRE(p.n_levels == 2 || p.n_levels == 3, "n_levels must be 2 or 3");
   CRK_REQUIRE(p.setup_form == CRK_FORM_FP64 || p.setup_form == CRK_FORM_FP32, "setup_form must be FP64 or FP32");
+  CRK_REQUIRE(p.smooth_chunk >= 0 && p.svd_batch >= 0, "smooth_chunk and svd_batch must be >= 0");
   CRK_REQUIRE(L->V % kVL == 0, "the fine lattice volume must be a multiple of 64 for a hierarchy");
   int dims[4];
   std::memcpy(dims, L->dims, sizeof(dims));
@@ -185,37 +186,55 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
   }
 
   // ---- MR smoother on D psi ~ 0:  r = -D psi; repeat q = D r, alpha, psi += alpha r, r -= alpha q
-  DevBuf r(esz * n * m), q(esz * n * m);
+  // Every vector runs its own recursion, so on the fine level (rhs-outer
+  // layout) the vectors may be smoothed in chunks: when the residual fields r
+  // and q of all m' vectors would not fit comfortably next to them, the chunk
+  // is halved until they do.
+  int mc = m;
+  if (!inner && p.smooth_chunk > 0) {
+    mc = std::min(m, int(p.smooth_chunk));
+  } else if (!inner) {
+    size_t fr = 0, tot = 0;
+    CRK_HIP(hipMemGetInfo(&fr, &tot));
+    while (mc > 8 && 2 * esz * size_t(n) * size_t(mc) > fr / 10 * 6) mc = (mc + 1) / 2;
+  }
+  const int nchunk = (m + mc - 1) / mc;
+  DevBuf r(esz * n * mc), q(esz * n * mc);
   const int64_t nsb = wilson_partial_blocks(V);
   const int64_t ndp = rhs_dot_partials(n, inner);
-  DevBuf partial(sizeof(double) * 3 * m * (nsb > ndp ? nsb : ndp));
-  DevBuf sums(sizeof(double) * 3 * m), alpha(sizeof(double2) * m);
-  level_apply(H, l, form, psi.p, r.p, m, st, nullptr, /*negate=*/true);
-  const int64_t rs = inner ? 1 : n, es = inner ? m : 1;
+  DevBuf partial(sizeof(double) * 3 * mc * (nsb > ndp ? nsb : ndp));
+  DevBuf sums(sizeof(double) * 3 * mc), alpha(sizeof(double2) * mc);
   // events around every fine operator launch; read once after the stage
-  std::vector<hipEvent_t> dev_ev(inner ? 0 : 2 * size_t(p.n_smooth[l]));
+  std::vector<hipEvent_t> dev_ev(inner ? 0 : 2 * size_t(p.n_smooth[l]) * nchunk);
   for (auto& e : dev_ev) CRK_HIP(hipEventCreate(&e));
-  for (int it = 0; it < p.n_smooth[l]; ++it) {
-    if (!inner) {
-      CRK_HIP(hipEventRecord(dev_ev[2 * it], st));
-      level_apply(H, l, form, r.p, q.p, m, st, partial.as<double>());
-      CRK_HIP(hipEventRecord(dev_ev[2 * it + 1], st));
-      reduce_partials(partial.as<double>(), nsb, m, 3, sums.as<double>(), st);
-    } else {
-      level_apply(H, l, form, r.p, q.p, m, st);
-      // sums = (<q, r>, <q, q>)
-      rhs_dot(form, q.p, r.p, n, m, rs, es, partial.as<double>(), sums.as<double>(), st);
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int c0 = ch * mc, mm = std::min(mc, m - c0);
+    void* pc = static_cast<char*>(psi.p) + esz * size_t(n) * c0;  // rhs-outer: vectors c0 .. c0+mm-1
+    const int64_t rs = inner ? 1 : n, es = inner ? mm : 1;
+    level_apply(H, l, form, pc, r.p, mm, st, nullptr, /*negate=*/true);
+    for (int it = 0; it < p.n_smooth[l]; ++it) {
+      if (!inner) {
+        hipEvent_t* e = dev_ev.data() + 2 * (size_t(ch) * p.n_smooth[l] + it);
+        CRK_HIP(hipEventRecord(e[0], st));
+        level_apply(H, l, form, r.p, q.p, mm, st, partial.as<double>());
+        CRK_HIP(hipEventRecord(e[1], st));
+        reduce_partials(partial.as<double>(), nsb, mm, 3, sums.as<double>(), st);
+      } else {
+        level_apply(H, l, form, r.p, q.p, mm, st);
+        // sums = (<q, r>, <q, q>)
+        rhs_dot(form, q.p, r.p, n, mm, rs, es, partial.as<double>(), sums.as<double>(), st);
+      }
+      mr_alpha(sums.as<double>(), mm, alpha.as<double2>(), st);
+      mr_update(form, pc, r.p, q.p, alpha.as<double2>(), n, mm, inner, st);
     }
-    mr_alpha(sums.as<double>(), m, alpha.as<double2>(), st);
-    mr_update(form, psi.p, r.p, q.p, alpha.as<double2>(), n, m, inner, st);
   }
   ev.mark(1, st);
   double dsum = 0;
   if (!dev_ev.empty()) {
     CRK_HIP(hipEventSynchronize(dev_ev.back()));
-    for (int it = 0; it < p.n_smooth[l]; ++it) {
+    for (size_t i = 0; i < dev_ev.size(); i += 2) {
       float ms = 0;
-      CRK_HIP(hipEventElapsedTime(&ms, dev_ev[2 * it], dev_ev[2 * it + 1]));
+      CRK_HIP(hipEventElapsedTime(&ms, dev_ev[i], dev_ev[i + 1]));
       dsum += ms * 1e-3;
     }
   }
@@ -225,8 +244,11 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
   CRK_HIP(hipStreamSynchronize(st));
   r.release();
   q.release();
-  tm.dslash_count = inner ? 0 : p.n_smooth[l];
-  tm.dslash_avg = p.n_smooth[l] > 0 && !inner ? dsum / p.n_smooth[l] : 0;
+  const int launches = inner ? 0 : p.n_smooth[l] * nchunk;
+  tm.dslash_count = launches;
+  tm.dslash_avg = launches > 0 ? dsum / launches : 0;
+  tm.smoother_chunk = mc;
+  const int64_t rs = inner ? 1 : n, es = inner ? m : 1;
 
   // ---- normalisation factors 1/||psi_i||
   DevBuf& inv = H->inv_norm[l];
@@ -248,13 +270,25 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
   src.nb = t.nb;
   src.m = m;
   src.nblocks = t.nblocks;
-  DevBuf work(svd_work_bytes(m, t.nr, t.nblocks));
-  SvdWork w = svd_work_carve(work.p, m, t.nr, t.nblocks);
+  // SVD work space (Gram matrices, rotations and B = A V per block): in
+  // batches of blocks when all blocks at once would not fit in a quarter of
+  // the free device memory
+  int64_t wcap = t.nblocks;
+  {
+    size_t fr = 0, tot = 0;
+    CRK_HIP(hipMemGetInfo(&fr, &tot));
+    const size_t per = svd_work_bytes(m, t.nr, 1);
+    const int64_t fit = int64_t(fr / 4 / per);
+    if (fit < wcap) wcap = std::max<int64_t>(1, fit);
+    if (p.svd_batch > 0) wcap = std::min<int64_t>(t.nblocks, p.svd_batch);
+  }
+  DevBuf work(svd_work_bytes(m, t.nr, wcap));
+  SvdWork w = svd_work_carve(work.p, m, t.nr, wcap);
   t.P64.alloc(sizeof(double2) * 2 * t.nblocks * t.k * t.nr);
   t.P32.alloc(sizeof(float2) * 2 * t.nblocks * t.k * t.nr);
   t.nsig = m < t.nr ? m : t.nr;
   t.sigma.alloc(sizeof(double) * 2 * t.nblocks * t.nsig);
-  chiral_svd(src, form == CRK_FORM_FP64, psi.p, inv.as<double>(), t.k, w, t.P64.as<double2>(),
+  chiral_svd(src, form == CRK_FORM_FP64, psi.p, inv.as<double>(), t.k, w, wcap, t.P64.as<double2>(),
              t.sigma.as<double>(), st);
   field_convert(CRK_FORM_FP64, t.P64.p, CRK_FORM_FP32, t.P32.p, 2 * t.nblocks * t.k * t.nr, 1, 1, st);
   ev.mark(2, st);

@@ -17,6 +17,7 @@ struct ChiralSrc {
   int nb;       // sites per block
   int m;        // columns (test vectors)
   int64_t nblocks;
+  int64_t j0 = 0;  // first block of the batch the kernels process (set by chiral_svd)
 };
 
 struct SvdWork {
@@ -30,7 +31,8 @@ SvdWork svd_work_carve(void* p, int m, int nr, int64_t nblocks);
 
 // P: [2*nblocks][k][N_r] complex128 (pair = 2j + alpha, row rho = c'*nb + l);
 // sigma: [2*nblocks][min(m, N_r)].  inv_norm (optional): per-column scale.
+// w holds work space for wcap blocks; the blocks are processed in batches of wcap.
 void chiral_svd(const ChiralSrc& s, int src_is_double, const void* base, const double* inv_norm, int k,
-                const SvdWork& w, double2* P, double* sigma, hipStream_t st);
+                const SvdWork& w, int64_t wcap, double2* P, double* sigma, hipStream_t st);
 
 }  // namespace crk

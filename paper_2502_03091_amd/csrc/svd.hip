@@ -20,6 +20,8 @@
 //
 // Row order inside a block on the device: rho = c'*|Lambda| + l (component c'
 // of the chirality, local site l), which is contiguous in the field layouts.
+#include <algorithm>
+
 #include "field.h"
 #include "kernels.h"
 #include "svd.h"
@@ -38,7 +40,7 @@ __device__ __forceinline__ double2 ld2(const T2* p, int64_t i) {
 
 // Load rows [r0, r0+nrows) of the scaled block matrix into lds[row][col] (ld = m).
 template <class T2>
-__device__ void load_block_rows(const ChiralSrc& src, const T2* base, const double* inv_norm, int j, int alpha,
+__device__ void load_block_rows(const ChiralSrc& src, const T2* base, const double* inv_norm, int64_t j, int alpha,
                                 int r0, int nrows, int m, double2* lds, int ldm) {
   const int total = nrows * m;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
@@ -93,7 +95,8 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(ChiralSrc src, const T2*
                                                         const double* __restrict__ inv_norm,
                                                         double2* __restrict__ G) {
   extern __shared__ double2 lds[];
-  const int pair = blockIdx.x, j = pair >> 1, alpha = pair & 1;
+  const int pair = blockIdx.x, alpha = pair & 1;
+  const int64_t j = src.j0 + (pair >> 1);
   const int m = src.m, nr = src.h * src.nb;
   const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
   double2 acc[TI][TI];
@@ -230,7 +233,8 @@ __global__ __launch_bounds__(kThreads) void rotate_kernel(ChiralSrc src, const T
                                                           double2* __restrict__ G2) {
   extern __shared__ double2 lds[];
   const int m = src.m, nr = src.h * src.nb;
-  const int pair = blockIdx.x, j = pair >> 1, alpha = pair & 1;
+  const int pair = blockIdx.x, alpha = pair & 1;
+  const int64_t j = src.j0 + (pair >> 1);
   double2* Vs = lds;                   // [m][m]
   double2* As = Vs + m * m;            // [kRotChunk][m]
   double2* Bs = As + kRotChunk * m;    // [kRotChunk][m]
@@ -365,30 +369,36 @@ size_t jacobi_lds(int m) {
 }  // namespace
 
 void chiral_svd(const ChiralSrc& s, int src_is_double, const void* base, const double* inv_norm, int k,
-                const SvdWork& w, double2* P, double* sigma, hipStream_t st) {
+                const SvdWork& w, int64_t wcap, double2* P, double* sigma, hipStream_t st) {
   CRK_REQUIRE(s.m >= 1 && s.m <= 64, "m' must be in [1, 64]");
   const int nr = s.h * s.nb;
   CRK_REQUIRE(k >= 1 && k <= s.m && k <= nr, "k must satisfy 1 <= k <= min(m', N_r)");
+  CRK_REQUIRE(wcap >= 1, "SVD work space must hold at least one block");
   const int m = s.m;
-  const unsigned npair = unsigned(2 * s.nblocks);
-  if (src_is_double) launch_gram<double2>(s, base, inv_norm, w.G, st);
-  else launch_gram<float2>(s, base, inv_norm, w.G, st);
   const double tol = 1e-15;
-  allow_lds(jacobi_kernel, jacobi_lds(m));
-  hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kThreads), jacobi_lds(m), st, w.G, w.lam, w.V, m, 40, tol,
-                     w.sweeps);
-  CRK_LAUNCH_CHECK();
-  if (src_is_double) launch_rotate<double2>(s, base, inv_norm, w.V, w.B, w.G2, st);
-  else launch_rotate<float2>(s, base, inv_norm, w.V, w.B, w.G2, st);
-  hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kThreads), jacobi_lds(m), st, w.G2, w.lam2, w.W, m, 40, tol,
-                     w.sweeps ? w.sweeps + npair : nullptr);
-  CRK_LAUNCH_CHECK();
-  const size_t lds = sizeof(double2) * (size_t(m) * k + size_t(kFinChunk) * m);
-  allow_lds(finalize_kernel, lds);
   const int nsig = m < nr ? m : nr;
-  hipLaunchKernelGGL(finalize_kernel, dim3(npair), dim3(kThreads), lds, st, m, nr, k, w.V, w.W, w.lam2, w.B, P, sigma,
-                     nsig);
-  CRK_LAUNCH_CHECK();
+  const size_t lds = sizeof(double2) * (size_t(m) * k + size_t(kFinChunk) * m);
+  allow_lds(jacobi_kernel, jacobi_lds(m));
+  allow_lds(finalize_kernel, lds);
+  for (int64_t j0 = 0; j0 < s.nblocks; j0 += wcap) {
+    ChiralSrc b = s;
+    b.j0 = j0;
+    b.nblocks = std::min(wcap, s.nblocks - j0);
+    const unsigned npair = unsigned(2 * b.nblocks);
+    if (src_is_double) launch_gram<double2>(b, base, inv_norm, w.G, st);
+    else launch_gram<float2>(b, base, inv_norm, w.G, st);
+    hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kThreads), jacobi_lds(m), st, w.G, w.lam, w.V, m, 40, tol,
+                       w.sweeps);
+    CRK_LAUNCH_CHECK();
+    if (src_is_double) launch_rotate<double2>(b, base, inv_norm, w.V, w.B, w.G2, st);
+    else launch_rotate<float2>(b, base, inv_norm, w.V, w.B, w.G2, st);
+    hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kThreads), jacobi_lds(m), st, w.G2, w.lam2, w.W, m, 40, tol,
+                       w.sweeps ? w.sweeps + npair : nullptr);
+    CRK_LAUNCH_CHECK();
+    hipLaunchKernelGGL(finalize_kernel, dim3(npair), dim3(kThreads), lds, st, m, nr, k, w.V, w.W, w.lam2, w.B,
+                       P + 2 * j0 * int64_t(k) * nr, sigma + 2 * j0 * int64_t(nsig), nsig);
+    CRK_LAUNCH_CHECK();
+  }
 }
 
 size_t svd_work_bytes(int m, int nr, int64_t nblocks) {

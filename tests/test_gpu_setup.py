@@ -214,3 +214,25 @@ def test_three_level_setup_matches_oracle(crk):
     lhs = H.coarse_apply(2, vc)
     rhs = H.restrict(1, H.coarse_apply(1, H.prolong(1, vc)))
     assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+def test_chunked_smoother_and_batched_svd_equal_full(crk):
+    """Smoothing the fine-level test vectors in chunks and running the block SVDs
+    in batches (what the library does when device memory is short) gives the same
+    hierarchy bit for bit: every vector runs its own recursion with reductions
+    that do not depend on the other vectors, and every block is factorised alone."""
+    dims, block = [4, 4, 4, 4], [2, 2, 2, 2]
+    U = synth.gauge_field(dims, 0.3, 0, config=1)
+    v0 = synth.gaussian_vectors(16, 256, 12, config=1, level=0)
+    lat = crk.Lattice(dims, -0.4, 1.0)
+    lat.load_gauge(U)
+    out = []
+    for chunk, batch in ((0, 0), (8, 0), (5, 3), (0, 1)):
+        H = crk.Hierarchy(lat, m_prime=[16], k=[8], block=[block], n_smooth=[20], setup_form=crk.FORM_FP64,
+                          init_vectors=[v0], smooth_chunk=chunk, svd_batch=batch)
+        out.append((H.sigma(0), H.vectors(0), H.timing(0), H.prolongator(0), H.coarse_links(0)))
+        H.close()
+    for s, v, t, P, X in out[1:]:
+        assert np.array_equal(s, out[0][0]) and np.array_equal(v, out[0][1])
+        assert np.array_equal(P, out[0][3]) and all(np.array_equal(a, b) for a, b in zip(X, out[0][4]))
+    assert out[1][2]["dslash_count"] == 2 * 20 and out[2][2]["dslash_count"] == 4 * 20
