@@ -68,7 +68,7 @@ def measured_traffic():
     """HBM bytes per 48-RHS smoother launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE counters, or None when the kernel source changed since they were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "wilson_rhsloop_fp32_16x16x16x32_48rhs.json")
+    path = os.path.join(ROOT, "profiles", "wilson_tile_fp32_16x16x16x32_48rhs.json")
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -247,7 +247,8 @@ def workload_volume(crk, args):
     import torch
     dev = torch.device("cuda", 0)
     rows = []
-    for dims in ([24, 24, 24, 48], [32, 32, 32, 64], [48, 48, 48, 96]):
+    sizes = {24: [24, 24, 24, 48], 32: [32, 32, 32, 64], 48: [48, 48, 48, 96]}
+    for dims in (sizes[int(x)] for x in args.volumes.split(",")):
         V = int(np.prod(dims))
         U = synth.gauge_field_device(dims, ISO["eps"], ISO["n_ape"], config=ISO["config"], progress=log)
         lat = crk.Lattice(dims, m0, ISO["xi"])
@@ -368,7 +369,7 @@ def workload_aniso16(crk, args):
         "true_rel_resid": max(i["true_rel_resid"] for i in infos),
         "converged": all(i["converged"] for i in infos),
         "roofline": {
-            "kernel": "wilson_rhsloop_kernel<FP32> (48 RHS, 16^3x32, MR setup sweep)",
+            "kernel": "wilson_tile_kernel (FP32, 48 RHS, 16^3x32 in 4^4 blocks, MR setup sweep)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
             "algorithmic_bytes_per_launch": alg,
@@ -407,9 +408,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rates", default="5,10,20,50,100,200")
-    ap.add_argument("--serve-seconds", type=float, default=20.0)
-    ap.add_argument("--serve-max-requests", type=int, default=300)
+    ap.add_argument("--volumes", default="24,32,48", help="volume sweep: spatial extents to run (24, 32, 48)")
+    ap.add_argument("--serve-rates", default="0.25,0.5,1,2,5")
+    ap.add_argument("--serve-seconds", type=float, default=40.0)
+    ap.add_argument("--serve-max-requests", type=int, default=80)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU domain "

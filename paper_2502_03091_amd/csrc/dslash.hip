@@ -438,6 +438,143 @@ void launch_wilson(const WilsonArgs& a, hipStream_t st) {
   CRK_LAUNCH_CHECK();
 }
 
+
+// ---------------------------------------------------------------- tile kernel
+// FP32 variant for the fine level of a hierarchy with 4^4 blocks, whose device
+// order is block-major: one workgroup owns one block (256 consecutive
+// positions, one thread per site) and keeps the site's eight links in
+// registers for the whole loop over right-hand sides.  Per RHS the workgroup
+// stages the block's 256 spinors and the 512 spinors just outside its eight
+// faces (64 per face) in LDS, then every hop reads its neighbour from LDS.
+// Each spinor then passes through the vector cache three times per RHS (once
+// as a block site, twice on average as a face neighbour) instead of nine, which
+// is what bounds the one-thread-per-site kernels: their time follows the
+// number of cache lines the neighbour gathers touch, not the bytes.  The block
+// spinor of the next RHS is loaded while the current one is computed; the
+// per-site arithmetic and its order are those of the other kernels.
+constexpr int kTile = 256;                   // sites per block
+constexpr int kTileSlots = kTile + 8 * 64;   // block sites, then face neighbours [dir][64]
+
+// Index of block-local site l = l0 + 4 l1 + 16 l2 + 64 l3 on a face normal to mu:
+// its local index with coordinate mu removed.
+__device__ __forceinline__ int tile_face_index(int l, int mu) {
+  const int lo = (1 << (2 * mu)) - 1;
+  return (l & lo) | ((l >> (2 * mu + 2)) << (2 * mu));
+}
+// Inverse: the block-local site with face index i and coordinate mu = lmu.
+__device__ __forceinline__ int tile_face_site(int i, int mu, int lmu) {
+  const int lo = (1 << (2 * mu)) - 1;
+  return (i & lo) | (lmu << (2 * mu)) | ((i >> (2 * mu)) << (2 * mu + 2));
+}
+
+template <int MU, int SIGN>
+__device__ __forceinline__ void tile_hop(const float2 (*sp)[kTileSlots], int slot, const float2 (&u)[9],
+                                         float2 (&acc)[12], float coef) {
+  float2 psi[12], h[6], g[6];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) psi[c] = sp[c][slot];
+  project<MU, SIGN>(psi, h);
+  link_mul<SIGN>(u, h, g);
+  accumulate<MU, SIGN>(acc, g, coef);
+}
+
+__global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<CRK_FORM_FP32> in,
+                                                               FineView<CRK_FORM_FP32> out,
+                                                               GaugeView<CRK_FORM_FP32> U,
+                                                               const int* __restrict__ nbr, int64_t V, int nrhs,
+                                                               float diag, float4 hw, double* __restrict__ partial,
+                                                               int swz) {
+  __shared__ float2 sp[12][kTileSlots];  // [component][slot], 72 KiB
+  const int64_t blk = swz ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int l = threadIdx.x, lane = l & 63, wid = l >> 6;
+  const int64_t s = blk * kTile + l;
+  // LDS slot of each neighbour, and the eight links
+  int slot[8];
+  float2 u[8][9];
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    const int mu = d >> 1, lmu = (l >> (2 * mu)) & 3;
+    const bool fwd = (d & 1) == 0;
+    const bool inside = fwd ? lmu < 3 : lmu > 0;
+    slot[d] = inside ? (fwd ? l + (1 << (2 * mu)) : l - (1 << (2 * mu))) : kTile + 64 * d + tile_face_index(l, mu);
+    const int64_t y = fwd ? s : int64_t(nbr[int64_t(d) * V + s]);
+    const float2* p = U.data + aidx(mu, 0, y, U.Vp, 9);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[d][e] = p[e * kVL];
+  }
+  // the two face neighbours this thread stages: directions wid and 4 + wid, face index lane
+  int64_t hy[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int d = 4 * k + wid, mu = d >> 1;
+    hy[k] = nbr[int64_t(d) * V + blk * kTile + tile_face_site(lane, mu, (d & 1) ? 0 : 3)];
+  }
+  float2 own[12];
+  in.load(0, s, own);
+  for (int r = 0; r < nrhs; ++r) {
+    {
+      float2 f0[12], f1[12];
+      in.load(r, hy[0], f0);
+      in.load(r, hy[1], f1);
+      __syncthreads();  // every thread is done with the previous RHS's tile
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        sp[c][l] = own[c];
+        sp[c][kTile + l] = f0[c];
+        sp[c][2 * kTile + l] = f1[c];
+      }
+      __syncthreads();
+    }
+    in.load(r + 1 < nrhs ? r + 1 : r, s, own);  // next RHS, in flight during the hops
+    float2 acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = cscale(sp[c][l], diag);
+    tile_hop<0, +1>(sp, slot[0], u[0], acc, hw.x);
+    tile_hop<0, -1>(sp, slot[1], u[1], acc, hw.x);
+    tile_hop<1, +1>(sp, slot[2], u[2], acc, hw.y);
+    tile_hop<1, -1>(sp, slot[3], u[3], acc, hw.y);
+    tile_hop<2, +1>(sp, slot[4], u[4], acc, hw.z);
+    tile_hop<2, -1>(sp, slot[5], u[5], acc, hw.z);
+    tile_hop<3, +1>(sp, slot[6], u[6], acc, hw.w);
+    tile_hop<3, -1>(sp, slot[7], u[7], acc, hw.w);
+    out.store(r, s, acc);
+    if (partial != nullptr) {
+      double v0 = 0, v1 = 0, v2 = 0;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const float2 q = acc[c], x = sp[c][l];
+        v0 += double(q.x) * x.x + double(q.y) * x.y;
+        v1 += double(q.x) * x.y - double(q.y) * x.x;
+        v2 += double(q.x) * q.x + double(q.y) * q.y;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        v0 += __shfl_xor(v0, o);
+        v1 += __shfl_xor(v1, o);
+        v2 += __shfl_xor(v2, o);
+      }
+      // one partial row per wavefront (64 sites), as in the other kernels
+      if (lane == 0) {
+        double* p = partial + ((blk * 4 + wid) * nrhs + r) * 3;
+        p[0] = v0;
+        p[1] = v1;
+        p[2] = v2;
+      }
+    }
+  }
+}
+
+void launch_wilson_tile(const WilsonArgs& a, hipStream_t st) {
+  CRK_REQUIRE(a.V % kTile == 0, "tile dslash: the volume must be a multiple of 4^4");
+  const int64_t nblk = a.V / kTile;
+  if (nblk > 0x7fffffff) fail(CRK_EINVAL, "dslash grid too large");
+  FineView<CRK_FORM_FP32> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
+  GaugeView<CRK_FORM_FP32> U{static_cast<const float2*>(a.gauge), pad_sites(a.V)};
+  const float4 hw = make_float4(float(a.hw[0]), float(a.hw[1]), float(a.hw[2]), float(a.hw[3]));
+  hipLaunchKernelGGL(wilson_tile_kernel, dim3(unsigned(nblk)), dim3(kTile), 0, st, in, out, U, a.nbr, a.V, a.nrhs,
+                     float(a.diag), hw, a.partial, a.swizzle);
+  CRK_LAUNCH_CHECK();
+}
 }  // namespace
 
 int64_t wilson_partial_blocks(int64_t V) { return (V + kVL - 1) / kVL; }
@@ -447,6 +584,7 @@ void wilson_apply(const WilsonArgs& a_in, hipStream_t st) {
   CRK_REQUIRE(a_in.in != a_in.out, "dslash: in and out must not alias");
   const WilsonArgs& a = a_in;
   const int R = a.rhs_per_thread < a.nrhs ? a.rhs_per_thread : a.nrhs;
+  if (a.form == CRK_FORM_FP32 && a.tile4) { launch_wilson_tile(a, st); return; }
   if (a.form == CRK_FORM_FP32) { launch_wilson_rhsloop<CRK_FORM_FP32>(a, st); return; }
   if (a.nrhs <= kDirMaxRhs && a.form == CRK_FORM_FP64) { launch_wilson_dir<CRK_FORM_FP64>(a, st); return; }
   switch (a.form) {

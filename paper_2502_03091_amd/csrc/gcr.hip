@@ -35,40 +35,49 @@ int64_t chunk_of(int64_t n) {
 // depends on n only, so an RHS's sums do not depend on the number of RHS.
 int64_t chunk_for_shape(int64_t n, bool inner) { return inner ? int64_t(kInnerChunk) : chunk_of(n); }
 
+// Directions per multidot workgroup: grid z runs over groups of kDotGroup
+// stored directions, so a thread keeps 2*kDotGroup sums and issues the loads
+// of all its group's directions together.  The last group repeats the last
+// direction for its unused members (in-bounds loads, sums not stored).
+constexpr int kDotGroup = 8;
+
 // partial[chunk][r][2*j + {0,1}] = chunk sum of conj(W_j) w
 template <class C>
 __global__ __launch_bounds__(kT) void multidot_kernel(const C* __restrict__ Wb, int64_t fstride, int nj,
                                                       const C* __restrict__ w, int64_t n, int nrhs, int64_t rs,
                                                       int64_t es, int64_t chunk, double* __restrict__ partial) {
-  __shared__ double sh[2 * kMaxBasis][4];
-  const int r = blockIdx.y;
+  __shared__ double sh[2 * kDotGroup][4];
+  const int r = blockIdx.y, j0 = blockIdx.z * kDotGroup;
   const int64_t e0 = int64_t(blockIdx.x) * chunk, e1 = min(n, e0 + chunk);
-  double acc[2 * kMaxBasis];
+  const C* Wg[kDotGroup];
 #pragma unroll
-  for (int q = 0; q < 2 * kMaxBasis; ++q) acc[q] = 0;
+  for (int g = 0; g < kDotGroup; ++g) Wg[g] = Wb + int64_t(min(j0 + g, nj - 1)) * fstride;
+  double acc[2 * kDotGroup];
+#pragma unroll
+  for (int q = 0; q < 2 * kDotGroup; ++q) acc[q] = 0;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int64_t idx = int64_t(r) * rs + e * es;
     const C y = w[idx];
+    C x[kDotGroup];
 #pragma unroll
-    for (int j = 0; j < kMaxBasis; ++j) {
-      if (j < nj) {
-        const C x = Wb[j * fstride + idx];
-        acc[2 * j] += double(x.x) * y.x + double(x.y) * y.y;
-        acc[2 * j + 1] += double(x.x) * y.y - double(x.y) * y.x;
-      }
+    for (int g = 0; g < kDotGroup; ++g) x[g] = Wg[g][idx];
+#pragma unroll
+    for (int g = 0; g < kDotGroup; ++g) {
+      acc[2 * g] += double(x[g].x) * y.x + double(x[g].y) * y.y;
+      acc[2 * g + 1] += double(x[g].x) * y.y - double(x[g].y) * y.x;
     }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < 2 * kMaxBasis; ++q) {
-    if (q < 2 * nj) {
-      const double t = wsum(acc[q]);
-      if (lane == 0) sh[q][wid] = t;
-    }
+  for (int q = 0; q < 2 * kDotGroup; ++q) {
+    const double t = wsum(acc[q]);
+    if (lane == 0) sh[q][wid] = t;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < 2 * nj; q += blockDim.x)
-    partial[(int64_t(blockIdx.x) * nrhs + r) * (2 * kMaxBasis) + q] = sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
+  const int nq = 2 * min(kDotGroup, nj - j0);
+  for (int q = threadIdx.x; q < nq; q += blockDim.x)
+    partial[(int64_t(blockIdx.x) * nrhs + r) * (2 * kMaxBasis) + 2 * j0 + q] =
+        sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
 }
 
 // Rhs-inner fields: one wavefront per (chunk of kInnerChunk elements, rhs);
@@ -79,34 +88,36 @@ template <class C>
 __global__ __launch_bounds__(64) void multidot_inner_kernel(const C* __restrict__ Wb, int64_t fstride, int nj,
                                                             const C* __restrict__ w, int64_t n, int nrhs,
                                                             int64_t rs, int64_t es, double* __restrict__ partial) {
-  __shared__ double sh[64][2 * kMaxBasis + 1];
-  const int r = blockIdx.y, l = threadIdx.x;
+  __shared__ double sh[64][2 * kDotGroup + 1];
+  const int r = blockIdx.y, l = threadIdx.x, j0 = blockIdx.z * kDotGroup;
   const int64_t c = blockIdx.x;
-  double acc[2 * kMaxBasis];
+  const C* Wg[kDotGroup];
 #pragma unroll
-  for (int q = 0; q < 2 * kMaxBasis; ++q) acc[q] = 0;
+  for (int g = 0; g < kDotGroup; ++g) Wg[g] = Wb + int64_t(min(j0 + g, nj - 1)) * fstride;
+  double acc[2 * kDotGroup];
+#pragma unroll
+  for (int q = 0; q < 2 * kDotGroup; ++q) acc[q] = 0;
   for (int i = 0; i < kInnerChunk / 64; ++i) {
     const int64_t e = c * kInnerChunk + l + 64 * i;
     if (e >= n) break;
     const int64_t idx = int64_t(r) * rs + e * es;
     const C y = w[idx];
+    C x[kDotGroup];
 #pragma unroll
-    for (int j = 0; j < kMaxBasis; ++j) {
-      if (j < nj) {
-        const C x = Wb[j * fstride + idx];
-        acc[2 * j] += double(x.x) * y.x + double(x.y) * y.y;
-        acc[2 * j + 1] += double(x.x) * y.y - double(x.y) * y.x;
-      }
+    for (int g = 0; g < kDotGroup; ++g) x[g] = Wg[g][idx];
+#pragma unroll
+    for (int g = 0; g < kDotGroup; ++g) {
+      acc[2 * g] += double(x[g].x) * y.x + double(x[g].y) * y.y;
+      acc[2 * g + 1] += double(x[g].x) * y.y - double(x[g].y) * y.x;
     }
   }
 #pragma unroll
-  for (int q = 0; q < 2 * kMaxBasis; ++q)
-    if (q < 2 * nj) sh[l][q] = acc[q];
+  for (int q = 0; q < 2 * kDotGroup; ++q) sh[l][q] = acc[q];
   __syncthreads();
-  if (l < 2 * nj) {
+  if (l < 2 * min(kDotGroup, nj - j0)) {
     double t = 0;
     for (int k = 0; k < 64; ++k) t += sh[k][l];
-    partial[(c * nrhs + r) * (2 * kMaxBasis) + l] = t;
+    partial[(c * nrhs + r) * (2 * kMaxBasis) + 2 * j0 + l] = t;
   }
 }
 
@@ -140,6 +151,7 @@ __global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb,
                                                        int64_t fstride, int nj, int j_first, C* __restrict__ z,
                                                        C* __restrict__ w, const double2* __restrict__ coef, int64_t n,
                                                        int nrhs, int64_t rs, int64_t es) {
+  constexpr int kU = 4;  // directions whose loads are issued together
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n * nrhs) return;
   const int r = es == 1 ? int(t / n) : int(t % nrhs);
@@ -147,13 +159,35 @@ __global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb,
   const int64_t idx = int64_t(r) * rs + e * es;
   using T = decltype(C::x);
   C zz = z[idx], ww = w[idx];
-  for (int t = 0; t < nj; ++t) {
-    const int j = t + j_first < nj ? t + j_first : t + j_first - nj;
-    const double2 cd = coef[r * kMaxCoef + j];
-    if (cd.x == 0.0 && cd.y == 0.0) continue;
-    const C c = mk<C>(T(-cd.x), T(-cd.y));
-    cfma(zz, c, Zb[j * fstride + idx]);
-    cfma(ww, c, Wb[j * fstride + idx]);
+  for (int t0 = 0; t0 < nj; t0 += kU) {
+    C zl[kU], wl[kU], c[kU];
+    int jj[kU];
+    bool on[kU];
+    // coefficients first, so that the direction loads below are issued back to back
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      // past the end: the last direction's index (in bounds), skipped
+      const int tt = t0 + u < nj ? t0 + u : nj - 1;
+      jj[u] = tt + j_first < nj ? tt + j_first : tt + j_first - nj;
+      const double2 cd = coef[r * kMaxCoef + jj[u]];
+      on[u] = t0 + u < nj && (cd.x != 0.0 || cd.y != 0.0);  // zero: an unused slot or a frozen RHS, not read
+      c[u] = mk<C>(T(-cd.x), T(-cd.y));
+    }
+    // a skipped direction re-reads this thread's own z, w entries (already in
+    // cache) instead of branching, so all loads stay in flight together
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t off = on[u] ? jj[u] * fstride + idx : idx;
+      zl[u] = (on[u] ? Zb : static_cast<const C*>(z))[off];
+      wl[u] = (on[u] ? Wb : static_cast<const C*>(w))[off];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (on[u]) {
+        cfma(zz, c[u], zl[u]);
+        cfma(ww, c[u], wl[u]);
+      }
+    }
   }
   z[idx] = zz;
   w[idx] = ww;
@@ -371,11 +405,11 @@ void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* 
   CRK_REQUIRE(nj <= kMaxCoef, "GCR basis above 64 vectors");
   CRK_REQUIRE(valid == nullptr || nj <= 32, "masked GCR basis above 32 vectors");
   const int64_t chunk = chunk_for_shape(f.n, f.es != 1), nch = shape_chunks(f);
-  const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
   const size_t esz = prec == CRK_FORM_FP64 ? sizeof(double2) : sizeof(float2);
-  const dim3 gi = dim3(unsigned(nch), unsigned(f.nrhs));
   for (int j0 = 0; j0 < nj; j0 += kMaxBasis) {
     const int nc = nj - j0 < kMaxBasis ? nj - j0 : kMaxBasis;
+    const unsigned ng = unsigned((nc + kDotGroup - 1) / kDotGroup);
+    const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs), ng), gi = g;
     const void* Wj = static_cast<const char*>(W) + esz * size_t(j0) * size_t(fstride);
     if (f.es != 1 && prec == CRK_FORM_FP64)
       hipLaunchKernelGGL(multidot_inner_kernel<double2>, gi, dim3(64), 0, st, static_cast<const double2*>(Wj), fstride,

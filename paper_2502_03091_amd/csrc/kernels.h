@@ -40,6 +40,7 @@ struct WilsonArgs {
   int rhs_per_thread;
   int order = 0;    // 0: RHS groups of a site block consecutive; 1: site blocks of a RHS group consecutive
   int swizzle = 1;  // XCD-contiguous workgroup mapping
+  int tile4 = 0;    // device order is block-major in 4^4 blocks (every extent a multiple of 4)
 };
 void wilson_apply(const WilsonArgs& a, hipStream_t st);
 int64_t wilson_partial_blocks(int64_t V);

@@ -90,6 +90,8 @@ void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int n
       for (double& h : a.hw) h = -h;
     a.partial = partial;
     a.rhs_per_thread = 4;
+    const Geometry& g = H->fine_geo;
+    a.tile4 = g.blocked && g.block[0] == 4 && g.block[1] == 4 && g.block[2] == 4 && g.block[3] == 4;
     wilson_apply(a, st);
   } else {
     const CoarseLevel& c = H->coarse[l - 1];

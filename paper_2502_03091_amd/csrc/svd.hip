@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int m, int nr, int k
   extern __shared__ double2 lds[];
   const int pair = blockIdx.x;
   double2* T = lds;             // [m][k]
-  double2* Bs = T + m * k;      // [kFinChunk][m]
+  double2* Bs = T + m * k;      // [kFinChunk][m + 1]
   __shared__ double2 phase[64];
   __shared__ double sig[64];
   __shared__ double2 colsum[64];
@@ -311,15 +311,16 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int m, int nr, int k
   }
   const double2* Bp = B + int64_t(pair) * nr * m;
   double2* Pp = P + int64_t(pair) * k * nr;
+  const int mp = m + 1;  // padded row stride: lanes of consecutive rows hit different LDS banks
   for (int r0 = 0; r0 < nr; r0 += kFinChunk) {
     const int nrows = min(kFinChunk, nr - r0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nrows * m; e += blockDim.x) Bs[e] = Bp[int64_t(r0) * m + e];
+    for (int e = threadIdx.x; e < nrows * m; e += blockDim.x) Bs[(e / m) * mp + e % m] = Bp[int64_t(r0) * m + e];
     __syncthreads();
     for (int e = threadIdx.x; e < nrows * k; e += blockDim.x) {
       const int i = e / nrows, rr = e % nrows;
       double2 t = make_double2(0, 0);
-      for (int y = 0; y < m; ++y) cfma(t, Bs[rr * m + y], T[y * k + i]);
+      for (int y = 0; y < m; ++y) cfma(t, Bs[rr * mp + y], T[y * k + i]);
       Pp[int64_t(i) * nr + r0 + rr] = t;
     }
   }
@@ -377,7 +378,7 @@ void chiral_svd(const ChiralSrc& s, int src_is_double, const void* base, const d
   const int m = s.m;
   const double tol = 1e-15;
   const int nsig = m < nr ? m : nr;
-  const size_t lds = sizeof(double2) * (size_t(m) * k + size_t(kFinChunk) * m);
+  const size_t lds = sizeof(double2) * (size_t(m) * k + size_t(kFinChunk) * (m + 1));
   allow_lds(jacobi_kernel, jacobi_lds(m));
   allow_lds(finalize_kernel, lds);
   for (int64_t j0 = 0; j0 < s.nblocks; j0 += wcap) {

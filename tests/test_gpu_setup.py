@@ -170,6 +170,22 @@ def test_setup_fp32_smoother_bounds(crk):
     assert np.abs(H.sigma(0) - so).max() <= 1e-4 * so[..., 0].max()
 
 
+def test_setup_fp32_smoother_4x4_blocks(crk):
+    """The FP32 smoother on the block-staged fine operator (4^4 blocks, block-major
+    order, MR partial sums fused into the operator launch): same bounds as above.
+    Extent 4 in y and t puts one block along them (neighbours wrap into the block)."""
+    dims, block = [8, 4, 8, 4], [4, 4, 4, 4]
+    print("fp32 smoother, 4^4 blocks", dims, flush=True)
+    lat, H, op, ref = _build(crk, dims, block, 16, 8, 20, form=1, m0=-0.2)
+    vg = H.vectors(0)
+    vo = as_fields(ref[0].vectors)
+    err = (np.abs(vg - vo).max(axis=(1, 2)) / np.abs(vo).max(axis=(1, 2))).max()
+    print("fp32 smoother vector error (4^4 blocks)", err, flush=True)
+    assert err <= 1e-4
+    so = ref[0].sigma
+    assert np.abs(H.sigma(0) - so).max() <= 1e-4 * so[..., 0].max()
+
+
 def test_setup_rejects_bad_parameters(crk):
     lat = crk.Lattice([4, 4, 4, 4], -0.4, 1.0)
     lat.load_gauge(synth.gauge_field([4, 4, 4, 4], 0.3, 0, config=1))
