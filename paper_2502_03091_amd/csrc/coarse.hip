@@ -65,21 +65,56 @@ __global__ __launch_bounds__(64 * kLinkWaves) void coarse_mfma_kernel(const type
   const int n = tile * 16 + (lane & 15);
   const int kq = lane >> 4;
   const bool live = n < nrhs;
-  A are = A{0, 0, 0, 0}, aim = A{0, 0, 0, 0};
-  for (int nb = 3 * wv; nb < 3 * wv + 3; ++nb) {
+  // columns past nrhs read the last RHS (in bounds, no branch around the loads,
+  // so the loads of all K steps can be in flight together); output column n of
+  // a product depends on B column n only, and those columns are not stored
+  const int nc = live ? n : nrhs - 1;
+  // The wavefront's three links: the A and B operands of link t + 1 are loaded
+  // while link t is multiplied; two accumulators per real/imaginary part keep
+  // consecutive MFMAs independent.
+  constexpr int KS = N / 4;
+  A are0 = A{0, 0, 0, 0}, are1 = A{0, 0, 0, 0}, aim0 = A{0, 0, 0, 0}, aim1 = A{0, 0, 0, 0};
+  C av[KS], bv[KS];
+  auto load_link = [&](int nb, C (&a)[KS], C (&b)[KS]) {
     const int64_t s = nb == 0 ? j : int64_t(nbr[int64_t(nb - 1) * Vc + j]);
     const C* Lb = links + (j * 9 + nb) * int64_t(N) * N + mt * 16 + (lane & 15);
-    const C* vb = in + s * int64_t(N) * nrhs + n;
+    const C* vb = in + s * int64_t(N) * nrhs + nc;
 #pragma unroll
-    for (int ks = 0; ks < N / 4; ++ks) {
+    for (int ks = 0; ks < KS; ++ks) {
       const int kk = ks * 4 + kq;
-      const C bv = live ? vb[int64_t(kk) * nrhs] : C{0, 0};
-      const C av = Lb[int64_t(kk) * N];
-      are = Mfma<T>::op(av.x, bv.x, are);
-      are = Mfma<T>::op(-av.y, bv.y, are);
-      aim = Mfma<T>::op(av.x, bv.y, aim);
-      aim = Mfma<T>::op(av.y, bv.x, aim);
+      a[ks] = Lb[int64_t(kk) * N];
+      b[ks] = vb[int64_t(kk) * nrhs];
     }
+  };
+  load_link(3 * wv, av, bv);
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    C an[KS], bn[KS];
+    if (t < 2) load_link(3 * wv + t + 1, an, bn);
+    // keep the next link's loads above this link's products (the scheduler
+    // would otherwise sink each load to its use and wait on it there)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      are0 = Mfma<T>::op(av[ks].x, bv[ks].x, are0);
+      aim0 = Mfma<T>::op(av[ks].x, bv[ks].y, aim0);
+      are1 = Mfma<T>::op(-av[ks].y, bv[ks].y, are1);
+      aim1 = Mfma<T>::op(av[ks].y, bv[ks].x, aim1);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (t < 2) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        av[ks] = an[ks];
+        bv[ks] = bn[ks];
+      }
+    }
+  }
+  A are, aim;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    are[i] = are0[i] + are1[i];
+    aim[i] = aim0[i] + aim1[i];
   }
   if (wv > 0) {
 #pragma unroll
@@ -130,6 +165,7 @@ __global__ __launch_bounds__(64) void coarse_mfma_f16_kernel(const __half2* __re
   const int n = tile * 16 + (lane & 15);
   const int kq = lane >> 4;
   const bool live = n < nrhs;
+  const int nc = live ? n : nrhs - 1;  // past nrhs: the last RHS (in bounds), not stored
   floatx4 tre[MT], tim[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) { tre[mt] = floatx4{0, 0, 0, 0}; tim[mt] = floatx4{0, 0, 0, 0}; }
@@ -141,7 +177,7 @@ __global__ __launch_bounds__(64) void coarse_mfma_f16_kernel(const __half2* __re
     // vectors of this link's neighbour: per-rhs scale so the fp16 B operand is well conditioned
     float vmax = 0.f;
     for (int kk = 0; kk < N; ++kk) {
-      const float2 v = live ? vb[int64_t(kk) * nrhs + n] : float2{0, 0};
+      const float2 v = vb[int64_t(kk) * nrhs + nc];
       vmax = fmaxf(vmax, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
     const float vinv = vmax > 0.f ? 1.f / vmax : 0.f;
@@ -153,7 +189,7 @@ __global__ __launch_bounds__(64) void coarse_mfma_f16_kernel(const __half2* __re
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int kk = ks * 16 + kq * 4 + i;
-        const float2 v = live ? vb[int64_t(kk) * nrhs + n] : float2{0, 0};
+        const float2 v = vb[int64_t(kk) * nrhs + nc];
         br[i] = _Float16(v.x * vinv);
         bi[i] = _Float16(v.y * vinv);
       }

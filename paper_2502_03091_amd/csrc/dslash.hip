@@ -539,14 +539,17 @@ __global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<CRK_FORM
     tile_hop<3, -1>(sp, slot[7], u[7], acc, hw.w);
     out.store(r, s, acc);
     if (partial != nullptr) {
-      double v0 = 0, v1 = 0, v2 = 0;
+      // the site's twelve terms in FP32 (the form's accumulation precision),
+      // the sums over sites in FP64
+      float f0 = 0, f1 = 0, f2 = 0;
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const float2 q = acc[c], x = sp[c][l];
-        v0 += double(q.x) * x.x + double(q.y) * x.y;
-        v1 += double(q.x) * x.y - double(q.y) * x.x;
-        v2 += double(q.x) * q.x + double(q.y) * q.y;
+        f0 += q.x * x.x + q.y * x.y;
+        f1 += q.x * x.y - q.y * x.x;
+        f2 += q.x * q.x + q.y * q.y;
       }
+      double v0 = f0, v1 = f1, v2 = f2;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         v0 += __shfl_xor(v0, o);

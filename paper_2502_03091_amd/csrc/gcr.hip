@@ -131,8 +131,20 @@ __global__ __launch_bounds__(kT) void multidot_reduce_kernel(const double* __res
   const int r = blockIdx.x;
   const int q = threadIdx.x & 63, g = threadIdx.x >> 6;
   double acc = 0;
-  if (q < 2 * nj)
-    for (int64_t c = g; c < nch; c += kT / 64) acc += partial[(c * nrhs + r) * (2 * kMaxBasis) + q];
+  if (q < 2 * nj) {
+    // loads issued eight at a time, added in chunk order
+    for (int64_t c0 = g; c0 < nch; c0 += 8 * (kT / 64)) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t c = c0 + int64_t(u) * (kT / 64);
+        v[u] = c < nch ? partial[(c * nrhs + r) * (2 * kMaxBasis) + q] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + int64_t(u) * (kT / 64) < nch) acc += v[u];
+    }
+  }
   sh[g][q] = acc;
   __syncthreads();
   for (int j = threadIdx.x; j < nj; j += blockDim.x) {
@@ -173,6 +185,11 @@ __global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb,
       on[u] = t0 + u < nj && (cd.x != 0.0 || cd.y != 0.0);  // zero: an unused slot or a frozen RHS, not read
       c[u] = mk<C>(T(-cd.x), T(-cd.y));
     }
+    // nothing to add (unused slots, or a frozen RHS): no loads at all
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) any |= on[u];
+    if (!any) continue;
     // a skipped direction re-reads this thread's own z, w entries (already in
     // cache) instead of branching, so all loads stay in flight together
 #pragma unroll
@@ -323,8 +340,20 @@ __global__ __launch_bounds__(kT) void check_kernel(const double* __restrict__ pa
   for (int r0 = 0; r0 < nrhs; r0 += 64) {
     const int r = r0 + q;
     double acc = 0;
-    if (r < nrhs)
-      for (int64_t c = g; c < nch; c += kT / 64) acc += partial[c * nrhs + r];
+    if (r < nrhs) {
+      // loads issued eight at a time, added in chunk order
+      for (int64_t c0 = g; c0 < nch; c0 += 8 * (kT / 64)) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t c = c0 + int64_t(u) * (kT / 64);
+          v[u] = c < nch ? partial[c * nrhs + r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (c0 + int64_t(u) * (kT / 64) < nch) acc += v[u];
+      }
+    }
     sh[g][q] = acc;
     __syncthreads();
     if (g == 0 && r < nrhs) {
