@@ -45,6 +45,7 @@ template <> struct Mfma<double> {
 // links gives the small coarse lattices enough wavefronts to keep loads in
 // flight.
 constexpr int kLinkWaves = 3;
+constexpr int kLinksPerWave = 9 / kLinkWaves;
 
 template <class T, int MT>
 __global__ __launch_bounds__(64 * kLinkWaves) void coarse_mfma_kernel(const typename cplx_t<T>::type* __restrict__ links,
@@ -86,11 +87,11 @@ __global__ __launch_bounds__(64 * kLinkWaves) void coarse_mfma_kernel(const type
       b[ks] = vb[int64_t(kk) * nrhs];
     }
   };
-  load_link(3 * wv, av, bv);
+  load_link(kLinksPerWave * wv, av, bv);
 #pragma unroll
-  for (int t = 0; t < 3; ++t) {
+  for (int t = 0; t < kLinksPerWave; ++t) {
     C an[KS], bn[KS];
-    if (t < 2) load_link(3 * wv + t + 1, an, bn);
+    if (t + 1 < kLinksPerWave) load_link(kLinksPerWave * wv + t + 1, an, bn);
     // keep the next link's loads above this link's products (the scheduler
     // would otherwise sink each load to its use and wait on it there)
     __builtin_amdgcn_sched_barrier(0);
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(64 * kLinkWaves) void coarse_mfma_kernel(const type
       aim1 = Mfma<T>::op(av[ks].y, bv[ks].x, aim1);
     }
     __builtin_amdgcn_sched_barrier(0);
-    if (t < 2) {
+    if (t + 1 < kLinksPerWave) {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         av[ks] = an[ks];
