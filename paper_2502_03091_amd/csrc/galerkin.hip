@@ -20,6 +20,7 @@ namespace crk {
 namespace {
 
 constexpr int kT = 256;
+constexpr int kGalerkinMaxNb = 1024;  // fine sites per block (list in LDS)
 
 // Projection of the (chirality-sparse) column onto the half spinor of (1 - sign gamma_mu).
 template <int MU, int SIGN>
@@ -113,35 +114,66 @@ __device__ __forceinline__ void maybe_hop(const GalerkinArgs& A, int64_t x, int6
   if (part == 0 ? inside : (SIGN > 0 && MU == part - 1 && !inside)) add_hop<MU, SIGN>(A, x, y, col, a, t);
 }
 
+// The block's contributing sites (all for X, the +mu face for Y_{+mu}) are
+// listed in site order and taken kSiteBatch at a time: the hop results of a
+// batch are formed together, then added site by site in list order, so every
+// output has the same summation order as a site-by-site loop.
+constexpr int kSiteBatch = 4;
+
 template <int TI>
 __global__ __launch_bounds__(kT) void galerkin_kernel(GalerkinArgs A) {
   constexpr int N = 16 * TI;  // 2k
-  __shared__ double2 T[12][N];
-  __shared__ double2 Pc[6][N];
+  constexpr int S = kSiteBatch;
+  __shared__ double2 T[S][12][N];
+  __shared__ double2 Pc[S][6][N];
+  __shared__ int list[kGalerkinMaxNb];
+  __shared__ int wcount[kT / 64];
+  __shared__ int nlist;
   const int64_t j = blockIdx.x / 5;
   const int part = blockIdx.x % 5;
   const int k = A.k;
   const int rg = threadIdx.x / 16, cg = threadIdx.x % 16;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // compaction of the contributing local sites, in order
+  if (threadIdx.x == 0) nlist = 0;
+  for (int l0 = 0; l0 < A.nb; l0 += kT) {
+    const int l = l0 + threadIdx.x;
+    bool use = l < A.nb;
+    if (use && part > 0) {
+      const int64_t y = A.nbr[int64_t(2 * (part - 1)) * A.V + j * A.nb + l];
+      use = (y / A.nb) != j;
+    }
+    const uint64_t m = __ballot(use);
+    __syncthreads();
+    if (lane == 0) wcount[wid] = __popcll(m);
+    __syncthreads();
+    int off = nlist;
+    for (int w = 0; w < wid; ++w) off += wcount[w];
+    if (use) list[off + __popcll(m & ((uint64_t(1) << lane) - 1))] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) nlist += wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    __syncthreads();
+  }
+  const int nl = nlist;
   double2 acc[TI][TI];
 #pragma unroll
   for (int x = 0; x < TI; ++x)
 #pragma unroll
     for (int y = 0; y < TI; ++y) acc[x][y] = make_double2(0, 0);
 
-  for (int l = 0; l < A.nb; ++l) {
-    const int64_t x = j * A.nb + l;
-    if (part > 0) {
-      const int64_t y = A.nbr[int64_t(2 * (part - 1)) * A.V + x];
-      if (y / A.nb == j) continue;  // uniform across the workgroup
-    }
+  for (int b0 = 0; b0 < nl; b0 += S) {
+    const int ns = min(S, nl - b0);
     __syncthreads();
     // P(x) per column, compressed to its chirality's 6 components
-    for (int e = threadIdx.x; e < 6 * N; e += blockDim.x) {
-      const int c = e / N, col = e % N, beta = col / k, i = col % k;
-      Pc[c][col] = A.P[((2 * j + beta) * k + i) * int64_t(A.nr) + int64_t(c) * A.nb + l];
+    for (int e = threadIdx.x; e < ns * 6 * N; e += blockDim.x) {
+      const int sb = e / (6 * N), c = (e / N) % 6, col = e % N, beta = col / k, i = col % k;
+      const int l = list[b0 + sb];
+      Pc[sb][c][col] = A.P[((2 * j + beta) * k + i) * int64_t(A.nr) + int64_t(c) * A.nb + l];
     }
-    for (int e = threadIdx.x; e < 3 * N; e += blockDim.x) {
-      const int col = e / 3, a = e % 3;
+    for (int e = threadIdx.x; e < ns * 3 * N; e += blockDim.x) {
+      const int sb = e / (3 * N), col = (e / 3) % N, a = e % 3;
+      const int l = list[b0 + sb];
+      const int64_t x = j * A.nb + l;
       double2 t[4];
 #pragma unroll
       for (int sp = 0; sp < 4; ++sp) t[sp] = make_double2(0, 0);
@@ -166,19 +198,21 @@ __global__ __launch_bounds__(kT) void galerkin_kernel(GalerkinArgs A) {
       maybe_hop<3, +1>(A, x, j, col, a, part, t);
       maybe_hop<3, -1>(A, x, j, col, a, part, t);
 #pragma unroll
-      for (int sp = 0; sp < 4; ++sp) T[3 * sp + a][col] = t[sp];
+      for (int sp = 0; sp < 4; ++sp) T[sb][3 * sp + a][col] = t[sp];
     }
     __syncthreads();
-    // acc[r][c] += sum_c' conj(P(x)[alpha_r*6 + c'][r]) T[alpha_r*6 + c'][c]
+    // acc[r][c] += sum_c' conj(P(x)[alpha_r*6 + c'][r]) T[alpha_r*6 + c'][c], sites in list order
+    for (int sb = 0; sb < ns; ++sb) {
 #pragma unroll
-    for (int xr = 0; xr < TI; ++xr) {
-      const int r = rg * TI + xr;
-      const int ar = r / k;
+      for (int xr = 0; xr < TI; ++xr) {
+        const int r = rg * TI + xr;
+        const int ar = r / k;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        const double2 pr = Pc[c][r];
+        for (int c = 0; c < 6; ++c) {
+          const double2 pr = Pc[sb][c][r];
 #pragma unroll
-        for (int yc = 0; yc < TI; ++yc) cfmac(acc[xr][yc], pr, T[6 * ar + c][cg * TI + yc]);
+          for (int yc = 0; yc < TI; ++yc) cfmac(acc[xr][yc], pr, T[sb][6 * ar + c][cg * TI + yc]);
+        }
       }
     }
   }
@@ -216,6 +250,7 @@ __global__ __launch_bounds__(kT) void backward_links_kernel(double2* __restrict_
 void galerkin_fine(const GalerkinArgs& A, const int* nbr_c, int64_t Vc, hipStream_t st) {
   const int N = 2 * A.k;
   CRK_REQUIRE(N % 16 == 0 && N <= 128, "2k must be a multiple of 16 and <= 128");
+  CRK_REQUIRE(A.nb >= 1 && A.nb <= kGalerkinMaxNb, "Galerkin: at most 1024 fine sites per block");
   const dim3 g = dim3(unsigned(A.ncoarse * 5));
   switch (N / 16) {
     case 1: hipLaunchKernelGGL(galerkin_kernel<1>, g, dim3(kT), 0, st, A); break;
