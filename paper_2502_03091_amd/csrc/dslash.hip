@@ -537,7 +537,20 @@ __global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<CRK_FORM
     tile_hop<2, -1>(sp, slot[5], u[5], acc, hw.z);
     tile_hop<3, +1>(sp, slot[6], u[6], acc, hw.w);
     tile_hop<3, -1>(sp, slot[7], u[7], acc, hw.w);
-    out.store(r, s, acc);
+    {
+      // streaming stores: the output is not read again by this launch, so it
+      // does not displace from L2 the spinors that neighbouring blocks still
+      // read as face neighbours
+      typedef float v2f __attribute__((ext_vector_type(2)));
+      float2* po = out.data + aidx(r, 0, s, out.Vp, 12);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        v2f v;
+        v.x = acc[c].x;
+        v.y = acc[c].y;
+        __builtin_nontemporal_store(v, reinterpret_cast<v2f*>(po + c * kVL));
+      }
+    }
     if (partial != nullptr) {
       // the site's twelve terms in FP32 (the form's accumulation precision),
       // the sums over sites in FP64
