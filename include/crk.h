@@ -203,8 +203,10 @@ int crk_mg_get_timing(crk_mg_t mg, int32_t level, double* out6);
 /* Apply the operator of level l in a form to host complex128 vectors
  * [nrhs][V_l][N_l]: l = 1..n_levels-1 the Galerkin coarse operator (2k
  * components per coarse site), l = 0 the fine Wilson operator through the
- * hierarchy's own kernels and block-major site order (FP64 or FP32), i.e.
- * the operator the smoother and the K-cycle apply. */
+ * hierarchy's own kernels and block-major site order, i.e. the operator the
+ * smoother and the K-cycle apply (FP16S at level 0: FP16 spinors with one
+ * scale per site and RHS and half links, as the FP16S form's post-smoother
+ * uses them; the input is rounded to that storage). */
 int crk_mg_coarse_apply(crk_mg_t mg, int32_t level, int32_t form, const double* in, double* out,
                         int32_t nrhs);
 

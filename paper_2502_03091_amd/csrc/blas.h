@@ -33,6 +33,9 @@ void mr_alpha(const double* sums3, int nrhs, double2* alpha, hipStream_t st);
 // psi += alpha r; r -= alpha q (n entries per rhs; rhs-outer or rhs-inner layout).
 void mr_update(int prec, void* psi, void* r, const void* q, const double2* alpha, int64_t n, int nrhs, bool rhs_inner,
                hipStream_t st);
+// The same update on the fine level with psi in FP32 and r, q in FP16 storage
+// (AoSoA fine fields of V sites, one scale per site and RHS; r is rescaled).
+void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st);
 
 // out[i] = 1/sqrt(sums[i*nv + comp]) (0 for a zero sum).
 void inv_sqrt(const double* sums, int nv, int comp, int n, double* out, hipStream_t st);

@@ -87,6 +87,35 @@ __global__ void mr_alpha_kernel(const double* __restrict__ sums, int nrhs, doubl
   alpha[r] = qq > 0 ? make_double2(sums[3 * r] / qq, sums[3 * r + 1] / qq) : make_double2(0, 0);
 }
 
+// psi += alpha r ;  r -= alpha q  with psi FP32 and r, q in FP16 storage: one
+// thread per (site, rhs) of the fine AoSoA layout, the same complex arithmetic
+// as mr_update_kernel<float>, the new r stored with its site's new scale.
+__global__ __launch_bounds__(kT) void mr_update_h_kernel(float2* __restrict__ psi, FineView<CRK_FORM_FP16S> r,
+                                                         FineView<CRK_FORM_FP16S> q,
+                                                         const double2* __restrict__ alpha, int64_t V, int nrhs) {
+  const int64_t Vp = pad_sites(V);
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= Vp * nrhs) return;
+  const int64_t rr = i / Vp, s = i % Vp;
+  if (s >= V) return;  // padding sites are never read
+  const double2 ad = alpha[rr];
+  const float2 a = make_float2(float(ad.x), float(ad.y));
+  float2 rv[12], qv[12];
+  r.load(rr, s, rv);
+  q.load(rr, s, qv);
+  float2* pp = psi + aidx(rr, 0, s, Vp, 12);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    float2 p = pp[c * kVL];
+    cfma(p, a, rv[c]);
+    pp[c * kVL] = p;
+    const float2 qa = cmul(a, qv[c]);
+    rv[c].x -= qa.x;
+    rv[c].y -= qa.y;
+  }
+  r.store(rr, s, rv);
+}
+
 // psi += alpha r ;  r -= alpha q    (rhs-outer layout, n entries per rhs)
 template <class T>
 __global__ __launch_bounds__(kT) void mr_update_kernel(typename C2<T>::t* __restrict__ psi,
@@ -224,6 +253,14 @@ void mr_update(int prec, void* psi, void* r, const void* q, const double2* alpha
   else
     hipLaunchKernelGGL(mr_update_kernel<float>, g, dim3(kT), 0, st, static_cast<float2*>(psi),
                        static_cast<float2*>(r), static_cast<const float2*>(q), alpha, n, nrhs, int(rhs_inner));
+  CRK_LAUNCH_CHECK();
+}
+
+void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st) {
+  if (V <= 0 || nrhs <= 0) return;
+  FineView<CRK_FORM_FP16S> rv(r, V, nrhs), qv(const_cast<void*>(q), V, nrhs);
+  hipLaunchKernelGGL(mr_update_h_kernel, dim3(ceil_div(pad_sites(V) * nrhs, kT)), dim3(kT), 0, st,
+                     static_cast<float2*>(psi), rv, qv, alpha, V, nrhs);
   CRK_LAUNCH_CHECK();
 }
 

@@ -265,25 +265,30 @@ int crk_mg_get_timing(crk_mg_t mg, int32_t level, double* out6) {
   });
 }
 
-static void host_level_import(Hierarchy* H, int l, int form, const double* in, void* dst, int nrhs, hipStream_t st) {
+// Fine vectors are FP32 for the FP16S form (the K-cycle's restriction and
+// prolongation work on FP32 fields) unless fine_storage asks for the form's
+// own storage (the fine operator of that form).
+static void host_level_import(Hierarchy* H, int l, int form, const double* in, void* dst, int nrhs, hipStream_t st,
+                              bool fine_storage = false) {
   const int64_t V = H->V(l);
   const int N = H->N(l);
   const size_t hb = sizeof(double2) * size_t(V) * N * nrhs;
   DevBuf h(hb);
   CRK_HIP(hipMemcpyAsync(h.p, in, hb, hipMemcpyHostToDevice, st));
   const int vf = form == CRK_FORM_FP64 ? CRK_FORM_FP64 : CRK_FORM_FP32;
-  if (l == 0) field_import(vf, h.as<double2>(), dst, H->fine_geo.pos.as<int>(), V, 12, nrhs, st);
+  if (l == 0) field_import(fine_storage ? form : vf, h.as<double2>(), dst, H->fine_geo.pos.as<int>(), V, 12, nrhs, st);
   else mg_import_coarse(H, l, h.as<double2>(), dst, vf == CRK_FORM_FP64, nrhs, st);
   CRK_HIP(hipStreamSynchronize(st));
 }
 
-static void host_level_export(Hierarchy* H, int l, int form, const void* src, double* out, int nrhs, hipStream_t st) {
+static void host_level_export(Hierarchy* H, int l, int form, const void* src, double* out, int nrhs, hipStream_t st,
+                              bool fine_storage = false) {
   const int64_t V = H->V(l);
   const int N = H->N(l);
   const size_t hb = sizeof(double2) * size_t(V) * N * nrhs;
   DevBuf h(hb);
   const int vf = form == CRK_FORM_FP64 ? CRK_FORM_FP64 : CRK_FORM_FP32;
-  if (l == 0) field_export(vf, src, h.as<double2>(), H->fine_geo.pos.as<int>(), V, 12, nrhs, st);
+  if (l == 0) field_export(fine_storage ? form : vf, src, h.as<double2>(), H->fine_geo.pos.as<int>(), V, 12, nrhs, st);
   else mg_export_coarse(H, l, src, vf == CRK_FORM_FP64, h.as<double2>(), nrhs, st);
   CRK_HIP(hipMemcpyAsync(out, h.p, hb, hipMemcpyDeviceToHost, st));
   CRK_HIP(hipStreamSynchronize(st));
@@ -295,14 +300,14 @@ int crk_mg_coarse_apply(crk_mg_t mg, int32_t level, int32_t form, const double* 
     Hierarchy* H = hier(mg);
     check_level(H, level, 0, H->nlev - 1);
     CRK_REQUIRE(form >= 0 && form <= 2, "unknown form");
-    CRK_REQUIRE(level > 0 || form != CRK_FORM_FP16S, "level 0 applies the fine operator in FP64 or FP32");
     CRK_REQUIRE(nrhs >= 1 && in && out, "bad arguments");
-    const size_t vb = (form == CRK_FORM_FP64 ? 16 : 8) * size_t(H->V(level)) * H->N(level) * nrhs;
+    const size_t vb = level == 0 ? fine_field_bytes(form, H->V(0), nrhs)
+                                 : (form == CRK_FORM_FP64 ? 16 : 8) * size_t(H->V(level)) * H->N(level) * nrhs;
     DevBuf a(vb), b(vb);
     hipStream_t st = H->stream;
-    host_level_import(H, level, form, in, a.p, nrhs, st);
+    host_level_import(H, level, form, in, a.p, nrhs, st, true);
     level_apply(H, level, form, a.p, b.p, nrhs, st);
-    host_level_export(H, level, form, b.p, out, nrhs, st);
+    host_level_export(H, level, form, b.p, out, nrhs, st, true);
     return CRK_OK;
   });
 }

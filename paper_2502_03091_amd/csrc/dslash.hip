@@ -467,10 +467,24 @@ __device__ __forceinline__ int tile_face_site(int i, int mu, int lmu) {
   return (i & lo) | (lmu << (2 * mu)) | ((i >> (2 * mu)) << (2 * mu + 2));
 }
 
-template <int MU, int SIGN>
-__device__ __forceinline__ void tile_hop(const float2 (*sp)[kTileSlots], int slot, const float2 (&u)[9],
+// Links are held in their storage type (half2 links take half the registers)
+// and widened per hop.
+template <int MU, int SIGN, class S>
+__device__ __forceinline__ void tile_hop(const float2 (*sp)[kTileSlots], int slot, const S (&us)[9],
                                          float2 (&acc)[12], float coef) {
-  float2 psi[12], h[6], g[6];
+  float2 psi[12], h[6], g[6], u[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    if constexpr (sizeof(S) == sizeof(float2)) {
+      u[e] = us[e];
+    } else {
+      // widened here on every use: the empty asm keeps the compiler from
+      // hoisting 144 widened registers out of the RHS loop
+      uint32_t bits = __builtin_bit_cast(uint32_t, us[e]);
+      asm volatile("" : "+v"(bits));
+      u[e] = __half22float2(__builtin_bit_cast(__half2, bits));
+    }
+  }
 #pragma unroll
   for (int c = 0; c < 12; ++c) psi[c] = sp[c][slot];
   project<MU, SIGN>(psi, h);
@@ -478,9 +492,9 @@ __device__ __forceinline__ void tile_hop(const float2 (*sp)[kTileSlots], int slo
   accumulate<MU, SIGN>(acc, g, coef);
 }
 
-__global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<CRK_FORM_FP32> in,
-                                                               FineView<CRK_FORM_FP32> out,
-                                                               GaugeView<CRK_FORM_FP32> U,
+template <int FORM>  // FP32, or FP16S storage (half spinors with a per-site scale, half links) in FP32 arithmetic
+__global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<FORM> in, FineView<FORM> out,
+                                                               GaugeView<FORM> U,
                                                                const int* __restrict__ nbr, int64_t V, int nrhs,
                                                                float diag, float4 hw, double* __restrict__ partial,
                                                                int swz) {
@@ -490,7 +504,7 @@ __global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<CRK_FORM
   const int64_t s = blk * kTile + l;
   // LDS slot of each neighbour, and the eight links
   int slot[8];
-  float2 u[8][9];
+  typename Prec<FORM>::store u[8][9];
 #pragma unroll
   for (int d = 0; d < 8; ++d) {
     const int mu = d >> 1, lmu = (l >> (2 * mu)) & 3;
@@ -498,7 +512,7 @@ __global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<CRK_FORM
     const bool inside = fwd ? lmu < 3 : lmu > 0;
     slot[d] = inside ? (fwd ? l + (1 << (2 * mu)) : l - (1 << (2 * mu))) : kTile + 64 * d + tile_face_index(l, mu);
     const int64_t y = fwd ? s : int64_t(nbr[int64_t(d) * V + s]);
-    const float2* p = U.data + aidx(mu, 0, y, U.Vp, 9);
+    const typename Prec<FORM>::store* p = U.data + aidx(mu, 0, y, U.Vp, 9);
 #pragma unroll
     for (int e = 0; e < 9; ++e) u[d][e] = p[e * kVL];
   }
@@ -537,7 +551,7 @@ __global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<CRK_FORM
     tile_hop<2, -1>(sp, slot[5], u[5], acc, hw.z);
     tile_hop<3, +1>(sp, slot[6], u[6], acc, hw.w);
     tile_hop<3, -1>(sp, slot[7], u[7], acc, hw.w);
-    {
+    if constexpr (FORM == CRK_FORM_FP32) {
       // streaming stores: the output is not read again by this launch, so it
       // does not displace from L2 the spinors that neighbouring blocks still
       // read as face neighbours
@@ -550,6 +564,8 @@ __global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<CRK_FORM
         v.y = acc[c].y;
         __builtin_nontemporal_store(v, reinterpret_cast<v2f*>(po + c * kVL));
       }
+    } else {
+      out.store(r, s, acc);  // rescaled to the site's largest component
     }
     if (partial != nullptr) {
       // the site's twelve terms in FP32 (the form's accumulation precision),
@@ -580,15 +596,16 @@ __global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<CRK_FORM
   }
 }
 
+template <int FORM>
 void launch_wilson_tile(const WilsonArgs& a, hipStream_t st) {
   CRK_REQUIRE(a.V % kTile == 0, "tile dslash: the volume must be a multiple of 4^4");
   const int64_t nblk = a.V / kTile;
   if (nblk > 0x7fffffff) fail(CRK_EINVAL, "dslash grid too large");
-  FineView<CRK_FORM_FP32> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
-  GaugeView<CRK_FORM_FP32> U{static_cast<const float2*>(a.gauge), pad_sites(a.V)};
+  FineView<FORM> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
+  GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), pad_sites(a.V)};
   const float4 hw = make_float4(float(a.hw[0]), float(a.hw[1]), float(a.hw[2]), float(a.hw[3]));
-  hipLaunchKernelGGL(wilson_tile_kernel, dim3(unsigned(nblk)), dim3(kTile), 0, st, in, out, U, a.nbr, a.V, a.nrhs,
-                     float(a.diag), hw, a.partial, a.swizzle);
+  hipLaunchKernelGGL(wilson_tile_kernel<FORM>, dim3(unsigned(nblk)), dim3(kTile), 0, st, in, out, U, a.nbr, a.V,
+                     a.nrhs, float(a.diag), hw, a.partial, a.swizzle);
   CRK_LAUNCH_CHECK();
 }
 }  // namespace
@@ -600,7 +617,8 @@ void wilson_apply(const WilsonArgs& a_in, hipStream_t st) {
   CRK_REQUIRE(a_in.in != a_in.out, "dslash: in and out must not alias");
   const WilsonArgs& a = a_in;
   const int R = a.rhs_per_thread < a.nrhs ? a.rhs_per_thread : a.nrhs;
-  if (a.form == CRK_FORM_FP32 && a.tile4) { launch_wilson_tile(a, st); return; }
+  if (a.tile4 && a.form == CRK_FORM_FP32) { launch_wilson_tile<CRK_FORM_FP32>(a, st); return; }
+  if (a.tile4 && a.form == CRK_FORM_FP16S) { launch_wilson_tile<CRK_FORM_FP16S>(a, st); return; }
   if (a.form == CRK_FORM_FP32) { launch_wilson_rhsloop<CRK_FORM_FP32>(a, st); return; }
   if (a.nrhs <= kDirMaxRhs && a.form == CRK_FORM_FP64) { launch_wilson_dir<CRK_FORM_FP64>(a, st); return; }
   switch (a.form) {

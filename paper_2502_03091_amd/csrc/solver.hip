@@ -130,6 +130,30 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs
   level_prolong(H, l, form, nx.x.p, eout, nrhs, false, st);
   if (p.nu_post <= 0) return;
   // MR on D_l e = r, starting from e:  rho = r - D e ; q = D rho ; e += alpha rho ; rho -= alpha q
+  if (l == 0 && form == CRK_FORM_FP16S) {
+    // FP16-storage form on the fine level: e (the cycle's output) stays FP32,
+    // the MR residual rho and q = D rho are held in FP16 storage (one scale per
+    // site and RHS) and the fine operator reads and writes them in that form.
+    const int64_t V0 = H->V(0);
+    const FieldShape f0 = shape(H, 0, nrhs);
+    const size_t fb32 = vec_bytes(form) * size_t(f0.total());
+    void* q32 = w.fw.q.p;
+    void* r32 = w.fw.rho.p;
+    level_apply(H, 0, CRK_FORM_FP32, eout, q32, nrhs, st);
+    CRK_HIP(hipMemcpyAsync(r32, rin, fb32, hipMemcpyDeviceToDevice, st));
+    field_axpby(CRK_FORM_FP32, q32, r32, -1.0, 1.0, f0.total(), st);
+    void* rhoh = w.fw.q.p;  // q32 is no longer needed
+    void* qh = w.fw.rho.p;  // nor is r32 once converted (stream order)
+    field_convert(CRK_FORM_FP32, r32, CRK_FORM_FP16S, rhoh, V0, 12, nrhs, st);
+    GcrScalars& s0 = w.ow.s;
+    for (int it = 0; it < p.nu_post; ++it) {
+      level_apply(H, 0, CRK_FORM_FP16S, rhoh, qh, nrhs, st, s0.partial);
+      reduce_partials(s0.partial, wilson_partial_blocks(V0), nrhs, 3, s0.sums3, st);
+      mr_alpha(s0.sums3, nrhs, s0.a, st);
+      mr_update_fine_h(eout, rhoh, qh, s0.a, V0, nrhs, st);
+    }
+    return;
+  }
   const FieldShape f = shape(H, l, nrhs);
   const size_t fb = vec_bytes(form) * size_t(f.total());
   void *rho, *q;

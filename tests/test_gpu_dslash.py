@@ -134,7 +134,7 @@ def test_hierarchy_fine_operator_4x4_blocks(crk, dims):
     for nrhs in (1, 12):
         psi = synth.gaussian_vectors(nrhs, V, 12, config=13, level=nrhs)
         ref = as_fields(op.apply(as_columns(psi)))
-        for form, tol in ((crk.FORM_FP64, 1e-12), (crk.FORM_FP32, 2e-6)):
+        for form, tol in ((crk.FORM_FP64, 1e-12), (crk.FORM_FP32, 2e-6), (crk.FORM_FP16S, TOL[2])):
             out = H.coarse_apply(0, psi, form=form)
             err = np.abs(out - ref).max() / np.abs(ref).max()
             print(dims, nrhs, form, err, flush=True)

@@ -67,6 +67,27 @@ def test_c1_reduced_precision_reaches_fp64_residual(crk, c1, form):
         assert np.linalg.norm(res) <= 1e-10 * np.linalg.norm(b[r])
 
 
+@pytest.mark.parametrize("form", [1, 2])
+def test_4x4_blocks_reduced_precision_reaches_fp64_residual(crk, form):
+    """4^4 blocks (block-staged fine operator in the K-cycle; in the FP16S form its
+    post-smoother residuals are held in FP16 storage) still reach the FP64 residual."""
+    dims, block = [8, 4, 8, 4], [4, 4, 4, 4]
+    V = int(np.prod(dims))
+    U = synth.gauge_field(dims, 0.3, 1, config=9)
+    lat = crk.Lattice(dims, 0.1, 1.0)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[16], k=[8], block=[block], n_smooth=[20], setup_form=1)
+    b = synth.gaussian_rhs(3, V, config=9)
+    x, info = H.solve(b, form=form, nu_post=4, raise_on_noconv=False)
+    print("4^4 blocks form", form, info, flush=True)
+    assert info["converged"] and info["true_rel_resid"] <= 1e-10
+    op = WilsonOp(U, dims, 0.1, 1.0)
+    res = b - as_fields(op.apply(as_columns(x)))
+    for r in range(3):
+        assert np.linalg.norm(res[r]) <= 1e-10 * np.linalg.norm(b[r])
+    H.close()
+
+
 def test_multi_rhs_matches_single_rhs(crk, c1):
     """Each RHS in a batch gets the same result as alone (batch-invariant kernels)."""
     lat, H, op, ref = c1
