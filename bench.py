@@ -369,7 +369,7 @@ def workload_aniso16(crk, args):
         "true_rel_resid": max(i["true_rel_resid"] for i in infos),
         "converged": all(i["converged"] for i in infos),
         "roofline": {
-            "kernel": "wilson_tile_kernel (FP32, 48 RHS, 16^3x32 in 4^4 blocks, MR setup sweep)",
+            "kernel": "wilson_tile_kernel<FP32> (48 RHS, 16^3x32 in 4^4 blocks, MR setup sweep)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
             "algorithmic_bytes_per_launch": alg,
