@@ -6,12 +6,16 @@
 //
 // Each (1 -+ gamma_mu) has rank 2, so every hop projects the neighbour spinor
 // to a half spinor (2 spins x 3 colours), multiplies by the SU(3) link and
-// rebuilds the lower spins from the upper ones.  One thread owns one site and
-// R right-hand sides: the eight links of the site are loaded once and reused
-// for all R spinors, and neighbour addresses come from a per-site table so any
-// site order (lexicographic or block-major) uses the same kernel.  Optionally
-// the kernel also emits per-workgroup partial sums <Dr, r> and <Dr, Dr> for
-// the minimal-residual smoother, so no separate pass over the fields is needed.
+// rebuilds the lower spins from the upper ones.  Neighbour addresses come
+// from a per-site table, so any site order (lexicographic or block-major) can
+// be served.  Kernels: wilson_tile_kernel (the fine level of a hierarchy with
+// 4^4 blocks, FP32 and FP16 storage: a block and its faces staged in LDS),
+// wilson_rhsloop_kernel (FP32, any order: one thread per site, links in
+// registers across the RHS loop), wilson_dir_kernel (FP64: one wavefront per
+// direction, partial spinors exchanged through LDS) and wilson_kernel<FORM, R>
+// (R right-hand sides per thread, the remaining cases).  Optionally a launch
+// also emits per-wavefront partial sums <Dr, r> and <Dr, Dr> for the
+// minimal-residual smoother, so no separate pass over the fields is needed.
 #include "field.h"
 #include "kernels.h"
 
@@ -440,8 +444,9 @@ void launch_wilson(const WilsonArgs& a, hipStream_t st) {
 
 
 // ---------------------------------------------------------------- tile kernel
-// FP32 variant for the fine level of a hierarchy with 4^4 blocks, whose device
-// order is block-major: one workgroup owns one block (256 consecutive
+// Variant for the fine level of a hierarchy with 4^4 blocks (FP32, or FP16
+// storage with FP32 arithmetic), whose device order is block-major: one
+// workgroup owns one block (256 consecutive
 // positions, one thread per site) and keeps the site's eight links in
 // registers for the whole loop over right-hand sides.  Per RHS the workgroup
 // stages the block's 256 spinors and the 512 spinors just outside its eight
