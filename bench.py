@@ -67,18 +67,29 @@ def dslash_bytes(V, nrhs, form):
 def measured_traffic():
     """HBM bytes per 48-RHS smoother launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE counters, or None when the kernel source changed since they were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "wilson_tile_fp32_16x16x16x32_48rhs.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except OSError:
         return None
+    return rec["traffic_bytes_per_launch"] if kernel_source_hash() == rec["kernel_source_sha256"] else None
+
+
+def kernel_source_hash():
+    """sha256 of the dslash sources with comments and blank lines removed (a comment
+    edit does not change the kernel the counters were taken on)."""
+    import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("dslash.hip", "field.h"):
-        with open(os.path.join(ROOT, "paper_2502_03091_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["kernel_source_sha256"] else None
+        with open(os.path.join(ROOT, "paper_2502_03091_amd", "csrc", name)) as f:
+            text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code.strip():
+                h.update(code.encode() + b"\n")
+    return h.hexdigest()
 
 
 def cpu_baseline(U, m0, V):
