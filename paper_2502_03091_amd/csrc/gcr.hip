@@ -12,6 +12,8 @@
 // final sums).  Fields are addressed as entry e of rhs r at r*rs + e*es.
 #include "gcr.h"
 
+#include <algorithm>
+
 namespace crk {
 
 namespace {
@@ -118,6 +120,60 @@ __global__ __launch_bounds__(64) void multidot_inner_kernel(const C* __restrict_
     double t = 0;
     for (int k = 0; k < 64; ++k) t += sh[k][l];
     partial[(c * nrhs + r) * (2 * kMaxBasis) + 2 * j0 + l] = t;
+  }
+}
+
+// Same sums for rhs-inner fields with a workgroup per (chunk, group of up to
+// 16 RHS, group of kInnerGroup directions): thread (l, r) with r fastest, so a
+// wavefront reads contiguous RHS runs of consecutive entries.  Each (l, r)
+// thread adds entries l, l + 64, ... of the chunk in order and the 64 lane
+// sums of an RHS are added in lane order, exactly as in multidot_inner_kernel,
+// so the partials are the same numbers.
+constexpr int kInnerGroup = 4;
+constexpr int kInnerRhs = 16;
+
+template <class C>
+__global__ __launch_bounds__(64 * kInnerRhs) void multidot_inner_rg_kernel(const C* __restrict__ Wb, int64_t fstride,
+                                                                           int nj, const C* __restrict__ w, int64_t n,
+                                                                           int nrhs, double* __restrict__ partial) {
+  __shared__ double sh[kInnerRhs][64][2 * kInnerGroup + 1];
+  const int rg = min(kInnerRhs, nrhs - int(blockIdx.y) * kInnerRhs);  // RHS in this workgroup
+  const int t = threadIdx.x;
+  const int rl = t % rg, l = t / rg;
+  const int r = int(blockIdx.y) * kInnerRhs + rl;
+  const int j0 = blockIdx.z * kInnerGroup;
+  const int64_t c = blockIdx.x;
+  const C* Wg[kInnerGroup];
+#pragma unroll
+  for (int g = 0; g < kInnerGroup; ++g) Wg[g] = Wb + int64_t(min(j0 + g, nj - 1)) * fstride;
+  if (l < 64) {
+    double acc[2 * kInnerGroup];
+#pragma unroll
+    for (int q = 0; q < 2 * kInnerGroup; ++q) acc[q] = 0;
+    for (int i = 0; i < kInnerChunk / 64; ++i) {
+      const int64_t e = c * kInnerChunk + l + 64 * i;
+      if (e >= n) break;
+      const int64_t idx = e * nrhs + r;
+      const C y = w[idx];
+      C x[kInnerGroup];
+#pragma unroll
+      for (int g = 0; g < kInnerGroup; ++g) x[g] = Wg[g][idx];
+#pragma unroll
+      for (int g = 0; g < kInnerGroup; ++g) {
+        acc[2 * g] += double(x[g].x) * y.x + double(x[g].y) * y.y;
+        acc[2 * g + 1] += double(x[g].x) * y.y - double(x[g].y) * y.x;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * kInnerGroup; ++q) sh[rl][l][q] = acc[q];
+  }
+  __syncthreads();
+  const int nq = 2 * min(kInnerGroup, nj - j0);
+  if (t < rg * nq) {
+    const int rr = t / nq, q = t % nq;
+    double s = 0;
+    for (int k = 0; k < 64; ++k) s += sh[rr][k][q];
+    partial[(c * nrhs + int(blockIdx.y) * kInnerRhs + rr) * (2 * kMaxBasis) + 2 * j0 + q] = s;
   }
 }
 
@@ -440,7 +496,17 @@ void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* 
     const unsigned ng = unsigned((nc + kDotGroup - 1) / kDotGroup);
     const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs), ng), gi = g;
     const void* Wj = static_cast<const char*>(W) + esz * size_t(j0) * size_t(fstride);
-    if (f.es != 1 && prec == CRK_FORM_FP64)
+    const bool rhs_inner = f.es != 1 && f.rs == 1 && f.es == f.nrhs;
+    const dim3 grg = dim3(unsigned(nch), unsigned((f.nrhs + kInnerRhs - 1) / kInnerRhs),
+                          unsigned((nc + kInnerGroup - 1) / kInnerGroup));
+    const dim3 brg = dim3(unsigned(64 * std::min(f.nrhs, kInnerRhs)));
+    if (rhs_inner && prec == CRK_FORM_FP64)
+      hipLaunchKernelGGL(multidot_inner_rg_kernel<double2>, grg, brg, 0, st, static_cast<const double2*>(Wj),
+                         fstride, nc, static_cast<const double2*>(w), f.n, f.nrhs, partial);
+    else if (rhs_inner)
+      hipLaunchKernelGGL(multidot_inner_rg_kernel<float2>, grg, brg, 0, st, static_cast<const float2*>(Wj),
+                         fstride, nc, static_cast<const float2*>(w), f.n, f.nrhs, partial);
+    else if (f.es != 1 && prec == CRK_FORM_FP64)
       hipLaunchKernelGGL(multidot_inner_kernel<double2>, gi, dim3(64), 0, st, static_cast<const double2*>(Wj), fstride,
                          nc, static_cast<const double2*>(w), f.n, f.nrhs, f.rs, f.es, partial);
     else if (f.es != 1)
