@@ -69,6 +69,65 @@ __global__ __launch_bounds__(kT) void dot_partial_kernel(const typename C2<T>::t
   }
 }
 
+// dot_partial_kernel for rhs-inner fields (entry e of rhs r at e*nrhs + r):
+// workgroup per (chunk of kInnerChunk entries, group of up to 16 RHS), thread
+// (l, r) with r fastest, so a wavefront reads contiguous RHS runs; thread (l, r)
+// adds entries l, l + 64, ... of the chunk, the 64 lane sums of an RHS are
+// added in lane order (independent of how many RHS share the field).
+constexpr int kDotRhs = 16;
+
+template <class T>
+__global__ __launch_bounds__(64 * kDotRhs) void dot_partial_rg_kernel(const typename C2<T>::t* __restrict__ a,
+                                                                      const typename C2<T>::t* __restrict__ b,
+                                                                      int64_t n, int nrhs,
+                                                                      double* __restrict__ partial) {
+  __shared__ double sh[kDotRhs][64][3];
+  const int rg = min(kDotRhs, nrhs - int(blockIdx.y) * kDotRhs);
+  const int t = threadIdx.x;
+  const int rl = t % rg, l = t / rg;
+  const int r = int(blockIdx.y) * kDotRhs + rl;
+  if (l < 64) {
+    double v0 = 0, v1 = 0, v2 = 0;
+    for (int i = 0; i < kInnerChunk / 64; ++i) {
+      const int64_t e = int64_t(blockIdx.x) * kInnerChunk + l + 64 * i;
+      if (e >= n) break;
+      const int64_t idx = e * nrhs + r;
+      const auto x = a[idx];
+      const auto y = b ? b[idx] : x;
+      v0 += double(x.x) * y.x + double(x.y) * y.y;
+      v1 += double(x.x) * y.y - double(x.y) * y.x;
+      v2 += double(x.x) * x.x + double(x.y) * x.y;
+    }
+    sh[rl][l][0] = v0;
+    sh[rl][l][1] = v1;
+    sh[rl][l][2] = v2;
+  }
+  __syncthreads();
+  if (t < 3 * rg) {
+    const int rr = t / 3, v = t % 3;
+    double s = 0;
+    for (int k = 0; k < 64; ++k) s += sh[rr][k][v];
+    partial[(int64_t(blockIdx.x) * nrhs + int(blockIdx.y) * kDotRhs + rr) * 3 + v] = s;
+  }
+}
+
+// Chunk partials of (<a, b>, ||a||^2) for any layout (rhs-inner: the grouped kernel).
+template <class T>
+void launch_dot_partial(const void* a, const void* b, int64_t n, int nrhs, int64_t rs, int64_t es, int64_t chunk,
+                        int64_t nch, double* partial, hipStream_t st) {
+  using CT = typename C2<T>::t;
+  if (es != 1 && rs == 1 && es == nrhs && chunk == kInnerChunk) {
+    const dim3 g = dim3(unsigned(nch), unsigned((nrhs + kDotRhs - 1) / kDotRhs));
+    hipLaunchKernelGGL(dot_partial_rg_kernel<T>, g, dim3(unsigned(64 * (nrhs < kDotRhs ? nrhs : kDotRhs))), 0, st,
+                       static_cast<const CT*>(a), static_cast<const CT*>(b), n, nrhs, partial);
+  } else {
+    const dim3 g = dim3(unsigned(nch), unsigned(nrhs));
+    hipLaunchKernelGGL(dot_partial_kernel<T>, g, dim3(kT), 0, st, static_cast<const CT*>(a),
+                       static_cast<const CT*>(b), n, nrhs, rs, es, chunk, partial);
+  }
+  CRK_LAUNCH_CHECK();
+}
+
 // Sum partial[nchunk][nrhs][nv] over chunks in a fixed order; out[r][nv].
 __global__ __launch_bounds__(kT) void reduce_partial_kernel(const double* __restrict__ partial, int64_t nchunk,
                                                             int nrhs, int nv, double* __restrict__ out) {
@@ -206,14 +265,8 @@ int64_t rhs_dot_launch(int prec, const void* a, const void* b, int64_t n, int nr
   const int64_t chunk = es != 1 ? int64_t(kInnerChunk) : chunk_for(n);
   const int64_t nch = (n + chunk - 1) / chunk;
   if (nrhs <= 0 || n <= 0) return nch;
-  const dim3 g = dim3(unsigned(nch), unsigned(nrhs));
-  if (prec == CRK_FORM_FP64)
-    hipLaunchKernelGGL(dot_partial_kernel<double>, g, dim3(kT), 0, st, static_cast<const double2*>(a),
-                       static_cast<const double2*>(b), n, nrhs, rs, es, chunk, partial);
-  else
-    hipLaunchKernelGGL(dot_partial_kernel<float>, g, dim3(kT), 0, st, static_cast<const float2*>(a),
-                       static_cast<const float2*>(b), n, nrhs, rs, es, chunk, partial);
-  CRK_LAUNCH_CHECK();
+  if (prec == CRK_FORM_FP64) launch_dot_partial<double>(a, b, n, nrhs, rs, es, chunk, nch, partial, st);
+  else launch_dot_partial<float>(a, b, n, nrhs, rs, es, chunk, nch, partial, st);
   return nch;
 }
 
@@ -223,14 +276,8 @@ void rhs_dot(int prec, const void* a, const void* b, int64_t n, int nrhs, int64_
   // rhs-inner (coarse) fields: one element per thread, many small workgroups
   const int64_t chunk = es != 1 ? int64_t(kInnerChunk) : chunk_for(n);
   const int64_t nch = (n + chunk - 1) / chunk;
-  const dim3 g = dim3(unsigned(nch), unsigned(nrhs));
-  if (prec == CRK_FORM_FP64)
-    hipLaunchKernelGGL(dot_partial_kernel<double>, g, dim3(kT), 0, st, static_cast<const double2*>(a),
-                       static_cast<const double2*>(b), n, nrhs, rs, es, chunk, partial);
-  else
-    hipLaunchKernelGGL(dot_partial_kernel<float>, g, dim3(kT), 0, st, static_cast<const float2*>(a),
-                       static_cast<const float2*>(b), n, nrhs, rs, es, chunk, partial);
-  CRK_LAUNCH_CHECK();
+  if (prec == CRK_FORM_FP64) launch_dot_partial<double>(a, b, n, nrhs, rs, es, chunk, nch, partial, st);
+  else launch_dot_partial<float>(a, b, n, nrhs, rs, es, chunk, nch, partial, st);
   reduce_partials(partial, nch, nrhs, 3, out3, st);
 }
 

@@ -382,6 +382,83 @@ __global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ z, C* 
   if (threadIdx.x == 0) partial[int64_t(blockIdx.x) * nrhs + r] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// update_fused_kernel for rhs-inner fields: workgroup per (chunk, group of up
+// to 16 RHS), thread (l, r) with r fastest (coalesced), entries l, l + 64, ...
+// of the chunk per thread; every sum over lanes runs in lane order, so an RHS's
+// numbers do not depend on how many RHS share the field.
+template <class C>
+__global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __restrict__ z, C* __restrict__ w,
+                                                                         C* __restrict__ x, C* __restrict__ res,
+                                                                         const double* __restrict__ dpart,
+                                                                         int64_t dnch, const int* __restrict__ active,
+                                                                         int* __restrict__ breakdown, int64_t n,
+                                                                         int nrhs, double* __restrict__ partial) {
+  __shared__ double sh[kInnerRhs][64][3];
+  __shared__ double scal[kInnerRhs][3];
+  using T = decltype(C::x);
+  const int rg = min(kInnerRhs, nrhs - int(blockIdx.y) * kInnerRhs);
+  const int t = threadIdx.x;
+  const int rl = t % rg, l = t / rg;
+  const int r = int(blockIdx.y) * kInnerRhs + rl;
+  // (<w, r>, ||w||^2) of each RHS from the dot partials
+  if (l < 64) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int64_t c = l; c < dnch; c += 64) {
+      const double* p = dpart + (c * nrhs + r) * 3;
+      s0 += p[0];
+      s1 += p[1];
+      s2 += p[2];
+    }
+    sh[rl][l][0] = s0;
+    sh[rl][l][1] = s1;
+    sh[rl][l][2] = s2;
+  }
+  __syncthreads();
+  if (t < 3 * rg) {
+    const int rr = t / 3, v = t % 3;
+    double a = 0;
+    for (int k = 0; k < 64; ++k) a += sh[rr][k][v];
+    scal[rr][v] = a;
+  }
+  __syncthreads();
+  double acc = 0;
+  if (l < 64) {
+    const double ww = scal[rl][2], nw = sqrt(ww);
+    const bool act0 = active[r] != 0;
+    const bool ok = act0 && ww > 0.0 && isfinite(nw);
+    if (blockIdx.x == 0 && l == 0 && breakdown) breakdown[r] = act0 && !ok;
+    const T sc = T(ok ? 1.0 / nw : 0.0);
+    const C ar = ok ? mk<C>(T(scal[rl][0] / nw), T(scal[rl][1] / nw)) : mk<C>(T(0), T(0));
+    for (int i = 0; i < kInnerChunk / 64; ++i) {
+      const int64_t e = int64_t(blockIdx.x) * kInnerChunk + l + 64 * i;
+      if (e >= n) break;
+      const int64_t idx = e * nrhs + r;
+      const C zn = cscale(z[idx], sc), wn = cscale(w[idx], sc);
+      z[idx] = zn;
+      w[idx] = wn;
+      C rr = res[idx];
+      if (ok) {
+        C xx = x[idx];
+        cfma(xx, ar, zn);
+        x[idx] = xx;
+        const C aw = cmul(ar, wn);
+        rr.x -= aw.x;
+        rr.y -= aw.y;
+        res[idx] = rr;
+      }
+      acc += double(rr.x) * rr.x + double(rr.y) * rr.y;
+    }
+  }
+  __syncthreads();  // sh is reused
+  if (l < 64) sh[rl][l][0] = acc;
+  __syncthreads();
+  if (t < rg) {
+    double a = 0;
+    for (int k = 0; k < 64; ++k) a += sh[t][k][0];
+    partial[int64_t(blockIdx.x) * nrhs + int(blockIdx.y) * kInnerRhs + t] = a;
+  }
+}
+
 // rn2[r] = sum of partials (wavefront g adds chunks g, g + 4, ... in order, then
 // the four sums in a fixed order); convergence bookkeeping of an inner solve.
 __global__ __launch_bounds__(kT) void check_kernel(const double* __restrict__ partial, int64_t nch, int nrhs,
@@ -571,6 +648,21 @@ void gcr_update_fused(int prec, void* z, void* w, void* x, void* r, const double
                       hipStream_t st) {
   const int64_t chunk = chunk_for_shape(f.n, f.es != 1), nch = shape_chunks(f);
   const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
+  if (f.es != 1 && f.rs == 1 && f.es == f.nrhs) {
+    const dim3 grg = dim3(unsigned(nch), unsigned((f.nrhs + kInnerRhs - 1) / kInnerRhs));
+    const dim3 brg = dim3(unsigned(64 * std::min(f.nrhs, kInnerRhs)));
+    if (prec == CRK_FORM_FP64)
+      hipLaunchKernelGGL(update_fused_rg_kernel<double2>, grg, brg, 0, st, static_cast<double2*>(z),
+                         static_cast<double2*>(w), static_cast<double2*>(x), static_cast<double2*>(r), dpart, dnch,
+                         active, breakdown, f.n, f.nrhs, partial);
+    else
+      hipLaunchKernelGGL(update_fused_rg_kernel<float2>, grg, brg, 0, st, static_cast<float2*>(z),
+                         static_cast<float2*>(w), static_cast<float2*>(x), static_cast<float2*>(r), dpart, dnch,
+                         active, breakdown, f.n, f.nrhs, partial);
+    CRK_LAUNCH_CHECK();
+    if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
+    return;
+  }
   if (prec == CRK_FORM_FP64)
     hipLaunchKernelGGL(update_fused_kernel<double2>, g, dim3(kT), 0, st, static_cast<double2*>(z),
                        static_cast<double2*>(w), static_cast<double2*>(x), static_cast<double2*>(r), dpart, dnch,
