@@ -41,7 +41,7 @@ int64_t chunk_for_shape(int64_t n, bool inner) { return inner ? int64_t(kInnerCh
 // stored directions, so a thread keeps 2*kDotGroup sums and issues the loads
 // of all its group's directions together.  The last group repeats the last
 // direction for its unused members (in-bounds loads, sums not stored).
-constexpr int kDotGroup = 8;
+constexpr int kDotGroup = 16;
 
 // partial[chunk][r][2*j + {0,1}] = chunk sum of conj(W_j) w
 template <class C>
