@@ -40,7 +40,7 @@ import synth  # noqa: E402
 DIMS = [16, 16, 16, 32]
 XI, EPS, N_APE, CONFIG = 3.5, 0.2, 3, 2
 M_PRIME, K, BLOCK, N_SMOOTH, NRHS = 48, 24, [4, 4, 4, 4], 60, 10
-SOLVE = dict(nu_post=8, tau=0.1, restart=16, max_iter=500)
+SOLVE = dict(nu_post=8, tau=0.1, restart=8, max_iter=500)
 ISO = dict(xi=1.0, eps=0.25, n_ape=3, config=4)
 HBM_PEAK_GBPS = 8000.0
 METRIC = "MG setup s & dslash GB/s; solves/s, p50/p99 at 1e-10 vs plain FP64 form"
