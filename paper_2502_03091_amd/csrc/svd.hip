@@ -127,7 +127,9 @@ __device__ __forceinline__ void pair_of(int round, int k, int mm, int& p, int& q
   if (p > q) { int t = p; p = q; q = t; }
 }
 
-__global__ __launch_bounds__(kThreads) void jacobi_kernel(const double2* __restrict__ Gin, double* __restrict__ lam,
+constexpr int kJacobiThreads = 576;  // one 2x2 block update per thread for m' = 48 (24 x 24 pairs)
+
+__global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(const double2* __restrict__ Gin, double* __restrict__ lam,
                                                           double2* __restrict__ Vout, int m, int max_sweeps,
                                                           double tol, int* __restrict__ sweeps_out) {
   extern __shared__ double2 sh[];
@@ -388,12 +390,12 @@ void chiral_svd(const ChiralSrc& s, int src_is_double, const void* base, const d
     const unsigned npair = unsigned(2 * b.nblocks);
     if (src_is_double) launch_gram<double2>(b, base, inv_norm, w.G, st);
     else launch_gram<float2>(b, base, inv_norm, w.G, st);
-    hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kThreads), jacobi_lds(m), st, w.G, w.lam, w.V, m, 40, tol,
+    hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kJacobiThreads), jacobi_lds(m), st, w.G, w.lam, w.V, m, 40, tol,
                        w.sweeps);
     CRK_LAUNCH_CHECK();
     if (src_is_double) launch_rotate<double2>(b, base, inv_norm, w.V, w.B, w.G2, st);
     else launch_rotate<float2>(b, base, inv_norm, w.V, w.B, w.G2, st);
-    hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kThreads), jacobi_lds(m), st, w.G2, w.lam2, w.W, m, 40, tol,
+    hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kJacobiThreads), jacobi_lds(m), st, w.G2, w.lam2, w.W, m, 40, tol,
                        w.sweeps ? w.sweeps + npair : nullptr);
     CRK_LAUNCH_CHECK();
     hipLaunchKernelGGL(finalize_kernel, dim3(npair), dim3(kThreads), lds, st, m, nr, k, w.V, w.W, w.lam2, w.B,
