@@ -8,8 +8,9 @@
 //   Y_{-mu}(j) = sigma3 Y_{+mu}(j-mu)^dag sigma3          (gamma5-hermiticity of D)
 // One workgroup per (coarse site, part) with part 0 = X and parts 1..4 = Y_{+mu}.
 // For each fine site the hop results T = sum H P(y) (12 x 2k) are formed by
-// threads (column, colour) from the half-spinor projection, staged in LDS, and
-// contracted with P(x)^dag into per-thread register tiles of the 2k x 2k output.
+// threads (site of a batch, column), each for all three colours, from the
+// half-spinor projection, staged in LDS, and contracted with P(x)^dag into
+// per-thread register tiles of the 2k x 2k output.
 // Coarse links are stored per coarse site as 9 column-major 2k x 2k blocks:
 // index 0 = X, 1 + 2mu = Y_{+mu}, 2 + 2mu = Y_{-mu}.
 #include "field.h"
@@ -84,41 +85,43 @@ __device__ __forceinline__ void load_pcol(const GalerkinArgs& A, int64_t y, int 
 }
 
 template <int MU, int SIGN>
-__device__ __forceinline__ void add_hop(const GalerkinArgs& A, int64_t x, int64_t y, int col, int a,
-                                        double2 (&t)[4]) {
+__device__ __forceinline__ void add_hop(const GalerkinArgs& A, int64_t x, int64_t y, int col, double2 (&t)[3][4]) {
   double2 s[4][3], h[2][3];
   load_pcol(A, y, col, s);
   project_col<MU, SIGN>(s, h);
   const int64_t Vp = pad_sites(A.V);
-  double2 g0 = make_double2(0, 0), g1 = make_double2(0, 0);
 #pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    if constexpr (SIGN > 0) {
-      const double2 u = A.gauge[aidx(MU, 3 * a + b, x, Vp, 9)];
-      cfma(g0, u, h[0][b]);
-      cfma(g1, u, h[1][b]);
-    } else {
-      const double2 u = A.gauge[aidx(MU, 3 * b + a, y, Vp, 9)];
-      cfmac(g0, u, h[0][b]);
-      cfmac(g1, u, h[1][b]);
+  for (int a = 0; a < 3; ++a) {
+    double2 g0 = make_double2(0, 0), g1 = make_double2(0, 0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if constexpr (SIGN > 0) {
+        const double2 u = A.gauge[aidx(MU, 3 * a + b, x, Vp, 9)];
+        cfma(g0, u, h[0][b]);
+        cfma(g1, u, h[1][b]);
+      } else {
+        const double2 u = A.gauge[aidx(MU, 3 * b + a, y, Vp, 9)];
+        cfmac(g0, u, h[0][b]);
+        cfmac(g1, u, h[1][b]);
+      }
     }
+    rebuild<MU, SIGN>(t[a], g0, g1, A.hw[MU]);
   }
-  rebuild<MU, SIGN>(t, g0, g1, A.hw[MU]);
 }
 
 template <int MU, int SIGN>
-__device__ __forceinline__ void maybe_hop(const GalerkinArgs& A, int64_t x, int64_t j, int col, int a, int part,
-                                          double2 (&t)[4]) {
+__device__ __forceinline__ void maybe_hop(const GalerkinArgs& A, int64_t x, int64_t j, int col, int part,
+                                          double2 (&t)[3][4]) {
   const int64_t y = A.nbr[int64_t(2 * MU + (SIGN > 0 ? 0 : 1)) * A.V + x];
   const bool inside = (y / A.nb) == j;
-  if (part == 0 ? inside : (SIGN > 0 && MU == part - 1 && !inside)) add_hop<MU, SIGN>(A, x, y, col, a, t);
+  if (part == 0 ? inside : (SIGN > 0 && MU == part - 1 && !inside)) add_hop<MU, SIGN>(A, x, y, col, t);
 }
 
 // The block's contributing sites (all for X, the +mu face for Y_{+mu}) are
 // listed in site order and taken kSiteBatch at a time: the hop results of a
 // batch are formed together, then added site by site in list order, so every
 // output has the same summation order as a site-by-site loop.
-constexpr int kSiteBatch = 4;
+constexpr int kSiteBatch = 5;
 
 template <int TI>
 __global__ __launch_bounds__(kT) void galerkin_kernel(GalerkinArgs A) {
@@ -170,35 +173,44 @@ __global__ __launch_bounds__(kT) void galerkin_kernel(GalerkinArgs A) {
       const int l = list[b0 + sb];
       Pc[sb][c][col] = A.P[((2 * j + beta) * k + i) * int64_t(A.nr) + int64_t(c) * A.nb + l];
     }
-    for (int e = threadIdx.x; e < ns * 3 * N; e += blockDim.x) {
-      const int sb = e / (3 * N), col = (e / 3) % N, a = e % 3;
+    // one thread per (site, column) forms the column's three colour rows, so
+    // P(y) is read once per hop for all of them
+    for (int e = threadIdx.x; e < ns * N; e += blockDim.x) {
+      const int sb = e % ns, col = e / ns;  // the batch's sites side by side: their P(y) rows are adjacent
       const int l = list[b0 + sb];
       const int64_t x = j * A.nb + l;
-      double2 t[4];
+      double2 t[3][4];
 #pragma unroll
-      for (int sp = 0; sp < 4; ++sp) t[sp] = make_double2(0, 0);
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) t[a][sp] = make_double2(0, 0);
       if (part == 0) {
         // site term: (m0 + sum w) P(x)
         const int beta = col / k, i = col % k;
         const double2* p = A.P + ((2 * j + beta) * k + i) * int64_t(A.nr) + l;
-        const double2 v0 = cscale(p[int64_t(a) * A.nb], A.diag);
-        const double2 v1 = cscale(p[int64_t(3 + a) * A.nb], A.diag);
         const double2 z = make_double2(0, 0);
-        t[0] = beta == 0 ? v0 : z;
-        t[1] = beta == 0 ? v1 : z;
-        t[2] = beta == 0 ? z : v0;
-        t[3] = beta == 0 ? z : v1;
-      }
-      maybe_hop<0, +1>(A, x, j, col, a, part, t);
-      maybe_hop<0, -1>(A, x, j, col, a, part, t);
-      maybe_hop<1, +1>(A, x, j, col, a, part, t);
-      maybe_hop<1, -1>(A, x, j, col, a, part, t);
-      maybe_hop<2, +1>(A, x, j, col, a, part, t);
-      maybe_hop<2, -1>(A, x, j, col, a, part, t);
-      maybe_hop<3, +1>(A, x, j, col, a, part, t);
-      maybe_hop<3, -1>(A, x, j, col, a, part, t);
 #pragma unroll
-      for (int sp = 0; sp < 4; ++sp) T[sb][3 * sp + a][col] = t[sp];
+        for (int a = 0; a < 3; ++a) {
+          const double2 v0 = cscale(p[int64_t(a) * A.nb], A.diag);
+          const double2 v1 = cscale(p[int64_t(3 + a) * A.nb], A.diag);
+          t[a][0] = beta == 0 ? v0 : z;
+          t[a][1] = beta == 0 ? v1 : z;
+          t[a][2] = beta == 0 ? z : v0;
+          t[a][3] = beta == 0 ? z : v1;
+        }
+      }
+      maybe_hop<0, +1>(A, x, j, col, part, t);
+      maybe_hop<0, -1>(A, x, j, col, part, t);
+      maybe_hop<1, +1>(A, x, j, col, part, t);
+      maybe_hop<1, -1>(A, x, j, col, part, t);
+      maybe_hop<2, +1>(A, x, j, col, part, t);
+      maybe_hop<2, -1>(A, x, j, col, part, t);
+      maybe_hop<3, +1>(A, x, j, col, part, t);
+      maybe_hop<3, -1>(A, x, j, col, part, t);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) T[sb][3 * sp + a][col] = t[a][sp];
     }
     __syncthreads();
     // acc[r][c] += sum_c' conj(P(x)[alpha_r*6 + c'][r]) T[alpha_r*6 + c'][c], sites in list order
