@@ -59,9 +59,10 @@ __device__ void load_block_rows(const ChiralSrc& src, const T2* base, const doub
 }
 
 // acc[x][y] += sum_rows conj(L[row][ti*TI + x]) * L[row][tj*TI + y]
-template <int TI>
+template <int TI, int UNR = 1>
 __device__ __forceinline__ void gram_accumulate(const double2* lds, int ldm, int nrows, int ti, int tj, int m,
                                                 double2 (&acc)[TI][TI]) {
+#pragma unroll UNR
   for (int r = 0; r < nrows; ++r) {
     double2 a[TI], b[TI];
 #pragma unroll
@@ -257,12 +258,13 @@ __global__ __launch_bounds__(kThreads) void rotate_kernel(ChiralSrc src, const T
     for (int e = threadIdx.x; e < nrows * m; e += blockDim.x) {
       const int rr = e / m, col = e % m;
       double2 t = make_double2(0, 0);
+#pragma unroll 8
       for (int i = 0; i < m; ++i) cfma(t, As[rr * m + i], Vs[i * m + col]);
       Bs[rr * m + col] = t;
       Bp[int64_t(r0 + rr) * m + col] = t;
     }
     __syncthreads();
-    gram_accumulate<TI>(Bs, m, nrows, ti, tj, m, acc);
+    gram_accumulate<TI, 4>(Bs, m, nrows, ti, tj, m, acc);
   }
   gram_store<TI>(G2 + int64_t(pair) * m * m, m, ti, tj, acc);
 }
@@ -322,6 +324,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int m, int nr, int k
     for (int e = threadIdx.x; e < nrows * k; e += blockDim.x) {
       const int i = e / nrows, rr = e % nrows;
       double2 t = make_double2(0, 0);
+#pragma unroll 8
       for (int y = 0; y < m; ++y) cfma(t, Bs[rr * mp + y], T[y * k + i]);
       Pp[int64_t(i) * nr + r0 + rr] = t;
     }
