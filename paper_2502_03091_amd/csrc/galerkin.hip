@@ -216,14 +216,21 @@ __global__ __launch_bounds__(kT) void galerkin_kernel(GalerkinArgs A) {
     // acc[r][c] += sum_c' conj(P(x)[alpha_r*6 + c'][r]) T[alpha_r*6 + c'][c], sites in list order
     for (int sb = 0; sb < ns; ++sb) {
 #pragma unroll
-      for (int xr = 0; xr < TI; ++xr) {
-        const int r = rg * TI + xr;
-        const int ar = r / k;
+      for (int c = 0; c < 6; ++c) {
+        // this thread's T columns of both chiralities, read once for all TI rows
+        double2 t0[TI], t1[TI];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
+        for (int yc = 0; yc < TI; ++yc) {
+          t0[yc] = T[sb][c][cg * TI + yc];
+          t1[yc] = T[sb][6 + c][cg * TI + yc];
+        }
+#pragma unroll
+        for (int xr = 0; xr < TI; ++xr) {
+          const int r = rg * TI + xr;
+          const bool ar = r >= k;
           const double2 pr = Pc[sb][c][r];
 #pragma unroll
-          for (int yc = 0; yc < TI; ++yc) cfmac(acc[xr][yc], pr, T[sb][6 * ar + c][cg * TI + yc]);
+          for (int yc = 0; yc < TI; ++yc) cfmac(acc[xr][yc], pr, ar ? t1[yc] : t0[yc]);
         }
       }
     }
