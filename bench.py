@@ -301,6 +301,115 @@ def workload_volume(crk, args):
     }
 
 
+# ------------------------------------------------------------------ kernel sweeps
+FORM_NAMES = {0: "FP64", 1: "FP32", 2: "FP16S"}
+MFMA_PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0}  # dense MFMA peaks: fp64, fp32, fp16 inputs
+
+
+def _device_field(torch, nbytes, form, nrhs, V, dev, gen):
+    """A field of nbytes in a form's device layout with Gaussian data (FP16S: unit scales)."""
+    buf = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if form == 2:
+        nd = nbytes - 4 * nrhs * ((V + 63) // 64 * 64)
+        buf[:nd].view(torch.float16).normal_(0.0, 0.3, generator=gen)
+        buf[nd:].view(torch.float32).fill_(1.0)
+    else:
+        buf.view(torch.float64 if form == 0 else torch.float32).normal_(generator=gen)
+    return buf
+
+
+def _time_apply(torch, H, level, a, b, nrhs, form, reps, flush=None):
+    """Average launch time over reps launches, each bracketed by its own events.
+    With flush (a large buffer), it is overwritten before every launch so that
+    no input is still held in the 256 MB last-level cache, as in the setup and
+    the K-cycle, where each operator launch follows a pass over larger fields."""
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        H.apply_dev(level, a, b, nrhs, form, stream=st)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        if flush is not None:
+            flush.zero_()
+        e0.record(st)
+        H.apply_dev(level, a, b, nrhs, form, stream=st)
+        e1.record(st)
+    ev[-1][1].synchronize()
+    return sum(e0.elapsed_time(e1) for e0, e1 in ev) * 1e-3 / reps
+
+
+def workload_kernels(crk, args):
+    """The fine operator (tile dslash on the hierarchy's block-major layout) over
+    volumes, forms and RHS counts against the HBM roofline, and the MFMA coarse
+    operator (2k = 48) over RHS counts against the MFMA and link-streaming rooflines."""
+    import torch
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(20250305)
+    m0 = tuned_m0("iso_xi1_eps0.25")
+    sizes = {16: [16, 16, 16, 32], 32: [32, 32, 32, 32], 48: [48, 48, 48, 96]}
+    rows, coarse = [], []
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    for ext in (int(x) for x in args.volumes.split(",")):
+        dims = sizes[ext]
+        V = int(np.prod(dims))
+        U = synth.gauge_field_device(dims, ISO["eps"], ISO["n_ape"], config=ISO["config"])
+        lat = crk.Lattice(dims, m0, ISO["xi"])
+        lat.load_gauge(U)
+        del U
+        torch.cuda.empty_cache()
+        big = ext == 16  # the 16^3x32 hierarchy is the benchmark's own (2k = 48) for the coarse sweep
+        H = crk.Hierarchy(lat, m_prime=[48 if big else 8], k=[24 if big else 8], block=[BLOCK],
+                          n_smooth=[10 if big else 0], setup_form=crk.FORM_FP32, seed=0x2502030910)
+        for form in (0, 1, 2):
+            for nrhs in (1, 12, 64):
+                nb = H.field_bytes(0, form, nrhs)
+                free, _ = torch.cuda.mem_get_info()
+                row = {"lattice": dims, "form": FORM_NAMES[form], "nrhs": nrhs}
+                if 2 * nb > 0.8 * free:
+                    row["skipped"] = "fields do not fit"
+                    rows.append(row)
+                    continue
+                a = _device_field(torch, nb, form, nrhs, V, dev, gen)
+                b = torch.empty_like(a)
+                t = _time_apply(torch, H, 0, a, b, nrhs, form, reps=10, flush=flush)
+                alg = dslash_bytes(V, nrhs, form)
+                row.update({"us": t * 1e6, "alg_GBps": alg / t / 1e9, "frac_of_8TBps": alg / t / 1e9 / HBM_PEAK_GBPS})
+                log("kernels", json.dumps(row))
+                rows.append(row)
+                del a, b
+                torch.cuda.empty_cache()
+        if big:
+            Vc, N = H.volume(1), H.ncomp[1]
+            for form in (0, 1, 2):
+                for nrhs in (1, 12, 32, 48):
+                    nb = H.field_bytes(1, form, nrhs)
+                    a = _device_field(torch, nb, 1 if form == 2 else form, nrhs, Vc, dev, gen)
+                    b = torch.empty_like(a)
+                    t = _time_apply(torch, H, 1, a, b, nrhs, form, reps=50)
+                    flops = 72.0 * N * N * Vc * nrhs
+                    link_bytes = 9.0 * N * N * Vc * {0: 16, 1: 8, 2: 4}[form]
+                    row = {"coarse_lattice": [d // 4 for d in dims], "dof": N, "form": FORM_NAMES[form],
+                           "nrhs": nrhs, "us": t * 1e6, "TFLOPs": flops / t / 1e12,
+                           "frac_of_mfma_peak": flops / t / 1e12 / MFMA_PEAK_TFLOPS[form],
+                           "link_GBps": link_bytes / t / 1e9}
+                    log("kernels", json.dumps(row))
+                    coarse.append(row)
+        H.close()
+        lat.close()
+    return {
+        "metric": "fine operator GB/s (algorithmic) and coarse MFMA TFLOP/s vs volume, form and RHS count",
+        "value": None, "unit": "GB/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f64/f32/f16s",
+        "data": "synthetic",
+        "config": {"workload": "tile dslash on 4^4 block-major layouts of 16^3x32, 32^4, 48^3x96 (xi=1, eps=0.25 "
+                               "+ 3 APE) in FP64/FP32/FP16S with 1/12/64 RHS; MFMA coarse operator of the "
+                               "16^3x32 hierarchy (m'=48 -> k=24, 2k=48 on 4x4x4x8 coarse sites) with 1/12/32/48 "
+                               "RHS; HIP events around each of 10 fine launches (a 1 GiB buffer is overwritten before each, so no "
+                               "input is served from the last-level cache) and 50 coarse launches (links stay cached, "
+                               "as between the coarse iterations of a solve)", "parallelism": "none (1 GPU)"},
+        "dslash": rows, "coarse": coarse,
+    }
+
+
 # ------------------------------------------------------------------ default: anisotropic 16^3x32
 
 def workload_aniso16(crk, args):
@@ -415,11 +524,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="aniso16", choices=["aniso16", "iso32", "volume", "serve"])
+    ap.add_argument("--workload", default="aniso16", choices=["aniso16", "iso32", "volume", "serve", "kernels"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--volumes", default="24,32,48", help="volume sweep: spatial extents to run (24, 32, 48)")
+    ap.add_argument("--volumes", default=None,
+                    help="spatial extents to run: volume sweep 24,32,48 (default); kernel sweep 16,32,48 (default)")
     ap.add_argument("--serve-rates", default="0.25,0.5,1,2,5")
     ap.add_argument("--serve-seconds", type=float, default=40.0)
     ap.add_argument("--serve-max-requests", type=int, default=80)
@@ -432,7 +542,9 @@ def main():
 
     import paper_2502_03091_amd as crk
     fn = {"aniso16": workload_aniso16, "iso32": workload_iso32, "volume": workload_volume,
-          "serve": workload_serve}[args.workload]
+          "serve": workload_serve, "kernels": workload_kernels}[args.workload]
+    if args.volumes is None:
+        args.volumes = "16,32,48" if args.workload == "kernels" else "24,32,48"
     print(json.dumps(fn(crk, args)), flush=True)
 
 

@@ -210,6 +210,27 @@ int crk_mg_get_timing(crk_mg_t mg, int32_t level, double* out6);
 int crk_mg_coarse_apply(crk_mg_t mg, int32_t level, int32_t form, const double* in, double* out,
                         int32_t nrhs);
 
+/* Device-resident variant of crk_mg_coarse_apply (paper, Sec. 2, Eq. (4) for
+ * l >= 1; the Wilson operator for l = 0) on the hierarchy's own device layout
+ * of level l, the one the smoother and the K-cycle use, for callers that keep
+ * fields on the device and for timing the operator kernels:
+ *   l = 0: the native layout of crk_dirac_apply_dev with every site at its
+ *          CRK_GET_DEVICE_ORDER position (block-major) instead of its
+ *          lexicographic index (FP16S: half2 spinors plus one float scale
+ *          per site and RHS, after the data);
+ *   l >= 1: entry (rhs r, component c, device site p) at complex element
+ *          (p*N_l + c)*nrhs + r (FP64 double2; FP32 and FP16S float2, the
+ *          FP16S form keeping FP16 links only).
+ * in and out are device pointers of crk_mg_field_bytes(mg, l, form, nrhs)
+ * bytes each and may not alias; the work is ordered on hip_stream (NULL: the
+ * default stream) and the call returns without waiting.  nrhs = 0 is a no-op;
+ * CRK_EINVAL for a bad level, form or pointer. */
+int crk_mg_apply_dev(crk_mg_t mg, int32_t level, int32_t form, const void* in, void* out, int32_t nrhs,
+                     void* hip_stream);
+
+/* Bytes of nrhs fields of level l in a form for crk_mg_apply_dev; -1 on bad arguments. */
+int64_t crk_mg_field_bytes(crk_mg_t mg, int32_t level, int32_t form, int32_t nrhs);
+
 /* Restrict fine-level (level l) host vectors [nrhs][V_l][N_l] to level l+1, and prolong back. */
 int crk_mg_restrict(crk_mg_t mg, int32_t level, int32_t form, const double* in, double* out, int32_t nrhs);
 int crk_mg_prolong(crk_mg_t mg, int32_t level, int32_t form, const double* in, double* out, int32_t nrhs);

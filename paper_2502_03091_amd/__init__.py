@@ -161,6 +161,8 @@ def _load():
         "crk_mg_get_bytes": (i64, [vp, i32, i32]),
         "crk_mg_get_timing": (i32, [vp, i32, C.POINTER(dbl)]),
         "crk_mg_coarse_apply": (i32, [vp, i32, i32, vp, vp, i32]),
+        "crk_mg_apply_dev": (i32, [vp, i32, i32, vp, vp, i32, vp]),
+        "crk_mg_field_bytes": (i64, [vp, i32, i32, i32]),
         "crk_mg_restrict": (i32, [vp, i32, i32, vp, vp, i32]),
         "crk_mg_prolong": (i32, [vp, i32, i32, vp, vp, i32]),
         "crk_mg_footprint_bytes": (i64, [vp, i32, i32]),
@@ -194,8 +196,8 @@ def exported_symbols():
         "crk_field_export_dev", "crk_lattice_get_map", "crk_lattice_destroy", "crk_mg_params_default",
         "crk_mg_setup", "crk_solve_info_default", "crk_mg_solve", "crk_mg_solve_dev",
         "crk_mg_last_solve_rhs", "crk_mg_get", "crk_mg_get_bytes", "crk_mg_get_timing",
-        "crk_mg_coarse_apply", "crk_mg_restrict", "crk_mg_prolong", "crk_mg_footprint_bytes",
-        "crk_mg_destroy",
+        "crk_mg_coarse_apply", "crk_mg_apply_dev", "crk_mg_field_bytes", "crk_mg_restrict", "crk_mg_prolong",
+        "crk_mg_footprint_bytes", "crk_mg_destroy",
     ]
 
 
@@ -413,6 +415,14 @@ class Hierarchy:
         out = np.empty_like(v)
         _check(_load().crk_mg_coarse_apply(self.handle, level, int(form), _cptr(v), _cptr(out), v.shape[0]))
         return out
+
+    def apply_dev(self, level, inp, out, nrhs, form, stream=None):
+        """Operator of level `level` on device tensors in the hierarchy's own layout (see crk.h); stream-ordered."""
+        _check(_load().crk_mg_apply_dev(self.handle, int(level), int(form), _tptr(inp), _tptr(out), int(nrhs),
+                                        _stream(stream)))
+
+    def field_bytes(self, level, form, nrhs):
+        return int(_load().crk_mg_field_bytes(self.handle, int(level), int(form), int(nrhs)))
 
     def restrict(self, level, v, form=FORM_FP64):
         v = _as_c128(v)

@@ -312,6 +312,30 @@ int crk_mg_coarse_apply(crk_mg_t mg, int32_t level, int32_t form, const double* 
   });
 }
 
+int64_t crk_mg_field_bytes(crk_mg_t mg, int32_t level, int32_t form, int32_t nrhs) {
+  if (!mg || !mg->H || nrhs < 0 || form < 0 || form > 2) return -1;
+  Hierarchy* H = mg->H;
+  if (level < 0 || level >= H->nlev) return -1;
+  if (level == 0) return int64_t(fine_field_bytes(form, H->V(0), nrhs));
+  return int64_t(form == CRK_FORM_FP64 ? 16 : 8) * H->V(level) * H->N(level) * nrhs;
+}
+
+int crk_mg_apply_dev(crk_mg_t mg, int32_t level, int32_t form, const void* in, void* out, int32_t nrhs,
+                     void* hip_stream) {
+  crk_clear_error_();
+  return guarded_mg([&] {
+    Hierarchy* H = hier(mg);
+    check_level(H, level, 0, H->nlev - 1);
+    CRK_REQUIRE(form >= 0 && form <= 2, "unknown form");
+    CRK_REQUIRE(nrhs >= 0, "nrhs must be >= 0");
+    if (nrhs == 0) return CRK_OK;
+    CRK_REQUIRE(in && out, "NULL field pointer");
+    CRK_REQUIRE(in != out, "in and out must not alias");
+    level_apply(H, level, form, in, out, nrhs, static_cast<hipStream_t>(hip_stream));
+    return CRK_OK;
+  });
+}
+
 int crk_mg_restrict(crk_mg_t mg, int32_t level, int32_t form, const double* in, double* out, int32_t nrhs) {
   crk_clear_error_();
   return guarded_mg([&] {

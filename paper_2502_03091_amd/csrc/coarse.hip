@@ -153,91 +153,113 @@ __global__ __launch_bounds__(64 * kLinkWaves) void coarse_mfma_kernel(const type
 
 // FP16 links with a per-(site, link) fp32 scale; fp32 vectors; fp32 accumulation.
 // A operand of 16x16x16f16: lane holds A[row = lane%16][k = 4*(lane/16) + i], i < 4.
+// One workgroup of nine wavefronts per (coarse site, 16-RHS tile): wavefront nb
+// takes link nb for all 2k/16 row tiles.  Per link the B operand (the
+// neighbour's vector column) is scaled by its largest entry so that it is well
+// conditioned in fp16, and the product is rescaled by that value and the
+// link's scale in fp32; the nine rescaled products are then added in link
+// order through LDS.
+constexpr int kF16Waves = 9;
+
 template <int MT>
-__global__ __launch_bounds__(64) void coarse_mfma_f16_kernel(const __half2* __restrict__ links,
-                                                             const float* __restrict__ lscale,
-                                                             const float2* __restrict__ in, float2* __restrict__ out,
-                                                             const int* __restrict__ nbr, int64_t Vc, int nrhs,
-                                                             int ntiles, float sign, float2* __restrict__ copy) {
+__global__ __launch_bounds__(64 * kF16Waves) void coarse_mfma_f16_kernel(const __half2* __restrict__ links,
+                                                                         const float* __restrict__ lscale,
+                                                                         const float2* __restrict__ in,
+                                                                         float2* __restrict__ out,
+                                                                         const int* __restrict__ nbr, int64_t Vc,
+                                                                         int nrhs, int ntiles, float sign,
+                                                                         float2* __restrict__ copy) {
   constexpr int N = 16 * MT;
+  __shared__ float part[kF16Waves - 1][MT][8][64];
   const int64_t j = blockIdx.x / ntiles;
   const int tile = blockIdx.x % ntiles;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, nb = threadIdx.x >> 6;
   const int n = tile * 16 + (lane & 15);
   const int kq = lane >> 4;
   const bool live = n < nrhs;
   const int nc = live ? n : nrhs - 1;  // past nrhs: the last RHS (in bounds), not stored
-  floatx4 tre[MT], tim[MT];
+  const int64_t s = nb == 0 ? j : int64_t(nbr[int64_t(nb - 1) * Vc + j]);
+  const __half2* Lb = links + (j * 9 + nb) * int64_t(N) * N + (lane & 15);
+  const float2* vb = in + s * int64_t(N) * nrhs + nc;
+  const float ls = lscale[j * 9 + nb];
+  float vmax = 0.f;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) { tre[mt] = floatx4{0, 0, 0, 0}; tim[mt] = floatx4{0, 0, 0, 0}; }
-  for (int nb = 0; nb < 9; ++nb) {
-    const int64_t s = nb == 0 ? j : int64_t(nbr[int64_t(nb - 1) * Vc + j]);
-    const __half2* Lb = links + (j * 9 + nb) * int64_t(N) * N;
-    const float2* vb = in + s * int64_t(N) * nrhs;
-    const float ls = lscale[j * 9 + nb];
-    // vectors of this link's neighbour: per-rhs scale so the fp16 B operand is well conditioned
-    float vmax = 0.f;
-    for (int kk = 0; kk < N; ++kk) {
-      const float2 v = vb[int64_t(kk) * nrhs + nc];
-      vmax = fmaxf(vmax, fmaxf(fabsf(v.x), fabsf(v.y)));
+  for (int kk = 0; kk < N; ++kk) {
+    const float2 v = vb[int64_t(kk) * nrhs];
+    vmax = fmaxf(vmax, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  const float vinv = vmax > 0.f ? 1.f / vmax : 0.f;
+  floatx4 are[MT], aim[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) { are[mt] = floatx4{0, 0, 0, 0}; aim[mt] = floatx4{0, 0, 0, 0}; }
+#pragma unroll
+  for (int ks = 0; ks < N / 16; ++ks) {
+    halfx4 br, bi;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float2 v = vb[int64_t(ks * 16 + kq * 4 + i) * nrhs];
+      br[i] = _Float16(v.x * vinv);
+      bi[i] = _Float16(v.y * vinv);
     }
-    const float vinv = vmax > 0.f ? 1.f / vmax : 0.f;
-    floatx4 are[MT], aim[MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) { are[mt] = floatx4{0, 0, 0, 0}; aim[mt] = floatx4{0, 0, 0, 0}; }
-    for (int ks = 0; ks < N / 16; ++ks) {
-      halfx4 br, bi;
+    for (int mt = 0; mt < MT; ++mt) {
+      halfx4 ar, ai, ain;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int kk = ks * 16 + kq * 4 + i;
-        const float2 v = vb[int64_t(kk) * nrhs + nc];
-        br[i] = _Float16(v.x * vinv);
-        bi[i] = _Float16(v.y * vinv);
+        const __half2 a = Lb[int64_t(ks * 16 + kq * 4 + i) * N + mt * 16];
+        ar[i] = __builtin_bit_cast(_Float16, a.x);
+        ai[i] = __builtin_bit_cast(_Float16, a.y);
+        ain[i] = -ai[i];
       }
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        halfx4 ar, ai, ain;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int kk = ks * 16 + kq * 4 + i;
-          const __half2 a = Lb[int64_t(kk) * N + mt * 16 + (lane & 15)];
-          ar[i] = _Float16(__low2float(a));
-          ai[i] = _Float16(__high2float(a));
-          ain[i] = -ai[i];
-        }
-        are[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, br, are[mt], 0, 0, 0);
-        are[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ain, bi, are[mt], 0, 0, 0);
-        aim[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, bi, aim[mt], 0, 0, 0);
-        aim[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ai, br, aim[mt], 0, 0, 0);
-      }
+      are[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, br, are[mt], 0, 0, 0);
+      are[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ain, bi, are[mt], 0, 0, 0);
+      aim[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, bi, aim[mt], 0, 0, 0);
+      aim[mt] = __builtin_amdgcn_mfma_f32_16x16x16f16(ai, br, aim[mt], 0, 0, 0);
     }
-    // the lane's output column n has the same vector scale for every row
-    const float f = ls * vmax;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) { tre[mt][i] += f * are[mt][i]; tim[mt][i] += f * aim[mt][i]; }
   }
-  if (!live) return;
-  if (copy) {
-    const float2* vin = in + j * int64_t(N) * nrhs;
-    float2* vc = copy + j * int64_t(N) * nrhs;
+  // the lane's output column n has the same vector scale for every row
+  const float f = ls * vmax;
+  if (nb > 0) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = mt * 16 + kq * 4 + i;
-        vc[int64_t(row) * nrhs + n] = vin[int64_t(row) * nrhs + n];
+        part[nb - 1][mt][i][lane] = f * are[mt][i];
+        part[nb - 1][mt][4 + i][lane] = f * aim[mt][i];
       }
   }
-  float2* ob = out + j * int64_t(N) * nrhs;
+  __syncthreads();
+  if (nb > 0 || !live) return;
+  float2* ob = out + j * int64_t(N) * nrhs + n;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+  for (int mt = 0; mt < MT; ++mt) {
+    floatx4 tre, tim;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      tre[i] = 0.f + f * are[mt][i];
+      tim[i] = 0.f + f * aim[mt][i];
+    }
+#pragma unroll
+    for (int w = 0; w < kF16Waves - 1; ++w)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        tre[i] += part[w][mt][i][lane];
+        tim[i] += part[w][mt][4 + i][lane];
+      }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = mt * 16 + kq * 4 + i;
-      ob[int64_t(row) * nrhs + n] = float2{sign * tre[mt][i], sign * tim[mt][i]};
+      ob[int64_t(row) * nrhs] = float2{sign * tre[i], sign * tim[i]};
     }
+  }
+  if (copy) {
+    const float2* vin = in + j * int64_t(N) * nrhs + n;
+    float2* vc = copy + j * int64_t(N) * nrhs + n;
+#pragma unroll
+    for (int row = kq * 4; row < N; row += 16)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) vc[int64_t(row + i) * nrhs] = vin[int64_t(row + i) * nrhs];
+  }
 }
 
 __global__ void links_to_f32_kernel(const double2* __restrict__ src, float2* __restrict__ dst, int64_t n) {
@@ -292,16 +314,17 @@ void launch_f16(int N, const void* links, const void* in, void* out, const int* 
                 void* copy, hipStream_t st) {
   const int ntiles = (nrhs + 15) / 16;
   const dim3 g = dim3(unsigned(Vc * ntiles));
+  const dim3 b(64 * kF16Waves);
   const __half2* L = static_cast<const __half2*>(links);
   const float* ls = reinterpret_cast<const float*>(L + Vc * 9 * int64_t(N) * N);
   const float2* x = static_cast<const float2*>(in);
   float2* y = static_cast<float2*>(out);
   float2* cp = static_cast<float2*>(copy);
   switch (N / 16) {
-    case 1: hipLaunchKernelGGL((coarse_mfma_f16_kernel<1>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
-    case 2: hipLaunchKernelGGL((coarse_mfma_f16_kernel<2>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
-    case 3: hipLaunchKernelGGL((coarse_mfma_f16_kernel<3>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
-    case 4: hipLaunchKernelGGL((coarse_mfma_f16_kernel<4>), g, dim3(64), 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
+    case 1: hipLaunchKernelGGL((coarse_mfma_f16_kernel<1>), g, b, 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
+    case 2: hipLaunchKernelGGL((coarse_mfma_f16_kernel<2>), g, b, 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
+    case 3: hipLaunchKernelGGL((coarse_mfma_f16_kernel<3>), g, b, 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
+    case 4: hipLaunchKernelGGL((coarse_mfma_f16_kernel<4>), g, b, 0, st, L, ls, x, y, nbr, Vc, nrhs, ntiles, sign, cp); break;
     default: fail(CRK_EINVAL, "coarse operator: 2k must be 16, 32, 48 or 64");
   }
   CRK_LAUNCH_CHECK();

@@ -69,6 +69,8 @@ def test_null_handles_fail_cleanly_without_gpu():
     assert lib.crk_mg_solve(None, None, None, 1, None) == crk.EINVAL
     assert lib.crk_server_submit(None, 0, None, None, 1, None) == crk.EINVAL
     assert lib.crk_server_wait(None, 1, 0.0, None) == crk.EINVAL
+    assert lib.crk_mg_apply_dev(None, 0, crk.FORM_FP32, None, None, 1, None) == crk.EINVAL
+    assert lib.crk_mg_field_bytes(None, 0, crk.FORM_FP32, 1) == -1
     assert b"NULL" in lib.crk_last_error()
     lib.crk_server_destroy(None)
     lib.crk_mg_destroy(None)
