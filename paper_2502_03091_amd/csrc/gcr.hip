@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kT) void multidot_reduce_kernel(const double* __res
 // z -= sum_j coef_j Z_j ; w -= sum_j coef_j W_j, summed from stored slot j_first
 // onwards (cyclically), i.e. oldest direction first: the rounding of an RHS's
 // update then depends only on its own directions, not on where in a ring they sit.
-template <class C>
+template <class C, bool WZ>
 __global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb, const C* __restrict__ Wb,
                                                        int64_t fstride, int nj, int j_first, C* __restrict__ z,
                                                        C* __restrict__ w, const double2* __restrict__ coef, int64_t n,
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb,
   const int64_t e = es == 1 ? t % n : t / nrhs;
   const int64_t idx = int64_t(r) * rs + e * es;
   using T = decltype(C::x);
-  C zz = z[idx], ww = w[idx];
+  C zz = WZ ? z[idx] : C{}, ww = w[idx];
   for (int t0 = 0; t0 < nj; t0 += kU) {
     C zl[kU], wl[kU], c[kU];
     int jj[kU];
@@ -251,18 +251,18 @@ __global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb,
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int64_t off = on[u] ? jj[u] * fstride + idx : idx;
-      zl[u] = (on[u] ? Zb : static_cast<const C*>(z))[off];
+      if constexpr (WZ) zl[u] = (on[u] ? Zb : static_cast<const C*>(z))[off];
       wl[u] = (on[u] ? Wb : static_cast<const C*>(w))[off];
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if (on[u]) {
-        cfma(zz, c[u], zl[u]);
+        if constexpr (WZ) cfma(zz, c[u], zl[u]);
         cfma(ww, c[u], wl[u]);
       }
     }
   }
-  z[idx] = zz;
+  if constexpr (WZ) z[idx] = zz;
   w[idx] = ww;
 }
 
@@ -321,13 +321,14 @@ __global__ __launch_bounds__(kT) void update_kernel(C* __restrict__ z, C* __rest
 // the <w, r>, ||w||^2 partials of its RHS (lane l takes chunks l, l + 64, ... in
 // order, then a fixed shuffle tree; the same in every workgroup) and derives
 // inv = 1/||w|| and a = <w, r>/||w||, which saves the reduction and scalar launches.
-template <class C>
+template <class C, bool LAZY>
 __global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ z, C* __restrict__ w, C* __restrict__ x,
                                                           C* __restrict__ res, const double* __restrict__ dpart,
                                                           int64_t dnch, const int* __restrict__ active,
                                                           int* __restrict__ breakdown, int64_t n, int nrhs,
                                                           int64_t rs, int64_t es, int64_t chunk,
-                                                          double* __restrict__ partial) {
+                                                          double* __restrict__ partial, double* __restrict__ hinv,
+                                                          double2* __restrict__ ha) {
   __shared__ double sh[4];
   __shared__ double scal[3];
   using T = decltype(C::x);
@@ -354,6 +355,12 @@ __global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ z, C* 
   const bool act0 = active[r] != 0;
   const bool ok = act0 && ww > 0.0 && isfinite(nw);
   if (blockIdx.x == 0 && threadIdx.x == 0 && breakdown) breakdown[r] = act0 && !ok;
+  if constexpr (LAZY) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      hinv[r] = ok ? 1.0 / nw : 0.0;
+      ha[r] = ok ? make_double2(scal[0] / nw, scal[1] / nw) : make_double2(0, 0);
+    }
+  }
   const T s = T(ok ? 1.0 / nw : 0.0);
   const bool act = ok;
   const C ar = ok ? mk<C>(T(scal[0] / nw), T(scal[1] / nw)) : mk<C>(T(0), T(0));
@@ -361,14 +368,19 @@ __global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ z, C* 
   double acc = 0;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int64_t idx = int64_t(r) * rs + e * es;
-    const C zn = cscale(z[idx], s), wn = cscale(w[idx], s);
-    z[idx] = zn;
+    const C wn = cscale(w[idx], s);
     w[idx] = wn;
     C rr = res[idx];
+    if constexpr (!LAZY) {
+      const C zn = cscale(z[idx], s);
+      z[idx] = zn;
+      if (act) {
+        C xx = x[idx];
+        cfma(xx, ar, zn);
+        x[idx] = xx;
+      }
+    }
     if (act) {
-      C xx = x[idx];
-      cfma(xx, ar, zn);
-      x[idx] = xx;
       const C aw = cmul(ar, wn);
       rr.x -= aw.x;
       rr.y -= aw.y;
@@ -386,13 +398,18 @@ __global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ z, C* 
 // to 16 RHS), thread (l, r) with r fastest (coalesced), entries l, l + 64, ...
 // of the chunk per thread; every sum over lanes runs in lane order, so an RHS's
 // numbers do not depend on how many RHS share the field.
-template <class C>
+// LAZY: the solution is not updated here (x = sum_i d_i z_i is formed once
+// after the iterations from the stored coefficients), z is left as it came
+// from the preconditioner, and 1/||w||, a of every RHS go to hinv[r], ha[r].
+template <class C, bool LAZY>
 __global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __restrict__ z, C* __restrict__ w,
                                                                          C* __restrict__ x, C* __restrict__ res,
                                                                          const double* __restrict__ dpart,
                                                                          int64_t dnch, const int* __restrict__ active,
                                                                          int* __restrict__ breakdown, int64_t n,
-                                                                         int nrhs, double* __restrict__ partial) {
+                                                                         int nrhs, double* __restrict__ partial,
+                                                                         double* __restrict__ hinv,
+                                                                         double2* __restrict__ ha) {
   __shared__ double sh[kInnerRhs][64][3];
   __shared__ double scal[kInnerRhs][3];
   using T = decltype(C::x);
@@ -427,20 +444,31 @@ __global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __re
     const bool act0 = active[r] != 0;
     const bool ok = act0 && ww > 0.0 && isfinite(nw);
     if (blockIdx.x == 0 && l == 0 && breakdown) breakdown[r] = act0 && !ok;
+    if constexpr (LAZY) {
+      if (blockIdx.x == 0 && l == 0) {
+        hinv[r] = ok ? 1.0 / nw : 0.0;
+        ha[r] = ok ? make_double2(scal[rl][0] / nw, scal[rl][1] / nw) : make_double2(0, 0);
+      }
+    }
     const T sc = T(ok ? 1.0 / nw : 0.0);
     const C ar = ok ? mk<C>(T(scal[rl][0] / nw), T(scal[rl][1] / nw)) : mk<C>(T(0), T(0));
     for (int i = 0; i < kInnerChunk / 64; ++i) {
       const int64_t e = int64_t(blockIdx.x) * kInnerChunk + l + 64 * i;
       if (e >= n) break;
       const int64_t idx = e * nrhs + r;
-      const C zn = cscale(z[idx], sc), wn = cscale(w[idx], sc);
-      z[idx] = zn;
+      const C wn = cscale(w[idx], sc);
       w[idx] = wn;
       C rr = res[idx];
+      if constexpr (!LAZY) {
+        const C zn = cscale(z[idx], sc);
+        z[idx] = zn;
+        if (ok) {
+          C xx = x[idx];
+          cfma(xx, ar, zn);
+          x[idx] = xx;
+        }
+      }
       if (ok) {
-        C xx = x[idx];
-        cfma(xx, ar, zn);
-        x[idx] = xx;
         const C aw = cmul(ar, wn);
         rr.x -= aw.x;
         rr.y -= aw.y;
@@ -457,6 +485,59 @@ __global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __re
     for (int k = 0; k < 64; ++k) a += sh[t][k][0];
     partial[int64_t(blockIdx.x) * nrhs + int(blockIdx.y) * kInnerRhs + t] = a;
   }
+}
+
+// Coefficients of the solution over the unmodified directions z_i of a lazy
+// inner solve (one wavefront per RHS, lane j holding coefficient j).  The GCR
+// direction is p_i = inv_i (z_i - sum_{j<i} c_ij p_j) and x = sum_i a_i p_i;
+// eliminating p from the last direction down gives x = sum_i d_i z_i with
+// d_i = s_i inv_i and s_j -= d_i c_ij (j < i), s starting at a.
+__global__ __launch_bounds__(64) void lazy_coef_kernel(const double2* __restrict__ hcoef,
+                                                       const double* __restrict__ hinv,
+                                                       const double2* __restrict__ ha, int K, int nrhs,
+                                                       double2* __restrict__ dcoef) {
+  const int r = blockIdx.x, j = threadIdx.x;
+  double2 sj = j < K ? ha[int64_t(j) * nrhs + r] : make_double2(0, 0);
+  double2 dj = make_double2(0, 0);
+  for (int i = K - 1; i >= 0; --i) {
+    const double inv = hinv[int64_t(i) * nrhs + r];
+    const double dx = __shfl(sj.x * inv, i), dy = __shfl(sj.y * inv, i);
+    if (j == i) dj = make_double2(dx, dy);
+    if (j < i) {
+      const double2 c = hcoef[(int64_t(i) * nrhs + r) * kMaxCoef + j];
+      sj.x -= dx * c.x - dy * c.y;
+      sj.y -= dx * c.y + dy * c.x;
+    }
+  }
+  dcoef[int64_t(r) * kMaxCoef + j] = dj;
+}
+
+// x = sum_{i<K} d_i z_i (directions added in order).
+template <class C>
+__global__ __launch_bounds__(kT) void lazy_solution_kernel(const C* __restrict__ Zb, int64_t fstride, int K,
+                                                           const double2* __restrict__ dcoef, C* __restrict__ x,
+                                                           int64_t n, int nrhs, int64_t rs, int64_t es) {
+  constexpr int kU = 4;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const int r = es == 1 ? int(t / n) : int(t % nrhs);
+  const int64_t idx = int64_t(r) * rs + (es == 1 ? t % n : t / nrhs) * es;
+  using T = decltype(C::x);
+  C xx = mk<C>(T(0), T(0));
+  for (int i0 = 0; i0 < K; i0 += kU) {
+    C zl[kU], c[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u < K ? i0 + u : K - 1;  // past the end: the last direction (in bounds), not added
+      const double2 d = dcoef[int64_t(r) * kMaxCoef + i];
+      c[u] = mk<C>(T(d.x), T(d.y));
+      zl[u] = Zb[int64_t(i) * fstride + idx];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (i0 + u < K) cfma(xx, c[u], zl[u]);
+  }
+  x[idx] = xx;
 }
 
 // rn2[r] = sum of partials (wavefront g adds chunks g, g + 4, ... in order, then
@@ -609,12 +690,12 @@ void gcr_multiaxpy(int prec, const void* Z, const void* W, int64_t fstride, int 
   CRK_REQUIRE(j_first >= 0 && j_first < nj, "GCR ring start out of range");
   const dim3 g(ceil_div(f.n * f.nrhs, kT));
   if (prec == CRK_FORM_FP64)
-    hipLaunchKernelGGL(multiaxpy_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(Z),
+    hipLaunchKernelGGL((multiaxpy_kernel<double2, true>), g, dim3(kT), 0, st, static_cast<const double2*>(Z),
                        static_cast<const double2*>(W), fstride, nj, j_first, static_cast<double2*>(z),
                        static_cast<double2*>(w),
                        coef, f.n, f.nrhs, f.rs, f.es);
   else
-    hipLaunchKernelGGL(multiaxpy_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(Z),
+    hipLaunchKernelGGL((multiaxpy_kernel<float2, true>), g, dim3(kT), 0, st, static_cast<const float2*>(Z),
                        static_cast<const float2*>(W), fstride, nj, j_first, static_cast<float2*>(z),
                        static_cast<float2*>(w),
                        coef, f.n, f.nrhs, f.rs, f.es);
@@ -652,27 +733,88 @@ void gcr_update_fused(int prec, void* z, void* w, void* x, void* r, const double
     const dim3 grg = dim3(unsigned(nch), unsigned((f.nrhs + kInnerRhs - 1) / kInnerRhs));
     const dim3 brg = dim3(unsigned(64 * std::min(f.nrhs, kInnerRhs)));
     if (prec == CRK_FORM_FP64)
-      hipLaunchKernelGGL(update_fused_rg_kernel<double2>, grg, brg, 0, st, static_cast<double2*>(z),
+      hipLaunchKernelGGL((update_fused_rg_kernel<double2, false>), grg, brg, 0, st, static_cast<double2*>(z),
                          static_cast<double2*>(w), static_cast<double2*>(x), static_cast<double2*>(r), dpart, dnch,
-                         active, breakdown, f.n, f.nrhs, partial);
+                         active, breakdown, f.n, f.nrhs, partial, nullptr, nullptr);
     else
-      hipLaunchKernelGGL(update_fused_rg_kernel<float2>, grg, brg, 0, st, static_cast<float2*>(z),
+      hipLaunchKernelGGL((update_fused_rg_kernel<float2, false>), grg, brg, 0, st, static_cast<float2*>(z),
                          static_cast<float2*>(w), static_cast<float2*>(x), static_cast<float2*>(r), dpart, dnch,
-                         active, breakdown, f.n, f.nrhs, partial);
+                         active, breakdown, f.n, f.nrhs, partial, nullptr, nullptr);
     CRK_LAUNCH_CHECK();
     if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
     return;
   }
   if (prec == CRK_FORM_FP64)
-    hipLaunchKernelGGL(update_fused_kernel<double2>, g, dim3(kT), 0, st, static_cast<double2*>(z),
+    hipLaunchKernelGGL((update_fused_kernel<double2, false>), g, dim3(kT), 0, st, static_cast<double2*>(z),
                        static_cast<double2*>(w), static_cast<double2*>(x), static_cast<double2*>(r), dpart, dnch,
-                       active, breakdown, f.n, f.nrhs, f.rs, f.es, chunk, partial);
+                       active, breakdown, f.n, f.nrhs, f.rs, f.es, chunk, partial, nullptr, nullptr);
   else
-    hipLaunchKernelGGL(update_fused_kernel<float2>, g, dim3(kT), 0, st, static_cast<float2*>(z),
+    hipLaunchKernelGGL((update_fused_kernel<float2, false>), g, dim3(kT), 0, st, static_cast<float2*>(z),
                        static_cast<float2*>(w), static_cast<float2*>(x), static_cast<float2*>(r), dpart, dnch, active,
-                       breakdown, f.n, f.nrhs, f.rs, f.es, chunk, partial);
+                       breakdown, f.n, f.nrhs, f.rs, f.es, chunk, partial, nullptr, nullptr);
   CRK_LAUNCH_CHECK();
   if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
+}
+
+void gcr_multiaxpy_w(int prec, const void* W, int64_t fstride, int nj, void* w, const double2* coef,
+                     const FieldShape& f, hipStream_t st) {
+  if (nj <= 0) return;
+  CRK_REQUIRE(nj <= kMaxCoef, "GCR basis above 64 vectors");
+  const dim3 g(ceil_div(f.n * f.nrhs, kT));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL((multiaxpy_kernel<double2, false>), g, dim3(kT), 0, st, nullptr,
+                       static_cast<const double2*>(W), fstride, nj, 0, nullptr, static_cast<double2*>(w), coef, f.n,
+                       f.nrhs, f.rs, f.es);
+  else
+    hipLaunchKernelGGL((multiaxpy_kernel<float2, false>), g, dim3(kT), 0, st, nullptr,
+                       static_cast<const float2*>(W), fstride, nj, 0, nullptr, static_cast<float2*>(w), coef, f.n,
+                       f.nrhs, f.rs, f.es);
+  CRK_LAUNCH_CHECK();
+}
+
+void gcr_update_lazy(int prec, void* w, void* r, const double* dpart, int64_t dnch, const int* active, int* breakdown,
+                     const FieldShape& f, double* partial, double* hinv, double2* ha, hipStream_t st) {
+  const int64_t nch = shape_chunks(f);
+  if (!(f.es != 1 && f.rs == 1 && f.es == f.nrhs)) {  // one RHS, or rhs-outer: the per-RHS kernel
+    const int64_t chunk = chunk_for_shape(f.n, f.es != 1);
+    const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
+    if (prec == CRK_FORM_FP64)
+      hipLaunchKernelGGL((update_fused_kernel<double2, true>), g, dim3(kT), 0, st, nullptr, static_cast<double2*>(w),
+                         nullptr, static_cast<double2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, f.rs, f.es,
+                         chunk, partial, hinv, ha);
+    else
+      hipLaunchKernelGGL((update_fused_kernel<float2, true>), g, dim3(kT), 0, st, nullptr, static_cast<float2*>(w),
+                         nullptr, static_cast<float2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, f.rs, f.es,
+                         chunk, partial, hinv, ha);
+    CRK_LAUNCH_CHECK();
+    return;
+  }
+  const dim3 grg = dim3(unsigned(nch), unsigned((f.nrhs + kInnerRhs - 1) / kInnerRhs));
+  const dim3 brg = dim3(unsigned(64 * std::min(f.nrhs, kInnerRhs)));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL((update_fused_rg_kernel<double2, true>), grg, brg, 0, st, nullptr, static_cast<double2*>(w),
+                       nullptr, static_cast<double2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, partial, hinv,
+                       ha);
+  else
+    hipLaunchKernelGGL((update_fused_rg_kernel<float2, true>), grg, brg, 0, st, nullptr, static_cast<float2*>(w),
+                       nullptr, static_cast<float2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, partial, hinv,
+                       ha);
+  CRK_LAUNCH_CHECK();
+}
+
+void gcr_lazy_solution(int prec, const void* Z, int64_t fstride, int K, void* x, const double2* hcoef,
+                       const double* hinv, const double2* ha, double2* dcoef, const FieldShape& f, hipStream_t st) {
+  CRK_REQUIRE(K >= 1 && K <= kMaxCoef, "lazy GCR solution: 1 <= K <= 64 directions");
+  hipLaunchKernelGGL(lazy_coef_kernel, dim3(unsigned(f.nrhs)), dim3(64), 0, st, hcoef, hinv, ha, K, f.nrhs, dcoef);
+  CRK_LAUNCH_CHECK();
+  const dim3 g(ceil_div(f.n * f.nrhs, kT));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(lazy_solution_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(Z), fstride, K,
+                       dcoef, static_cast<double2*>(x), f.n, f.nrhs, f.rs, f.es);
+  else
+    hipLaunchKernelGGL(lazy_solution_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(Z), fstride, K,
+                       dcoef, static_cast<float2*>(x), f.n, f.nrhs, f.rs, f.es);
+  CRK_LAUNCH_CHECK();
 }
 
 void gcr_check(const double* partial, const FieldShape& f, double tol2, const double* b2, const int* breakdown,

@@ -26,7 +26,11 @@ struct GcrScalars {
   double2 *a, *coef;
   int *active, *iters, *breakdown, *n_active, *level_iters;
   uint32_t* valid;
-  void alloc(int nrhs, int64_t partial_doubles);
+  // lazy inner solves: per iteration c_ij [kMaxCoef][nrhs][kMaxCoef], 1/||w_i||
+  // and a_i [kMaxCoef][nrhs], and the solution coefficients [nrhs][kMaxCoef]
+  double2 *hcoef = nullptr, *ha = nullptr, *dcoef = nullptr;
+  double* hinv = nullptr;
+  void alloc(int nrhs, int64_t partial_doubles, bool history = false);
 };
 
 struct LevelWork {      // coarse level l >= 1: inner solve buffers (+ post-smoother fields)

@@ -23,7 +23,7 @@
 
 namespace crk {
 
-void GcrScalars::alloc(int nrhs, int64_t partial_doubles) {
+void GcrScalars::alloc(int nrhs, int64_t partial_doubles, bool history) {
   const size_t nr = size_t(nrhs);
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off += (b + 255) & ~size_t(255); return o; };
@@ -34,6 +34,9 @@ void GcrScalars::alloc(int nrhs, int64_t partial_doubles) {
                o_na = take(sizeof(int)), o_li = take(sizeof(int) * nr), o_val = take(sizeof(uint32_t) * nr),
                o_part = take(sizeof(double) * size_t(partial_doubles)),
                o_dpart = take(sizeof(double) * size_t(partial_doubles));
+  const size_t nh = history ? size_t(kMaxCoef) : 0;
+  const size_t o_hc = take(sizeof(double2) * nh * nr * kMaxCoef), o_hi = take(sizeof(double) * nh * nr),
+               o_ha = take(sizeof(double2) * nh * nr), o_dc = take(sizeof(double2) * (history ? nr : 0) * kMaxCoef);
   buf.alloc(off);
   char* c = static_cast<char*>(buf.p);
   sums3 = reinterpret_cast<double*>(c + o_s3);
@@ -50,6 +53,10 @@ void GcrScalars::alloc(int nrhs, int64_t partial_doubles) {
   valid = reinterpret_cast<uint32_t*>(c + o_val);
   partial = reinterpret_cast<double*>(c + o_part);
   dpart = reinterpret_cast<double*>(c + o_dpart);
+  hcoef = history ? reinterpret_cast<double2*>(c + o_hc) : nullptr;
+  hinv = history ? reinterpret_cast<double*>(c + o_hi) : nullptr;
+  ha = history ? reinterpret_cast<double2*>(c + o_ha) : nullptr;
+  dcoef = history ? reinterpret_cast<double2*>(c + o_dc) : nullptr;
 }
 
 namespace {
@@ -84,7 +91,6 @@ void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int 
   const int64_t fs = f.total();  // complex entries per stored field
   const size_t fb = vec_bytes(form) * size_t(fs);
   GcrScalars& s = lw.s;
-  CRK_HIP(hipMemsetAsync(lw.x.p, 0, fb, st));
   CRK_HIP(hipMemcpyAsync(lw.r.p, lw.b.p, fb, hipMemcpyDeviceToDevice, st));
   rhs_dot(prec, lw.b.p, nullptr, f.n, nrhs, f.rs, f.es, s.partial, s.sums3, st);
   gcr_start(s.sums3, nrhs, s.b2, s.active, s.iters, s.n_active, st);
@@ -92,7 +98,7 @@ void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int 
   const bool precond = l < H->nlev - 1;
   char* Z = static_cast<char*>(lw.Z.p);
   char* W = static_cast<char*>(lw.W.p);
-  int n_active = 1;
+  int n_active = 1, K = 0;
   for (int i = 0; i < lw.maxit; ++i) {
     void* zi = Z + fb * i;
     void* wi = W + fb * i;
@@ -103,13 +109,18 @@ void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int 
       // unpreconditioned: z_i = r, stored by the operator launch that computes w_i = D r
       level_apply(H, l, form, lw.r.p, wi, nrhs, st, nullptr, false, zi);
     }
+    // z_i stays as the preconditioner (or the copy of r) left it: only w_i is
+    // orthogonalised and normalised, and the solution is formed after the loop
+    double2* ci = s.hcoef + size_t(i) * nrhs * kMaxCoef;
     if (i > 0) {
-      gcr_multidot(prec, W, fs, i, wi, f, s.partial, nullptr, s.coef, st);
-      gcr_multiaxpy(prec, Z, W, fs, i, 0, zi, wi, s.coef, f, st);
+      gcr_multidot(prec, W, fs, i, wi, f, s.partial, nullptr, ci, st);
+      gcr_multiaxpy_w(prec, W, fs, i, wi, ci, f, st);
     }
     const int64_t dn = rhs_dot_launch(prec, wi, lw.r.p, f.n, nrhs, f.rs, f.es, s.dpart, st);
-    gcr_update_fused(prec, zi, wi, lw.x.p, lw.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, nullptr, st);
+    gcr_update_lazy(prec, wi, lw.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, s.hinv + size_t(i) * nrhs,
+                    s.ha + size_t(i) * nrhs, st);
     gcr_check(s.partial, f, tol2, s.b2, s.breakdown, s.active, s.iters, s.rn2, s.n_active, s.level_iters, st);
+    K = i + 1;
     // Converged RHS are frozen on the device; the host only polls every few
     // iterations to stop launching once every RHS is done.
     if ((i + 1) % kPollEvery == 0 || i + 1 == lw.maxit) {
@@ -118,6 +129,7 @@ void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int 
       if (n_active == 0) break;
     }
   }
+  gcr_lazy_solution(prec, Z, fs, K, lw.x.p, s.hcoef, s.hinv, s.ha, s.dcoef, f, st);
 }
 
 void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs, const void* rin, void* eout,
@@ -237,7 +249,7 @@ std::unique_ptr<Workspace> make_workspace(Hierarchy* H, int cap, int form, const
     lw.x.alloc(cv); lw.r.alloc(cv); lw.b.alloc(cv);
     if (l < H->nlev - 1) { lw.rho.alloc(cv); lw.q.alloc(cv); w.bytes += 2 * cv; }
     lw.Z.alloc(cv * lw.maxit); lw.W.alloc(cv * lw.maxit);
-    lw.s.alloc(cap, partial_doubles(int64_t(H->N(l)) * H->V(l), cap, true));
+    lw.s.alloc(cap, partial_doubles(int64_t(H->N(l)) * H->V(l), cap, true), true);
     CRK_HIP(hipMemsetAsync(lw.s.level_iters, 0, sizeof(int) * cap, st));
     w.bytes += cv * (3 + 2 * size_t(lw.maxit));
   }

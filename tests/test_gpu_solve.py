@@ -100,6 +100,35 @@ def test_multi_rhs_matches_single_rhs(crk, c1):
         assert err <= 1e-12, err
 
 
+@pytest.mark.parametrize("form", [0, 1])
+def test_single_rhs_on_a_multi_chunk_coarse_lattice(crk, form):
+    """One RHS alone (coarse fields laid out rhs-outer, long reduction chunks)
+    against the same RHS in a batch of three (rhs-inner coarse fields) on a
+    coarse lattice of 4^4 sites x 16 components, several chunks of either
+    kind: both reach the true residual, in the same number of iterations
+    within one, and agree to well within the solve's accuracy."""
+    dims = [8, 8, 8, 8]
+    V = 8 ** 4
+    U = synth.gauge_field(dims, 0.3, 0, config=9)
+    lat = crk.Lattice(dims, -0.4, 1.0)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[16], k=[8], block=[[2, 2, 2, 2]], n_smooth=[20], setup_form=form)
+    try:
+        b = synth.gaussian_rhs(3, V, config=10)
+        xb, ib = H.solve(b, form=form, restart=8)
+        xs, i_s = H.solve(b[:1], form=form, restart=8)
+        assert ib["converged"] and i_s["converged"]
+        assert abs(ib["rhs"]["iters"][0] - i_s["iters"]) <= 1
+        op = WilsonOp(U, dims, -0.4, 1.0)
+        for x in (xs[0], xb[0]):
+            res = b[0] - as_fields(op.apply(as_columns(x[None])))[0]
+            assert np.linalg.norm(res) <= 1e-10 * np.linalg.norm(b[0])
+        assert np.abs(xb[0] - xs[0]).max() <= 1e-8 * np.abs(xs[0]).max()
+    finally:
+        H.close()
+        lat.close()
+
+
 def test_zero_rhs_and_mixed_batch(crk, c1):
     lat, H, op, ref = c1
     b = synth.gaussian_rhs(2, 256, config=5)
