@@ -8,6 +8,10 @@
 //   w_i  -= sum_j c_j w_j ; z_i -= sum_j c_j z_j   (classical Gram-Schmidt)
 //   a     = <w_i, r>/||w_i|| ;  w_i, z_i /= ||w_i||
 //   x    += a z_i ;  r -= a w_i ;  ||r||^2                          (update)
+// The inner solves use a lazy form of the same recursion: z_i is neither
+// orthogonalised nor normalised and x is not updated per iteration; c_ij,
+// 1/||w_i|| and a_i are recorded and x = sum_i d_i z_i is formed at the end
+// (lazy_coef_kernel, lazy_solution_kernel), which saves the z and x traffic.
 // Reductions are deterministic (fixed thread ranges, fixed trees, fixed-order
 // final sums).  Fields are addressed as entry e of rhs r at r*rs + e*es.
 #include "gcr.h"
