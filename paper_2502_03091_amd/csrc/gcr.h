@@ -42,13 +42,21 @@ void gcr_update_fused(int prec, void* z, void* w, void* x, void* r, const double
 // they are and form the solution once at the end (lazy): the iterations only
 // orthogonalise and normalise w, update r and record c_ij (hcoef, per
 // iteration [nrhs][kMaxCoef]), 1/||w_i|| (hinv[i][r]) and a_i (ha[i][r]).
-void gcr_multiaxpy_w(int prec, const void* W, int64_t fstride, int nj, void* w, const double2* coef,
+void gcr_multiaxpy_w(int prec, const void* W, int64_t fstride, int nj, int j_first, void* w, const double2* coef,
                      const FieldShape& f, hipStream_t st);
 void gcr_update_lazy(int prec, void* w, void* r, const double* dpart, int64_t dnch, const int* active, int* breakdown,
-                     const FieldShape& f, double* partial, double* hinv, double2* ha, hipStream_t st);
+                     const FieldShape& f, double* partial, double* rn2, double* hinv, double2* ha, hipStream_t st);
 // x = sum_{i<K} d_i z_i with the d_i of the recorded recursion (dcoef: [nrhs][kMaxCoef] work space).
 void gcr_lazy_solution(int prec, const void* Z, int64_t fstride, int K, void* x, const double2* hcoef,
                        const double* hinv, const double2* ha, double2* dcoef, const FieldShape& f, hipStream_t st);
+// Outer (FP64, rhs-outer) lazy form over a ring of nslots directions: RHS r's
+// window is its nb[r] (device) latest directions ending at ring slot last;
+// records are [slot][cap] (c: [slot][cap][kMaxCoef]).  Adds the not yet
+// applied part of the solution, sum over the window of a_i p_i, to x and
+// clears those a_i.
+void gcr_ring_materialize(const void* Z, int64_t fstride, const int* nb, int last, int nslots, int cap, void* x,
+                          const double2* hcoef, const double* hinv, double2* ha, double2* dcoef, const FieldShape& f,
+                          hipStream_t st);
 void gcr_check(const double* partial, const FieldShape& f, double tol2, const double* b2, const int* breakdown,
                int* active, int* iters, double* rn2, int* n_active, int* level_iters, hipStream_t st);
 void gcr_start(const double* sums3, int nrhs, double* b2, int* active, int* iters, int* n_active, hipStream_t st);

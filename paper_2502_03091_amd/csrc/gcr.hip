@@ -544,6 +544,67 @@ __global__ __launch_bounds__(kT) void lazy_solution_kernel(const C* __restrict__
   x[idx] = xx;
 }
 
+// The same elimination for the outer solve, whose directions sit in a ring of
+// nslots slots shared by all RHS: RHS r's current cycle is the window of its
+// nb[r] latest directions, ending at ring slot last.  Per-direction records
+// are indexed [slot][cap] (c: [slot][cap][kMaxCoef] over ring slots); only
+// the a_i not yet applied are non-zero, and they are cleared once applied.
+__global__ __launch_bounds__(64) void ring_lazy_coef_kernel(const double2* __restrict__ hcoef,
+                                                            const double* __restrict__ hinv,
+                                                            double2* __restrict__ ha, const int* __restrict__ nb,
+                                                            int last, int nslots, int cap,
+                                                            double2* __restrict__ dcoef) {
+  const int r = blockIdx.x, k = threadIdx.x, n = nb[r];
+  const int sk = (last - n + 1 + k + 2 * nslots) % nslots;  // ring slot of window position k
+  double2 s = k < n ? ha[int64_t(sk) * cap + r] : make_double2(0, 0);
+  double2 d = make_double2(0, 0);
+  for (int i = n - 1; i >= 0; --i) {
+    const int si = (last - n + 1 + i + 2 * nslots) % nslots;
+    const double inv = hinv[int64_t(si) * cap + r];
+    const double dx = __shfl(s.x * inv, i), dy = __shfl(s.y * inv, i);
+    if (k == i) d = make_double2(dx, dy);
+    if (k < i) {
+      const double2 c = hcoef[(int64_t(si) * cap + r) * kMaxCoef + sk];
+      s.x -= dx * c.x - dy * c.y;
+      s.y -= dx * c.y + dy * c.x;
+    }
+  }
+  dcoef[int64_t(r) * kMaxCoef + k] = k < n ? d : make_double2(0, 0);
+  if (k < n) ha[int64_t(sk) * cap + r] = make_double2(0, 0);
+}
+
+// x_r += sum_k d_k z_{slot k} over RHS r's window, oldest direction first (rhs-outer fields).
+template <class C>
+__global__ __launch_bounds__(kT) void ring_lazy_x_kernel(const C* __restrict__ Zb, int64_t fstride,
+                                                         const int* __restrict__ nb, int last, int nslots,
+                                                         const double2* __restrict__ dcoef, C* __restrict__ x,
+                                                         int64_t n, int nrhs, int64_t rs) {
+  constexpr int kU = 4;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const int r = int(t / n);
+  const int64_t idx = int64_t(r) * rs + t % n;
+  const int m = nb[r];
+  if (m == 0) return;
+  using T = decltype(C::x);
+  C xx = x[idx];
+  for (int k0 = 0; k0 < m; k0 += kU) {
+    C zl[kU], c[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u < m ? k0 + u : m - 1;  // past the end: the last direction (in bounds), not added
+      const int sk = (last - m + 1 + k + 2 * nslots) % nslots;
+      const double2 d = dcoef[int64_t(r) * kMaxCoef + k];
+      c[u] = mk<C>(T(d.x), T(d.y));
+      zl[u] = Zb[int64_t(sk) * fstride + idx];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (k0 + u < m) cfma(xx, c[u], zl[u]);
+  }
+  x[idx] = xx;
+}
+
 // rn2[r] = sum of partials (wavefront g adds chunks g, g + 4, ... in order, then
 // the four sums in a fixed order); convergence bookkeeping of an inner solve.
 __global__ __launch_bounds__(kT) void check_kernel(const double* __restrict__ partial, int64_t nch, int nrhs,
@@ -760,24 +821,25 @@ void gcr_update_fused(int prec, void* z, void* w, void* x, void* r, const double
   if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
 }
 
-void gcr_multiaxpy_w(int prec, const void* W, int64_t fstride, int nj, void* w, const double2* coef,
+void gcr_multiaxpy_w(int prec, const void* W, int64_t fstride, int nj, int j_first, void* w, const double2* coef,
                      const FieldShape& f, hipStream_t st) {
   if (nj <= 0) return;
   CRK_REQUIRE(nj <= kMaxCoef, "GCR basis above 64 vectors");
+  CRK_REQUIRE(j_first >= 0 && j_first < nj, "GCR ring start out of range");
   const dim3 g(ceil_div(f.n * f.nrhs, kT));
   if (prec == CRK_FORM_FP64)
     hipLaunchKernelGGL((multiaxpy_kernel<double2, false>), g, dim3(kT), 0, st, nullptr,
-                       static_cast<const double2*>(W), fstride, nj, 0, nullptr, static_cast<double2*>(w), coef, f.n,
+                       static_cast<const double2*>(W), fstride, nj, j_first, nullptr, static_cast<double2*>(w), coef, f.n,
                        f.nrhs, f.rs, f.es);
   else
     hipLaunchKernelGGL((multiaxpy_kernel<float2, false>), g, dim3(kT), 0, st, nullptr,
-                       static_cast<const float2*>(W), fstride, nj, 0, nullptr, static_cast<float2*>(w), coef, f.n,
+                       static_cast<const float2*>(W), fstride, nj, j_first, nullptr, static_cast<float2*>(w), coef, f.n,
                        f.nrhs, f.rs, f.es);
   CRK_LAUNCH_CHECK();
 }
 
 void gcr_update_lazy(int prec, void* w, void* r, const double* dpart, int64_t dnch, const int* active, int* breakdown,
-                     const FieldShape& f, double* partial, double* hinv, double2* ha, hipStream_t st) {
+                     const FieldShape& f, double* partial, double* rn2, double* hinv, double2* ha, hipStream_t st) {
   const int64_t nch = shape_chunks(f);
   if (!(f.es != 1 && f.rs == 1 && f.es == f.nrhs)) {  // one RHS, or rhs-outer: the per-RHS kernel
     const int64_t chunk = chunk_for_shape(f.n, f.es != 1);
@@ -791,6 +853,7 @@ void gcr_update_lazy(int prec, void* w, void* r, const double* dpart, int64_t dn
                          nullptr, static_cast<float2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, f.rs, f.es,
                          chunk, partial, hinv, ha);
     CRK_LAUNCH_CHECK();
+    if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
     return;
   }
   const dim3 grg = dim3(unsigned(nch), unsigned((f.nrhs + kInnerRhs - 1) / kInnerRhs));
@@ -804,6 +867,7 @@ void gcr_update_lazy(int prec, void* w, void* r, const double* dpart, int64_t dn
                        nullptr, static_cast<float2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, partial, hinv,
                        ha);
   CRK_LAUNCH_CHECK();
+  if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
 }
 
 void gcr_lazy_solution(int prec, const void* Z, int64_t fstride, int K, void* x, const double2* hcoef,
@@ -818,6 +882,20 @@ void gcr_lazy_solution(int prec, const void* Z, int64_t fstride, int K, void* x,
   else
     hipLaunchKernelGGL(lazy_solution_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(Z), fstride, K,
                        dcoef, static_cast<float2*>(x), f.n, f.nrhs, f.rs, f.es);
+  CRK_LAUNCH_CHECK();
+}
+
+void gcr_ring_materialize(const void* Z, int64_t fstride, const int* nb, int last, int nslots, int cap, void* x,
+                          const double2* hcoef, const double* hinv, double2* ha, double2* dcoef, const FieldShape& f,
+                          hipStream_t st) {
+  CRK_REQUIRE(f.es == 1, "ring materialisation: rhs-outer fields only");
+  CRK_REQUIRE(nslots >= 1 && nslots <= kMaxCoef && f.nrhs <= cap, "ring materialisation: bad ring");
+  hipLaunchKernelGGL(ring_lazy_coef_kernel, dim3(unsigned(f.nrhs)), dim3(64), 0, st, hcoef, hinv, ha, nb, last, nslots,
+                     cap, dcoef);
+  CRK_LAUNCH_CHECK();
+  hipLaunchKernelGGL(ring_lazy_x_kernel<double2>, dim3(ceil_div(f.n * f.nrhs, kT)), dim3(kT), 0, st,
+                     static_cast<const double2*>(Z), fstride, nb, last, nslots, dcoef, static_cast<double2*>(x), f.n,
+                     f.nrhs, f.rs);
   CRK_LAUNCH_CHECK();
 }
 

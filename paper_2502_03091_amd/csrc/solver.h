@@ -99,9 +99,13 @@ class OuterSolver {
   int ring_ = 0, used_ = 0;  // ring position of the next direction; stored directions
   std::vector<int> state_, iters_, nbasis_;
   std::vector<double> bn_, tres_;
+  DevBuf nbd_;  // per-slot window lengths for materialize
   void upload_active();
   int width() const;
   void true_residual(int width);  // tmp = b - D x over the first `width` slots, sums into s.sums3
+  // Adds to x the part of the solution not applied yet: slot r's window is its
+  // window[r] latest directions ending at ring slot `last` (0: nothing pending).
+  void materialize(int wd, const std::vector<int>& window, int last);
 };
 
 }  // namespace crk

@@ -114,11 +114,11 @@ void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int 
     double2* ci = s.hcoef + size_t(i) * nrhs * kMaxCoef;
     if (i > 0) {
       gcr_multidot(prec, W, fs, i, wi, f, s.partial, nullptr, ci, st);
-      gcr_multiaxpy_w(prec, W, fs, i, wi, ci, f, st);
+      gcr_multiaxpy_w(prec, W, fs, i, 0, wi, ci, f, st);
     }
     const int64_t dn = rhs_dot_launch(prec, wi, lw.r.p, f.n, nrhs, f.rs, f.es, s.dpart, st);
-    gcr_update_lazy(prec, wi, lw.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, s.hinv + size_t(i) * nrhs,
-                    s.ha + size_t(i) * nrhs, st);
+    gcr_update_lazy(prec, wi, lw.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, nullptr,
+                    s.hinv + size_t(i) * nrhs, s.ha + size_t(i) * nrhs, st);
     gcr_check(s.partial, f, tol2, s.b2, s.breakdown, s.active, s.iters, s.rn2, s.n_active, s.level_iters, st);
     K = i + 1;
     // Converged RHS are frozen on the device; the host only polls every few
@@ -226,7 +226,7 @@ std::unique_ptr<Workspace> make_workspace(Hierarchy* H, int cap, int form, const
   o.b.alloc(f64); o.x.alloc(f64); o.r.alloc(f64); o.tmp.alloc(f64);
   o.Z.alloc(f64 * nslots); o.W.alloc(f64 * nslots);
   o.mask.alloc(sizeof(int) * cap);
-  o.s.alloc(cap, partial_doubles(12 * V0, cap, false));
+  o.s.alloc(cap, partial_doubles(12 * V0, cap, false), true);
   // Slots may start at any ring position: every stored direction a slot's
   // kernels touch must hold finite values from the start.
   CRK_HIP(hipMemsetAsync(o.Z.p, 0, f64 * nslots, st));
@@ -268,6 +268,7 @@ OuterSolver::OuterSolver(Hierarchy* H, Workspace* w, const crk_solve_info& p, hi
   nbasis_.assign(cap_, 0);
   bn_.assign(cap_, 0.0);
   tres_.assign(cap_, 0.0);
+  nbd_.alloc(sizeof(int) * size_t(cap_));
 }
 
 int OuterSolver::free_slots() const { return int(std::count(state_.begin(), state_.end(), int(kSlotFree))); }
@@ -307,6 +308,8 @@ void OuterSolver::admit(int s0, int n, const void* b_dev) {
   field_import(CRK_FORM_FP64, static_cast<const double2*>(b_dev), b, H_->fine_geo.pos.as<int>(), V, 12, n, st_);
   CRK_HIP(hipMemsetAsync(x, 0, bytes, st_));
   CRK_HIP(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, st_));
+  for (int j = 0; j < nslots_; ++j)  // no solution part of an earlier occupant is pending in these slots
+    CRK_HIP(hipMemsetAsync(s.ha + size_t(j) * cap_ + s0, 0, sizeof(double2) * size_t(n), st_));
   for (int l = 1; l < H_->nlev; ++l)
     CRK_HIP(hipMemsetAsync(w_->lv[l].s.level_iters + s0, 0, sizeof(int) * n, st_));
   rhs_dot(CRK_FORM_FP64, b, nullptr, per, n, per, 1, s.partial, s.sums3, st_);
@@ -362,33 +365,50 @@ int OuterSolver::step() {
   }
   level_apply(H_, 0, CRK_FORM_FP64, zi, wi, wd, st_);
   used_ = std::min(used_ + 1, nslots_);
+  // Lazy form: z_i stays as the K-cycle returned it, only w_i is orthogonalised
+  // and normalised; c_ij, 1/||w_i|| and a_i are recorded per ring slot and the
+  // solution is brought up to date (materialize) whenever it is needed.
+  double2* ci = s.hcoef + size_t(ring_) * cap_ * kMaxCoef;
   if (used_ > 1) {
     std::vector<uint32_t> valid(wd, 0);
     for (int r = 0; r < wd; ++r)
       for (int a = 1; a <= nbasis_[r]; ++a) valid[r] |= 1u << ((ring_ - a + nslots_) % nslots_);
     CRK_HIP(hipMemcpyAsync(s.valid, valid.data(), sizeof(uint32_t) * wd, hipMemcpyHostToDevice, st_));
-    gcr_multidot(CRK_FORM_FP64, W, fcap, used_, wi, f, s.partial, s.valid, s.coef, st_);
-    gcr_multiaxpy(CRK_FORM_FP64, Z, W, fcap, used_, (ring_ + 1) % used_, zi, wi, s.coef, f, st_);
+    gcr_multidot(CRK_FORM_FP64, W, fcap, used_, wi, f, s.partial, s.valid, ci, st_);
+    gcr_multiaxpy_w(CRK_FORM_FP64, W, fcap, used_, (ring_ + 1) % used_, wi, ci, f, st_);
     CRK_HIP(hipStreamSynchronize(st_));  // valid lives on the host stack
   }
   const int64_t dn = rhs_dot_launch(CRK_FORM_FP64, wi, o.r.p, f.n, wd, f.rs, f.es, s.dpart, st_);
-  gcr_update_fused(CRK_FORM_FP64, zi, wi, o.x.p, o.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, s.rn2,
-                   st_);
+  gcr_update_lazy(CRK_FORM_FP64, wi, o.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, s.rn2,
+                  s.hinv + size_t(ring_) * cap_, s.ha + size_t(ring_) * cap_, st_);
   std::vector<double> rn2(wd);
   std::vector<int> bd(wd);
   CRK_HIP(hipMemcpyAsync(rn2.data(), s.rn2, sizeof(double) * wd, hipMemcpyDeviceToHost, st_));
   CRK_HIP(hipMemcpyAsync(bd.data(), s.breakdown, sizeof(int) * wd, hipMemcpyDeviceToHost, st_));
   CRK_HIP(hipStreamSynchronize(st_));
-  bool need_true = false;
-  std::vector<int> claim(wd, 0), restart(wd, 0);
+  bool need_true = false, update_x = false;
+  // window[r] > 0: slot r's solution is brought up to date in this step, over
+  // its cycle's directions up to the current one.  That happens exactly when
+  // the slot itself needs x (a convergence claim or a restart, whose true
+  // residual reads it, or a stop, which keeps it), so a slot's x is formed at
+  // the same points of its recursion whatever other slots share the solve.
+  std::vector<int> claim(wd, 0), restart(wd, 0), window(cap_, 0);
   for (int r = 0; r < wd; ++r) {
     if (state_[r] != kSlotRunning) continue;
+    const int wr = nbasis_[r] + 1;
     iters_[r] += 1;
-    if (bd[r]) { state_[r] = kSlotStopped; continue; }  // breakdown: keep the best x
+    if (bd[r]) {  // breakdown: keep the best x
+      state_[r] = kSlotStopped;
+      window[r] = wr;
+      continue;
+    }
     nbasis_[r] += 1;
-    if (std::sqrt(rn2[r]) <= p_.tol * bn_[r]) { claim[r] = 1; need_true = true; }
-    else if (nbasis_[r] >= nslots_) { restart[r] = 1; need_true = true; }
+    if (std::sqrt(rn2[r]) <= p_.tol * bn_[r]) { claim[r] = 1; need_true = true; window[r] = wr; }
+    else if (nbasis_[r] >= nslots_) { restart[r] = 1; need_true = true; window[r] = wr; }
+    if (iters_[r] >= p_.max_iter) window[r] = wr;
+    update_x |= window[r] > 0;
   }
+  if (update_x) materialize(wd, window, ring_);
   if (need_true) {
     true_residual(wd);
     std::vector<double> h3(3 * size_t(wd));
@@ -416,7 +436,20 @@ int OuterSolver::step() {
   return running();
 }
 
+void OuterSolver::materialize(int wd, const std::vector<int>& window, int last) {
+  OuterWork& o = w_->ow;
+  GcrScalars& s = o.s;
+  const int64_t V = H_->V(0);
+  CRK_HIP(hipMemcpyAsync(nbd_.p, window.data(), sizeof(int) * size_t(cap_), hipMemcpyHostToDevice, st_));
+  gcr_ring_materialize(o.Z.p, 12 * V * cap_, nbd_.as<int>(), last, nslots_, cap_, o.x.p, s.hcoef, s.hinv, s.ha,
+                       s.dcoef, fine_shape(V, wd), st_);
+  CRK_HIP(hipStreamSynchronize(st_));  // window lives on the caller's stack
+}
+
 void OuterSolver::refresh_residuals() {
+  // The solution of every slot that has stopped or converged is up to date
+  // (step() forms it when a slot leaves the running state); a running slot's
+  // value here is provisional and is formed again when it finishes.
   const int wd = width();
   if (wd == 0) return;
   true_residual(wd);
