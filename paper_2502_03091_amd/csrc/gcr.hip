@@ -8,10 +8,13 @@
 //   w_i  -= sum_j c_j w_j ; z_i -= sum_j c_j z_j   (classical Gram-Schmidt)
 //   a     = <w_i, r>/||w_i|| ;  w_i, z_i /= ||w_i||
 //   x    += a z_i ;  r -= a w_i ;  ||r||^2                          (update)
-// The inner solves use a lazy form of the same recursion: z_i is neither
+// The solvers use a lazy form of the same recursion: z_i is neither
 // orthogonalised nor normalised and x is not updated per iteration; c_ij,
-// 1/||w_i|| and a_i are recorded and x = sum_i d_i z_i is formed at the end
-// (lazy_coef_kernel, lazy_solution_kernel), which saves the z and x traffic.
+// 1/||w_i|| and a_i are recorded and the solution is formed from the raw z_i
+// when it is needed, which saves the z and x traffic: once at the end of an
+// inner solve (lazy_coef_kernel, lazy_solution_kernel), and for an outer slot
+// over its window of the direction ring when it claims convergence, restarts
+// or stops (ring_lazy_coef_kernel, ring_lazy_x_kernel).
 // Reductions are deterministic (fixed thread ranges, fixed trees, fixed-order
 // final sums).  Fields are addressed as entry e of rhs r at r*rs + e*es.
 #include "gcr.h"
