@@ -57,8 +57,10 @@ void gcr_lazy_solution(int prec, const void* Z, int64_t fstride, int K, void* x,
 void gcr_ring_materialize(const void* Z, int64_t fstride, const int* nb, int last, int nslots, int cap, void* x,
                           const double2* hcoef, const double* hinv, double2* ha, double2* dcoef, const FieldShape& f,
                           hipStream_t st);
+// n_active_host (optional): pinned host memory that also receives the count of active RHS.
 void gcr_check(const double* partial, const FieldShape& f, double tol2, const double* b2, const int* breakdown,
-               int* active, int* iters, double* rn2, int* n_active, int* level_iters, hipStream_t st);
+               int* active, int* iters, double* rn2, int* n_active, int* level_iters, hipStream_t st,
+               int* n_active_host = nullptr);
 void gcr_start(const double* sums3, int nrhs, double* b2, int* active, int* iters, int* n_active, hipStream_t st);
 void field_axpby(int prec, const void* x, void* y, double a, double b, int64_t total, hipStream_t st);
 void field_masked_copy(int prec, const void* x, void* y, const int* mask, const FieldShape& f, hipStream_t st);

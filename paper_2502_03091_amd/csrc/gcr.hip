@@ -614,7 +614,8 @@ __global__ __launch_bounds__(kT) void check_kernel(const double* __restrict__ pa
                                                    double tol2, const double* __restrict__ b2,
                                                    const int* __restrict__ breakdown, int* __restrict__ active,
                                                    int* __restrict__ iters, double* __restrict__ rn2,
-                                                   int* __restrict__ n_active, int* __restrict__ level_iters) {
+                                                   int* __restrict__ n_active, int* __restrict__ level_iters,
+                                                   int* __restrict__ n_active_host) {
   __shared__ double sh[kT / 64][64];
   __shared__ int cnt;
   const int q = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -651,7 +652,10 @@ __global__ __launch_bounds__(kT) void check_kernel(const double* __restrict__ pa
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *n_active = cnt;
+  if (threadIdx.x == 0) {
+    *n_active = cnt;
+    if (n_active_host) *n_active_host = cnt;  // pinned host copy: the host polls it without a copy launch
+  }
 }
 
 // Start of an inner solve: x = 0, r = b, b2 = ||b||^2 from sums3, active = b2 > 0, iters = 0.
@@ -903,10 +907,11 @@ void gcr_ring_materialize(const void* Z, int64_t fstride, const int* nb, int las
 }
 
 void gcr_check(const double* partial, const FieldShape& f, double tol2, const double* b2, const int* breakdown,
-               int* active, int* iters, double* rn2, int* n_active, int* level_iters, hipStream_t st) {
+               int* active, int* iters, double* rn2, int* n_active, int* level_iters, hipStream_t st,
+               int* n_active_host) {
   const int64_t nch = shape_chunks(f);
   hipLaunchKernelGGL(check_kernel, dim3(1), dim3(kT), 0, st, partial, nch, f.nrhs, tol2, b2, breakdown, active, iters,
-                     rn2, n_active, level_iters);
+                     rn2, n_active, level_iters, n_active_host);
   CRK_LAUNCH_CHECK();
 }
 

@@ -12,6 +12,7 @@
 #pragma once
 
 #include <memory>
+#include <utility>
 #include <vector>
 
 #include "gcr.h"
@@ -33,10 +34,31 @@ struct GcrScalars {
   void alloc(int nrhs, int64_t partial_doubles, bool history = false);
 };
 
+// Pinned host int written by kernels (a polled flag), freed with its owner.
+struct PinnedInt {
+  int* p = nullptr;
+  PinnedInt() = default;
+  PinnedInt(const PinnedInt&) = delete;
+  PinnedInt& operator=(const PinnedInt&) = delete;
+  PinnedInt(PinnedInt&& o) noexcept : p(o.p) { o.p = nullptr; }
+  PinnedInt& operator=(PinnedInt&& o) noexcept {
+    std::swap(p, o.p);
+    return *this;
+  }
+  ~PinnedInt() {
+    if (p) (void)hipHostFree(p);
+  }
+  void alloc() {
+    if (!p) CRK_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), sizeof(int), hipHostMallocCoherent));
+    *p = 1;
+  }
+};
+
 struct LevelWork {      // coarse level l >= 1: inner solve buffers (+ post-smoother fields)
   DevBuf x, r, b, Z, W, rho, q;
   int maxit = 0;
   GcrScalars s;
+  PinnedInt n_active_host;  // active RHS of the last inner iteration, for the host poll
 };
 
 struct FineWork {       // level-0 K-cycle fields in the vector precision

@@ -119,13 +119,15 @@ void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int 
     const int64_t dn = rhs_dot_launch(prec, wi, lw.r.p, f.n, nrhs, f.rs, f.es, s.dpart, st);
     gcr_update_lazy(prec, wi, lw.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, nullptr,
                     s.hinv + size_t(i) * nrhs, s.ha + size_t(i) * nrhs, st);
-    gcr_check(s.partial, f, tol2, s.b2, s.breakdown, s.active, s.iters, s.rn2, s.n_active, s.level_iters, st);
+    gcr_check(s.partial, f, tol2, s.b2, s.breakdown, s.active, s.iters, s.rn2, s.n_active, s.level_iters, st,
+              lw.n_active_host.p);
     K = i + 1;
     // Converged RHS are frozen on the device; the host only polls every few
-    // iterations to stop launching once every RHS is done.
+    // iterations to stop launching once every RHS is done (the check kernel
+    // writes the count to pinned host memory, so a poll is a stream wait only).
     if ((i + 1) % kPollEvery == 0 || i + 1 == lw.maxit) {
-      CRK_HIP(hipMemcpyAsync(&n_active, s.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
       CRK_HIP(hipStreamSynchronize(st));
+      n_active = *static_cast<volatile int*>(lw.n_active_host.p);
       if (n_active == 0) break;
     }
   }
@@ -250,6 +252,7 @@ std::unique_ptr<Workspace> make_workspace(Hierarchy* H, int cap, int form, const
     if (l < H->nlev - 1) { lw.rho.alloc(cv); lw.q.alloc(cv); w.bytes += 2 * cv; }
     lw.Z.alloc(cv * lw.maxit); lw.W.alloc(cv * lw.maxit);
     lw.s.alloc(cap, partial_doubles(int64_t(H->N(l)) * H->V(l), cap, true), true);
+    lw.n_active_host.alloc();
     CRK_HIP(hipMemsetAsync(lw.s.level_iters, 0, sizeof(int) * cap, st));
     w.bytes += cv * (3 + 2 * size_t(lw.maxit));
   }
