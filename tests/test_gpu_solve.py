@@ -145,6 +145,28 @@ def test_max_iter_reports_noconv(crk, c1):
     assert not info["converged"] and info["iters"] == 1 and np.isfinite(x).all()
 
 
+def test_stopped_iterates_have_monotone_true_residuals(crk, c1):
+    """GCR minimises the residual over its directions, so the true residual of
+    the iterate returned after k outer iterations cannot grow with k, across
+    restarts (restart 3) too; the solution is formed from the recorded
+    recursion whenever a slot stops, restarts or claims convergence, and an
+    error there (a dropped or doubled direction) would show as a jump."""
+    lat, H, op, ref = c1
+    b = synth.gaussian_rhs(1, 256, config=11)
+    prev, first = np.inf, None
+    bn = np.linalg.norm(b[0])
+    for k in range(1, 12):
+        x, info = H.solve(b, raise_on_noconv=False, form=0, max_iter=k, restart=3)
+        res = np.linalg.norm(b[0] - as_fields(op.apply(as_columns(x)))[0]) / bn
+        assert abs(res - info["true_rel_resid"]) <= 1e-12 + 1e-9 * res, (k, res, info["true_rel_resid"])
+        assert res <= prev * (1 + 1e-9), (k, res, prev)
+        prev = res
+        first = res if first is None else first
+        if info["converged"]:
+            break
+    assert prev < 0.1 * first  # and the iterations do make progress
+
+
 def test_three_level_solve_matches_oracle(crk):
     dims = [4, 4, 4, 4]
     U = synth.gauge_field(dims, 0.3, 0, config=8)
