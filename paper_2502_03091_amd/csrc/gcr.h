@@ -26,26 +26,20 @@ int64_t gcr_partial_rows(int64_t n, bool inner);
 
 void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* w, const FieldShape& f, double* partial,
                   const uint32_t* valid, double2* coef, hipStream_t st);
-// Sums the stored directions cyclically from slot j_first (the oldest one).
-void gcr_multiaxpy(int prec, const void* Z, const void* W, int64_t fstride, int nj, int j_first, void* z, void* w,
-                   const double2* coef, const FieldShape& f, hipStream_t st);
-void gcr_scalars(const double* sums3, const int* active, int nrhs, double* inv, double2* a, int* breakdown,
-                 hipStream_t st);
-void gcr_update(int prec, void* z, void* w, void* x, void* r, const double* inv, const double2* a, const int* active,
-                const FieldShape& f, double* partial, double* rn2, hipStream_t st);
-// gcr_scalars + gcr_update in one launch, the <w, r>, ||w||^2 partials (dpart,
-// dnch chunks, from rhs_dot_launch) reduced inside every workgroup.
-void gcr_update_fused(int prec, void* z, void* w, void* x, void* r, const double* dpart, int64_t dnch,
-                      const int* active, int* breakdown, const FieldShape& f, double* partial, double* rn2,
-                      hipStream_t st);
-// Inner solves on rhs-inner fields keep the preconditioned directions z_i as
-// they are and form the solution once at the end (lazy): the iterations only
-// orthogonalise and normalise w, update r and record c_ij (hcoef, per
-// iteration [nrhs][kMaxCoef]), 1/||w_i|| (hinv[i][r]) and a_i (ha[i][r]).
+// The solvers keep the preconditioned directions z_i as they are and form the
+// solution from them when it is needed (lazy): an iteration only
+// orthogonalises w_i against the stored directions (classical Gram-Schmidt,
+// summed cyclically from slot j_first, the oldest), normalises it, updates r
+// (with the <w_i, r>, ||w_i||^2 partials dpart of dnch chunks from
+// rhs_dot_launch, reduced inside every workgroup), and records c_ij (the
+// multidot's coef), 1/||w_i|| (hinv[r]) and a_i (ha[r]); rn2 (optional)
+// receives ||r||^2.
 void gcr_multiaxpy_w(int prec, const void* W, int64_t fstride, int nj, int j_first, void* w, const double2* coef,
                      const FieldShape& f, hipStream_t st);
 void gcr_update_lazy(int prec, void* w, void* r, const double* dpart, int64_t dnch, const int* active, int* breakdown,
                      const FieldShape& f, double* partial, double* rn2, double* hinv, double2* ha, hipStream_t st);
+// Inner solve of K iterations with records c_ij at hcoef[i][nrhs][kMaxCoef],
+// 1/||w_i|| and a_i at hinv/ha[i][nrhs]:
 // x = sum_{i<K} d_i z_i with the d_i of the recorded recursion (dcoef: [nrhs][kMaxCoef] work space).
 void gcr_lazy_solution(int prec, const void* Z, int64_t fstride, int K, void* x, const double2* hcoef,
                        const double* hinv, const double2* ha, double2* dcoef, const FieldShape& f, hipStream_t st);

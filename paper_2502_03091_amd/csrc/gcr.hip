@@ -218,12 +218,11 @@ __global__ __launch_bounds__(kT) void multidot_reduce_kernel(const double* __res
   }
 }
 
-// z -= sum_j coef_j Z_j ; w -= sum_j coef_j W_j, summed from stored slot j_first
+// w -= sum_j coef_j W_j, summed from stored slot j_first
 // onwards (cyclically), i.e. oldest direction first: the rounding of an RHS's
 // update then depends only on its own directions, not on where in a ring they sit.
-template <class C, bool WZ>
-__global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb, const C* __restrict__ Wb,
-                                                       int64_t fstride, int nj, int j_first, C* __restrict__ z,
+template <class C>
+__global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Wb, int64_t fstride, int nj, int j_first,
                                                        C* __restrict__ w, const double2* __restrict__ coef, int64_t n,
                                                        int nrhs, int64_t rs, int64_t es) {
   constexpr int kU = 4;  // directions whose loads are issued together
@@ -233,9 +232,9 @@ __global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb,
   const int64_t e = es == 1 ? t % n : t / nrhs;
   const int64_t idx = int64_t(r) * rs + e * es;
   using T = decltype(C::x);
-  C zz = WZ ? z[idx] : C{}, ww = w[idx];
+  C ww = w[idx];
   for (int t0 = 0; t0 < nj; t0 += kU) {
-    C zl[kU], wl[kU], c[kU];
+    C wl[kU], c[kU];
     int jj[kU];
     bool on[kU];
     // coefficients first, so that the direction loads below are issued back to back
@@ -253,84 +252,30 @@ __global__ __launch_bounds__(kT) void multiaxpy_kernel(const C* __restrict__ Zb,
 #pragma unroll
     for (int u = 0; u < kU; ++u) any |= on[u];
     if (!any) continue;
-    // a skipped direction re-reads this thread's own z, w entries (already in
+    // a skipped direction re-reads this thread's own w entry (already in
     // cache) instead of branching, so all loads stay in flight together
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int64_t off = on[u] ? jj[u] * fstride + idx : idx;
-      if constexpr (WZ) zl[u] = (on[u] ? Zb : static_cast<const C*>(z))[off];
       wl[u] = (on[u] ? Wb : static_cast<const C*>(w))[off];
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      if (on[u]) {
-        if constexpr (WZ) cfma(zz, c[u], zl[u]);
-        cfma(ww, c[u], wl[u]);
-      }
+      if (on[u]) cfma(ww, c[u], wl[u]);
     }
   }
-  if constexpr (WZ) z[idx] = zz;
   w[idx] = ww;
-}
-
-// From sums3[r] = (<w,r>, ||w||^2): inv[r] = 1/||w||, a[r] = <w,r>/||w|| (zero unless active and finite).
-__global__ void scalars_kernel(const double* __restrict__ sums3, const int* __restrict__ active, int nrhs,
-                               double* __restrict__ inv, double2* __restrict__ a, int* __restrict__ breakdown) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  const double ww = sums3[3 * r + 2];
-  const double nw = sqrt(ww);
-  const bool ok = active[r] && ww > 0.0 && isfinite(nw);
-  inv[r] = ok ? 1.0 / nw : 0.0;
-  a[r] = ok ? make_double2(sums3[3 * r] / nw, sums3[3 * r + 1] / nw) : make_double2(0, 0);
-  if (breakdown) breakdown[r] = active[r] && !ok;
-}
-
-// w *= inv; z *= inv; (active) x += a z; r -= a w; partial ||r||^2
-template <class C>
-__global__ __launch_bounds__(kT) void update_kernel(C* __restrict__ z, C* __restrict__ w, C* __restrict__ x,
-                                                    C* __restrict__ res, const double* __restrict__ inv,
-                                                    const double2* __restrict__ a, const int* __restrict__ active,
-                                                    int64_t n, int nrhs, int64_t rs, int64_t es, int64_t chunk,
-                                                    double* __restrict__ partial) {
-  __shared__ double sh[4];
-  using T = decltype(C::x);
-  const int r = blockIdx.y;
-  const int64_t e0 = int64_t(blockIdx.x) * chunk, e1 = min(n, e0 + chunk);
-  const T s = T(inv[r]);
-  const bool act = active[r] != 0;
-  const C ar = mk<C>(T(a[r].x), T(a[r].y));
-  double acc = 0;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const int64_t idx = int64_t(r) * rs + e * es;
-    const C zn = cscale(z[idx], s), wn = cscale(w[idx], s);
-    z[idx] = zn;
-    w[idx] = wn;
-    C rr = res[idx];
-    if (act) {
-      C xx = x[idx];
-      cfma(xx, ar, zn);
-      x[idx] = xx;
-      const C aw = cmul(ar, wn);
-      rr.x -= aw.x;
-      rr.y -= aw.y;
-      res[idx] = rr;
-    }
-    acc += double(rr.x) * rr.x + double(rr.y) * rr.y;
-  }
-  const double t = wsum(acc);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
-  __syncthreads();
-  if (threadIdx.x == 0) partial[int64_t(blockIdx.x) * nrhs + r] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // update with the scalars computed in place: every workgroup of RHS r first adds
 // the <w, r>, ||w||^2 partials of its RHS (lane l takes chunks l, l + 64, ... in
 // order, then a fixed shuffle tree; the same in every workgroup) and derives
 // inv = 1/||w|| and a = <w, r>/||w||, which saves the reduction and scalar launches.
-template <class C, bool LAZY>
-__global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ z, C* __restrict__ w, C* __restrict__ x,
-                                                          C* __restrict__ res, const double* __restrict__ dpart,
+// Then w *= inv and r -= a w; inv and a go to hinv[r], ha[r] (the solution is
+// formed later from the recorded recursion), and ||r||^2 to the partials.
+template <class C>
+__global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ w, C* __restrict__ res,
+                                                          const double* __restrict__ dpart,
                                                           int64_t dnch, const int* __restrict__ active,
                                                           int* __restrict__ breakdown, int64_t n, int nrhs,
                                                           int64_t rs, int64_t es, int64_t chunk,
@@ -362,11 +307,9 @@ __global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ z, C* 
   const bool act0 = active[r] != 0;
   const bool ok = act0 && ww > 0.0 && isfinite(nw);
   if (blockIdx.x == 0 && threadIdx.x == 0 && breakdown) breakdown[r] = act0 && !ok;
-  if constexpr (LAZY) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      hinv[r] = ok ? 1.0 / nw : 0.0;
-      ha[r] = ok ? make_double2(scal[0] / nw, scal[1] / nw) : make_double2(0, 0);
-    }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    hinv[r] = ok ? 1.0 / nw : 0.0;
+    ha[r] = ok ? make_double2(scal[0] / nw, scal[1] / nw) : make_double2(0, 0);
   }
   const T s = T(ok ? 1.0 / nw : 0.0);
   const bool act = ok;
@@ -378,15 +321,6 @@ __global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ z, C* 
     const C wn = cscale(w[idx], s);
     w[idx] = wn;
     C rr = res[idx];
-    if constexpr (!LAZY) {
-      const C zn = cscale(z[idx], s);
-      z[idx] = zn;
-      if (act) {
-        C xx = x[idx];
-        cfma(xx, ar, zn);
-        x[idx] = xx;
-      }
-    }
     if (act) {
       const C aw = cmul(ar, wn);
       rr.x -= aw.x;
@@ -405,12 +339,8 @@ __global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ z, C* 
 // to 16 RHS), thread (l, r) with r fastest (coalesced), entries l, l + 64, ...
 // of the chunk per thread; every sum over lanes runs in lane order, so an RHS's
 // numbers do not depend on how many RHS share the field.
-// LAZY: the solution is not updated here (x = sum_i d_i z_i is formed once
-// after the iterations from the stored coefficients), z is left as it came
-// from the preconditioner, and 1/||w||, a of every RHS go to hinv[r], ha[r].
-template <class C, bool LAZY>
-__global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __restrict__ z, C* __restrict__ w,
-                                                                         C* __restrict__ x, C* __restrict__ res,
+template <class C>
+__global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __restrict__ w, C* __restrict__ res,
                                                                          const double* __restrict__ dpart,
                                                                          int64_t dnch, const int* __restrict__ active,
                                                                          int* __restrict__ breakdown, int64_t n,
@@ -451,11 +381,9 @@ __global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __re
     const bool act0 = active[r] != 0;
     const bool ok = act0 && ww > 0.0 && isfinite(nw);
     if (blockIdx.x == 0 && l == 0 && breakdown) breakdown[r] = act0 && !ok;
-    if constexpr (LAZY) {
-      if (blockIdx.x == 0 && l == 0) {
-        hinv[r] = ok ? 1.0 / nw : 0.0;
-        ha[r] = ok ? make_double2(scal[rl][0] / nw, scal[rl][1] / nw) : make_double2(0, 0);
-      }
+    if (blockIdx.x == 0 && l == 0) {
+      hinv[r] = ok ? 1.0 / nw : 0.0;
+      ha[r] = ok ? make_double2(scal[rl][0] / nw, scal[rl][1] / nw) : make_double2(0, 0);
     }
     const T sc = T(ok ? 1.0 / nw : 0.0);
     const C ar = ok ? mk<C>(T(scal[rl][0] / nw), T(scal[rl][1] / nw)) : mk<C>(T(0), T(0));
@@ -466,15 +394,6 @@ __global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __re
       const C wn = cscale(w[idx], sc);
       w[idx] = wn;
       C rr = res[idx];
-      if constexpr (!LAZY) {
-        const C zn = cscale(z[idx], sc);
-        z[idx] = zn;
-        if (ok) {
-          C xx = x[idx];
-          cfma(xx, ar, zn);
-          x[idx] = xx;
-        }
-      }
       if (ok) {
         const C aw = cmul(ar, wn);
         rr.x -= aw.x;
@@ -755,79 +674,6 @@ void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* 
   }
 }
 
-void gcr_multiaxpy(int prec, const void* Z, const void* W, int64_t fstride, int nj, int j_first, void* z, void* w,
-                   const double2* coef, const FieldShape& f, hipStream_t st) {
-  if (nj <= 0) return;
-  CRK_REQUIRE(nj <= kMaxCoef, "GCR basis above 64 vectors");
-  CRK_REQUIRE(j_first >= 0 && j_first < nj, "GCR ring start out of range");
-  const dim3 g(ceil_div(f.n * f.nrhs, kT));
-  if (prec == CRK_FORM_FP64)
-    hipLaunchKernelGGL((multiaxpy_kernel<double2, true>), g, dim3(kT), 0, st, static_cast<const double2*>(Z),
-                       static_cast<const double2*>(W), fstride, nj, j_first, static_cast<double2*>(z),
-                       static_cast<double2*>(w),
-                       coef, f.n, f.nrhs, f.rs, f.es);
-  else
-    hipLaunchKernelGGL((multiaxpy_kernel<float2, true>), g, dim3(kT), 0, st, static_cast<const float2*>(Z),
-                       static_cast<const float2*>(W), fstride, nj, j_first, static_cast<float2*>(z),
-                       static_cast<float2*>(w),
-                       coef, f.n, f.nrhs, f.rs, f.es);
-  CRK_LAUNCH_CHECK();
-}
-
-void gcr_scalars(const double* sums3, const int* active, int nrhs, double* inv, double2* a, int* breakdown,
-                 hipStream_t st) {
-  hipLaunchKernelGGL(scalars_kernel, dim3(ceil_div(nrhs, 64)), dim3(64), 0, st, sums3, active, nrhs, inv, a, breakdown);
-  CRK_LAUNCH_CHECK();
-}
-
-void gcr_update(int prec, void* z, void* w, void* x, void* r, const double* inv, const double2* a, const int* active,
-                const FieldShape& f, double* partial, double* rn2, hipStream_t st) {
-  const int64_t chunk = chunk_for_shape(f.n, f.es != 1), nch = shape_chunks(f);
-  const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
-  if (prec == CRK_FORM_FP64)
-    hipLaunchKernelGGL(update_kernel<double2>, g, dim3(kT), 0, st, static_cast<double2*>(z), static_cast<double2*>(w),
-                       static_cast<double2*>(x), static_cast<double2*>(r), inv, a, active, f.n, f.nrhs, f.rs, f.es,
-                       chunk, partial);
-  else
-    hipLaunchKernelGGL(update_kernel<float2>, g, dim3(kT), 0, st, static_cast<float2*>(z), static_cast<float2*>(w),
-                       static_cast<float2*>(x), static_cast<float2*>(r), inv, a, active, f.n, f.nrhs, f.rs, f.es,
-                       chunk, partial);
-  CRK_LAUNCH_CHECK();
-  if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
-}
-
-void gcr_update_fused(int prec, void* z, void* w, void* x, void* r, const double* dpart, int64_t dnch,
-                      const int* active, int* breakdown, const FieldShape& f, double* partial, double* rn2,
-                      hipStream_t st) {
-  const int64_t chunk = chunk_for_shape(f.n, f.es != 1), nch = shape_chunks(f);
-  const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
-  if (f.es != 1 && f.rs == 1 && f.es == f.nrhs) {
-    const dim3 grg = dim3(unsigned(nch), unsigned((f.nrhs + kInnerRhs - 1) / kInnerRhs));
-    const dim3 brg = dim3(unsigned(64 * std::min(f.nrhs, kInnerRhs)));
-    if (prec == CRK_FORM_FP64)
-      hipLaunchKernelGGL((update_fused_rg_kernel<double2, false>), grg, brg, 0, st, static_cast<double2*>(z),
-                         static_cast<double2*>(w), static_cast<double2*>(x), static_cast<double2*>(r), dpart, dnch,
-                         active, breakdown, f.n, f.nrhs, partial, nullptr, nullptr);
-    else
-      hipLaunchKernelGGL((update_fused_rg_kernel<float2, false>), grg, brg, 0, st, static_cast<float2*>(z),
-                         static_cast<float2*>(w), static_cast<float2*>(x), static_cast<float2*>(r), dpart, dnch,
-                         active, breakdown, f.n, f.nrhs, partial, nullptr, nullptr);
-    CRK_LAUNCH_CHECK();
-    if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
-    return;
-  }
-  if (prec == CRK_FORM_FP64)
-    hipLaunchKernelGGL((update_fused_kernel<double2, false>), g, dim3(kT), 0, st, static_cast<double2*>(z),
-                       static_cast<double2*>(w), static_cast<double2*>(x), static_cast<double2*>(r), dpart, dnch,
-                       active, breakdown, f.n, f.nrhs, f.rs, f.es, chunk, partial, nullptr, nullptr);
-  else
-    hipLaunchKernelGGL((update_fused_kernel<float2, false>), g, dim3(kT), 0, st, static_cast<float2*>(z),
-                       static_cast<float2*>(w), static_cast<float2*>(x), static_cast<float2*>(r), dpart, dnch, active,
-                       breakdown, f.n, f.nrhs, f.rs, f.es, chunk, partial, nullptr, nullptr);
-  CRK_LAUNCH_CHECK();
-  if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
-}
-
 void gcr_multiaxpy_w(int prec, const void* W, int64_t fstride, int nj, int j_first, void* w, const double2* coef,
                      const FieldShape& f, hipStream_t st) {
   if (nj <= 0) return;
@@ -835,13 +681,11 @@ void gcr_multiaxpy_w(int prec, const void* W, int64_t fstride, int nj, int j_fir
   CRK_REQUIRE(j_first >= 0 && j_first < nj, "GCR ring start out of range");
   const dim3 g(ceil_div(f.n * f.nrhs, kT));
   if (prec == CRK_FORM_FP64)
-    hipLaunchKernelGGL((multiaxpy_kernel<double2, false>), g, dim3(kT), 0, st, nullptr,
-                       static_cast<const double2*>(W), fstride, nj, j_first, nullptr, static_cast<double2*>(w), coef, f.n,
-                       f.nrhs, f.rs, f.es);
+    hipLaunchKernelGGL(multiaxpy_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(W), fstride, nj,
+                       j_first, static_cast<double2*>(w), coef, f.n, f.nrhs, f.rs, f.es);
   else
-    hipLaunchKernelGGL((multiaxpy_kernel<float2, false>), g, dim3(kT), 0, st, nullptr,
-                       static_cast<const float2*>(W), fstride, nj, j_first, nullptr, static_cast<float2*>(w), coef, f.n,
-                       f.nrhs, f.rs, f.es);
+    hipLaunchKernelGGL(multiaxpy_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(W), fstride, nj,
+                       j_first, static_cast<float2*>(w), coef, f.n, f.nrhs, f.rs, f.es);
   CRK_LAUNCH_CHECK();
 }
 
@@ -852,13 +696,13 @@ void gcr_update_lazy(int prec, void* w, void* r, const double* dpart, int64_t dn
     const int64_t chunk = chunk_for_shape(f.n, f.es != 1);
     const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
     if (prec == CRK_FORM_FP64)
-      hipLaunchKernelGGL((update_fused_kernel<double2, true>), g, dim3(kT), 0, st, nullptr, static_cast<double2*>(w),
-                         nullptr, static_cast<double2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, f.rs, f.es,
-                         chunk, partial, hinv, ha);
+      hipLaunchKernelGGL(update_fused_kernel<double2>, g, dim3(kT), 0, st, static_cast<double2*>(w),
+                         static_cast<double2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, f.rs, f.es, chunk,
+                         partial, hinv, ha);
     else
-      hipLaunchKernelGGL((update_fused_kernel<float2, true>), g, dim3(kT), 0, st, nullptr, static_cast<float2*>(w),
-                         nullptr, static_cast<float2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, f.rs, f.es,
-                         chunk, partial, hinv, ha);
+      hipLaunchKernelGGL(update_fused_kernel<float2>, g, dim3(kT), 0, st, static_cast<float2*>(w),
+                         static_cast<float2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, f.rs, f.es, chunk,
+                         partial, hinv, ha);
     CRK_LAUNCH_CHECK();
     if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
     return;
@@ -866,13 +710,11 @@ void gcr_update_lazy(int prec, void* w, void* r, const double* dpart, int64_t dn
   const dim3 grg = dim3(unsigned(nch), unsigned((f.nrhs + kInnerRhs - 1) / kInnerRhs));
   const dim3 brg = dim3(unsigned(64 * std::min(f.nrhs, kInnerRhs)));
   if (prec == CRK_FORM_FP64)
-    hipLaunchKernelGGL((update_fused_rg_kernel<double2, true>), grg, brg, 0, st, nullptr, static_cast<double2*>(w),
-                       nullptr, static_cast<double2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, partial, hinv,
-                       ha);
+    hipLaunchKernelGGL(update_fused_rg_kernel<double2>, grg, brg, 0, st, static_cast<double2*>(w),
+                       static_cast<double2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, partial, hinv, ha);
   else
-    hipLaunchKernelGGL((update_fused_rg_kernel<float2, true>), grg, brg, 0, st, nullptr, static_cast<float2*>(w),
-                       nullptr, static_cast<float2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, partial, hinv,
-                       ha);
+    hipLaunchKernelGGL(update_fused_rg_kernel<float2>, grg, brg, 0, st, static_cast<float2*>(w),
+                       static_cast<float2*>(r), dpart, dnch, active, breakdown, f.n, f.nrhs, partial, hinv, ha);
   CRK_LAUNCH_CHECK();
   if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
 }

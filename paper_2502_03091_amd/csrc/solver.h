@@ -23,8 +23,8 @@ namespace crk {
 // Device scalars of one GCR instance.
 struct GcrScalars {
   DevBuf buf;
-  double *sums3, *b2, *rn2, *inv, *partial, *dpart;
-  double2 *a, *coef;
+  double *sums3, *b2, *rn2, *partial, *dpart;
+  double2* a;  // per-RHS minimal-residual step of the post-smoother
   int *active, *iters, *breakdown, *n_active, *level_iters;
   uint32_t* valid;
   // lazy inner solves: per iteration c_ij [kMaxCoef][nrhs][kMaxCoef], 1/||w_i||

@@ -28,8 +28,7 @@ void GcrScalars::alloc(int nrhs, int64_t partial_doubles, bool history) {
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off += (b + 255) & ~size_t(255); return o; };
   const size_t o_s3 = take(sizeof(double) * 3 * nr), o_b2 = take(sizeof(double) * nr),
-               o_rn = take(sizeof(double) * nr), o_inv = take(sizeof(double) * nr),
-               o_a = take(sizeof(double2) * nr), o_coef = take(sizeof(double2) * nr * kMaxCoef),
+               o_rn = take(sizeof(double) * nr), o_a = take(sizeof(double2) * nr),
                o_act = take(sizeof(int) * nr), o_it = take(sizeof(int) * nr), o_bd = take(sizeof(int) * nr),
                o_na = take(sizeof(int)), o_li = take(sizeof(int) * nr), o_val = take(sizeof(uint32_t) * nr),
                o_part = take(sizeof(double) * size_t(partial_doubles)),
@@ -42,9 +41,7 @@ void GcrScalars::alloc(int nrhs, int64_t partial_doubles, bool history) {
   sums3 = reinterpret_cast<double*>(c + o_s3);
   b2 = reinterpret_cast<double*>(c + o_b2);
   rn2 = reinterpret_cast<double*>(c + o_rn);
-  inv = reinterpret_cast<double*>(c + o_inv);
   a = reinterpret_cast<double2*>(c + o_a);
-  coef = reinterpret_cast<double2*>(c + o_coef);
   active = reinterpret_cast<int*>(c + o_act);
   iters = reinterpret_cast<int*>(c + o_it);
   breakdown = reinterpret_cast<int*>(c + o_bd);
