@@ -20,7 +20,9 @@ Other workloads (one JSON line each): --workload iso32 (32^4, m' = 64 -> k = 24,
 12 point sources, FP64 / FP32 / FP16S forms), --workload volume (three-level
 hierarchies on 24^3x48, 32^3x64, 48^3x96, rank-k vs conventional) and
 --workload serve (Poisson arrival-rate sweep of the serving loop over resident
-16^3x32, 24^3x48 and 32^4 hierarchies).
+16^3x32, 24^3x48 and 32^4 hierarchies), --workload kernels (operator launches
+per form and RHS count) and --workload params (setup and solve over m', k and
+the number of setup sweeps on the default workload).
 """
 from __future__ import annotations
 
@@ -301,6 +303,68 @@ def workload_volume(crk, args):
     }
 
 
+# ------------------------------------------------------------------ parameter sweeps
+PARAM_SWEEPS = {
+    # enlarged basis m' at fixed k (Sec. 4, Fig. 1: solve time against m' for k fixed)
+    "m_prime": [dict(m_prime=m, k=24, n_smooth=N_SMOOTH) for m in (24, 32, 40, 48, 56, 64)],
+    # kept rank k at the largest m' the SVD kernel takes (Sec. 4, Figs. 3-4: k at fixed m')
+    "k": [dict(m_prime=64, k=k, n_smooth=N_SMOOTH) for k in (8, 16, 24, 32)],
+    # setup iterations for rank-k (m' = 48 -> 24) and the conventional basis (24 -> 24) (Sec. 4, Figs. 5-6)
+    "n_smooth": [dict(m_prime=m, k=24, n_smooth=n) for m in (48, 24) for n in (5, 10, 20, 40, 60, 100)],
+}
+
+
+def workload_params(crk, args):
+    """Setup and 10-RHS solve on the anisotropic 16^3x32 workload over m', k and the
+    number of setup sweeps, everything else as in the default workload."""
+    import torch
+    dev = torch.device("cuda", 0)
+    V = int(np.prod(DIMS))
+    m0 = tuned_m0("aniso_xi3.5_eps0.2")
+    U = synth.gauge_field(DIMS, EPS, N_APE, config=CONFIG)
+    lat = crk.Lattice(DIMS, m0, XI)
+    lat.load_gauge(U)
+    b = torch.from_numpy(synth.gaussian_rhs(NRHS, V, config=CONFIG).view(np.float64)).to(dev)
+    x = torch.empty_like(b)
+    H = crk.Hierarchy(lat, m_prime=[M_PRIME], k=[K], block=[BLOCK], n_smooth=[N_SMOOTH],
+                      setup_form=crk.FORM_FP32, seed=0x2502030910)   # warm-up of every kernel
+    H.solve_dev(b, x, NRHS, form=crk.FORM_FP32, raise_on_noconv=False, **SOLVE)
+    H.close()
+    rows = []
+    for sweep, points in PARAM_SWEEPS.items():
+        for pt in points:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H = crk.Hierarchy(lat, m_prime=[pt["m_prime"]], k=[pt["k"]], block=[BLOCK], n_smooth=[pt["n_smooth"]],
+                              setup_form=crk.FORM_FP32, seed=0x2502030910)
+            t1 = time.perf_counter()
+            info = H.solve_dev(b, x, NRHS, form=crk.FORM_FP32, raise_on_noconv=False, **SOLVE)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            tim = H.timing(0)
+            H.close()
+            row = {"sweep": sweep, **pt, "setup_s": t1 - t0,
+                   "setup_stages_s": {k_: tim[k_] for k_ in ("smoother", "svd", "galerkin")},
+                   "smoother_vector_sweeps": pt["m_prime"] * pt["n_smooth"],
+                   "solve_s": t2 - t1, "iters": info["iters"], "level_iters": info["level_iters"],
+                   "s_per_outer_iter": (t2 - t1) / max(1, info["iters"]),
+                   "true_rel_resid": info["true_rel_resid"], "converged": info["converged"]}
+            log("params", json.dumps(row))
+            rows.append(row)
+    lat.close()
+    best = min((r for r in rows if r["converged"]), key=lambda r: r["setup_s"] + r["solve_s"], default=None)
+    return {
+        "metric": "setup s, solve s and outer iterations against m', k and setup sweeps (chiral rank-k)",
+        "value": best["setup_s"] + best["solve_s"] if best else None, "unit": "s", "higher_is_better": False,
+        "n_gpus": 1, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "16^3x32 xi=3.5 (eps=0.2, 3 APE), m0 = m_c + 0.01, 4^4 blocks, FP32 MR setup, "
+                               "two levels, 10 Gaussian RHS to 1e-10 (FP32 K-cycle, FP64 outer GCR); value = "
+                               "the smallest setup + solve over the sweep", "m0": m0,
+                   "parallelism": "none (1 GPU)"},
+        "best": best, "rows": rows,
+    }
+
+
 # ------------------------------------------------------------------ kernel sweeps
 FORM_NAMES = {0: "FP64", 1: "FP32", 2: "FP16S"}
 MFMA_PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0}  # dense MFMA peaks: fp64, fp32, fp16 inputs
@@ -524,7 +588,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="aniso16", choices=["aniso16", "iso32", "volume", "serve", "kernels"])
+    ap.add_argument("--workload", default="aniso16",
+                    choices=["aniso16", "iso32", "volume", "serve", "kernels", "params"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -542,7 +607,7 @@ def main():
 
     import paper_2502_03091_amd as crk
     fn = {"aniso16": workload_aniso16, "iso32": workload_iso32, "volume": workload_volume,
-          "serve": workload_serve, "kernels": workload_kernels}[args.workload]
+          "serve": workload_serve, "kernels": workload_kernels, "params": workload_params}[args.workload]
     if args.volumes is None:
         args.volumes = "16,32,48" if args.workload == "kernels" else "24,32,48"
     print(json.dumps(fn(crk, args)), flush=True)
