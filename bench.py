@@ -255,6 +255,16 @@ def workload_iso32(crk, args):
 
 # ------------------------------------------------------------------ three-level volume sweep
 
+# (name, m' per step, k per step, sweeps per step, level-2 setup from the coarse test vectors)
+VOLUME_BASES = (
+    ("rank_k", [64, 48], [24, 32], [N_SMOOTH, N_SMOOTH], False),
+    ("conventional", [24, 32], [24, 32], [N_SMOOTH, N_SMOOTH], False),
+    ("rank_k_coarse_init", [64, 48], [24, 32], [N_SMOOTH, N_SMOOTH], True),
+    ("rank_k_coarse_init_20", [64, 48], [24, 32], [N_SMOOTH, 20], True),
+    ("rank_k_20", [64, 48], [24, 32], [N_SMOOTH, 20], False),
+)
+
+
 def workload_volume(crk, args):
     m0 = tuned_m0("iso_xi1_eps0.25")
     import torch
@@ -270,12 +280,12 @@ def workload_volume(crk, args):
         torch.cuda.empty_cache()
         b = torch.from_numpy(synth.gaussian_rhs(1, V, config=ISO["config"]).view(np.float64)).to(dev)
         x = torch.empty_like(b)
-        for name, mp, k in (("rank_k", [64, 48], [24, 32]), ("conventional", [24, 32], [24, 32])):
-            row = {"lattice": dims, "basis": name, "m_prime": mp, "k": k}
+        for name, mp, k, ns, ci in VOLUME_BASES:
+            row = {"lattice": dims, "basis": name, "m_prime": mp, "k": k, "n_smooth": ns, "coarse_init": ci}
             try:
                 t0 = time.perf_counter()
-                H = crk.Hierarchy(lat, m_prime=mp, k=k, block=[BLOCK, [2, 2, 2, 2]], n_smooth=[N_SMOOTH, N_SMOOTH],
-                                  setup_form=crk.FORM_FP32, seed=0x2502030910)
+                H = crk.Hierarchy(lat, m_prime=mp, k=k, block=[BLOCK, [2, 2, 2, 2]], n_smooth=ns,
+                                  setup_form=crk.FORM_FP32, seed=0x2502030910, coarse_init=ci)
                 t1 = time.perf_counter()
                 info = H.solve_dev(b, x, 1, form=crk.FORM_FP32, raise_on_noconv=False, **SOLVE)
                 torch.cuda.synchronize()
@@ -298,7 +308,8 @@ def workload_volume(crk, args):
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "24^3x48, 32^3x64, 48^3x96, xi=1 (eps=0.25, 3 APE), m0 = m_c + 0.01; levels "
                                "(64->24, 4^4) and (48->32, 2^4) vs conventional (24, 32); 60 FP32 MR sweeps per "
-                               "level; one Gaussian RHS to 1e-10", "m0": m0, "parallelism": "none (1 GPU)"},
+                               "level, and rank-k with the second step started from the coarse test vectors "
+                               "(60 or 20 sweeps there); one Gaussian RHS to 1e-10", "m0": m0, "parallelism": "none (1 GPU)"},
         "rows": rows,
     }
 

@@ -133,6 +133,13 @@ typedef struct {
                                           device memory is short (then halved until r, q fit) */
   int32_t svd_batch;                   /* blocks per SVD batch, 0 = all unless the work space would
                                           exceed a quarter of the free device memory */
+  int32_t coarse_init;                 /* 1: a coarsening step l >= 1 without init_vectors[l] starts
+                                          from the coarse test vectors of step l-1 instead of random
+                                          vectors: per block and chirality Sigma_k V_k^dag of the
+                                          truncated SVD (Sec. 3, after Eq. (5)), i.e. P^dag of the
+                                          first m'_l (normalised) test vectors of step l-1, computed
+                                          on the device by the restriction in the setup form.
+                                          Requires m'_l <= m'_{l-1}.  0 (default): random vectors. */
 } crk_mg_params;
 
 /* Fill p with defaults (two levels, m'=48, k=24, 4^4 blocks, 20 sweeps, FP32 smoother). */

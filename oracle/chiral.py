@@ -122,6 +122,17 @@ def restrict(Pb, v, dims, block):
     return out.reshape(d, 2 * k, C)
 
 
+def coarse_test_vectors(A, Pb):
+    """Coarse test vectors (Sec. 3, after Eq. (5)): for block j and chirality a the
+    truncated SVD A_{j,a} ~ U_k Sigma_k V_k^dag leaves Sigma_k V_k^dag = U_k^dag A_{j,a}
+    (U_k with the prolongator's phase convention), the coordinates of the m' test
+    vectors in the kept basis.  Returned as a coarse field [d, 2k, m']: component
+    a k + i of coarse site j."""
+    C = np.einsum("jari,jarc->jaic", np.conj(Pb), A)
+    d, _, k, m = C.shape
+    return C.reshape(d, 2 * k, m)
+
+
 def prolong(Pb, vc, dims, block):
     """P vc: coarse [d, 2k, C] -> fine [V, N, C]."""
     d, _, nr, k = Pb.shape

@@ -28,7 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import lattice
-from .chiral import chiral_blocks, prolongator_blocks, prolong, restrict
+from .chiral import chiral_blocks, coarse_test_vectors, prolongator_blocks, prolong, restrict
 from .galerkin import galerkin
 from .mr import cdot, mr_null, mr_solve, normalize_columns
 
@@ -52,17 +52,27 @@ class CycleParams:
     restart: int = 16
 
 
-def mg_setup(fine_op, m_prime, k, blocks, n_smooth, init_vectors, normalize=True, keep_vectors=False):
-    """Build the hierarchy.  init_vectors[l] is [V_l, N_l, m'_l] (complex Gaussian)."""
+def mg_setup(fine_op, m_prime, k, blocks, n_smooth, init_vectors, normalize=True, keep_vectors=False,
+             coarse_init=False):
+    """Build the hierarchy.  init_vectors[l] is [V_l, N_l, m'_l] (complex Gaussian).
+    With coarse_init, a coarsening step l >= 1 whose init_vectors[l] is None starts
+    from the first m'_l coarse test vectors Sigma_k V_k^dag of step l - 1."""
     levels = []
     op = fine_op
     n_coarse = len(blocks)
+    coarse = None
     for l in range(n_coarse):
-        psi = mr_null(op, init_vectors[l], n_smooth[l])
+        iv = init_vectors[l]
+        if iv is None:
+            if not (coarse_init and coarse is not None and m_prime[l] <= coarse.shape[-1]):
+                raise ValueError("no initial vectors for step %d" % l)
+            iv = np.ascontiguousarray(coarse[:, :, :m_prime[l]])
+        psi = mr_null(op, iv, n_smooth[l])
         if normalize:
             psi = normalize_columns(psi)
         A = chiral_blocks(psi, op.dims, blocks[l])
         Pb, S = prolongator_blocks(A, k[l])
+        coarse = coarse_test_vectors(A, Pb)
         Dc = galerkin(op, Pb, blocks[l])
         levels.append(Level(op, list(blocks[l]), Pb, S, psi if keep_vectors else None))
         op = Dc

@@ -52,6 +52,7 @@ class MGParams(C.Structure):
         ("init_vectors", C.c_void_p * MAX_LEVELS),
         ("smooth_chunk", C.c_int32),
         ("svd_batch", C.c_int32),
+        ("coarse_init", C.c_int32),
     ]
 
 
@@ -306,7 +307,7 @@ class Hierarchy:
 
     def __init__(self, lattice, m_prime=(48,), k=(24,), block=((4, 4, 4, 4),), n_smooth=(20,),
                  setup_form=FORM_FP32, normalize=True, seed=0x2502030910, init_vectors=None, smooth_chunk=0,
-                 svd_batch=0):
+                 svd_batch=0, coarse_init=False):
         self.lattice = lattice
         p = MGParams()
         _load().crk_mg_params_default(C.byref(p))
@@ -323,6 +324,7 @@ class Hierarchy:
         p.seed = int(seed)
         p.smooth_chunk = int(smooth_chunk)
         p.svd_batch = int(svd_batch)
+        p.coarse_init = int(bool(coarse_init))
         keep = []
         if init_vectors is not None:
             for l, v in enumerate(init_vectors):

@@ -37,6 +37,9 @@ void mr_update(int prec, void* psi, void* r, const void* q, const double2* alpha
 // (AoSoA fine fields of V sites, one scale per site and RHS; r is rescaled).
 void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st);
 
+// v[e*nrhs + r] *= f[r] for n entries per rhs (rhs-inner layout).
+void scale_rhs_inner(int prec, void* v, const double* f, int64_t n, int nrhs, hipStream_t st);
+
 // out[i] = 1/sqrt(sums[i*nv + comp]) (0 for a zero sum).
 void inv_sqrt(const double* sums, int nv, int comp, int n, double* out, hipStream_t st);
 

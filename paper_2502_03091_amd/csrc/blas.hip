@@ -199,6 +199,19 @@ __global__ __launch_bounds__(kT) void mr_update_kernel(typename C2<T>::t* __rest
   r[i] = nr;
 }
 
+// v[e * nrhs + r] *= f[r] (rhs-inner field of n entries per rhs); the product in FP64.
+template <class T>
+__global__ __launch_bounds__(kT) void scale_rhs_inner_kernel(typename C2<T>::t* __restrict__ v,
+                                                             const double* __restrict__ f, int64_t n, int nrhs) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  const double a = f[i % nrhs];
+  typename C2<T>::t x = v[i];
+  x.x = T(double(x.x) * a);
+  x.y = T(double(x.y) * a);
+  v[i] = x;
+}
+
 __global__ void inv_sqrt_kernel(const double* __restrict__ sums, int nv, int comp, int n, double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -308,6 +321,16 @@ void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, i
   FineView<CRK_FORM_FP16S> rv(r, V, nrhs), qv(const_cast<void*>(q), V, nrhs);
   hipLaunchKernelGGL(mr_update_h_kernel, dim3(ceil_div(pad_sites(V) * nrhs, kT)), dim3(kT), 0, st,
                      static_cast<float2*>(psi), rv, qv, alpha, V, nrhs);
+  CRK_LAUNCH_CHECK();
+}
+
+void scale_rhs_inner(int prec, void* v, const double* f, int64_t n, int nrhs, hipStream_t st) {
+  if (n * nrhs <= 0) return;
+  const dim3 g(unsigned(ceil_div(n * nrhs, int64_t(kT))));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(scale_rhs_inner_kernel<double>, g, dim3(kT), 0, st, static_cast<double2*>(v), f, n, nrhs);
+  else
+    hipLaunchKernelGGL(scale_rhs_inner_kernel<float>, g, dim3(kT), 0, st, static_cast<float2*>(v), f, n, nrhs);
   CRK_LAUNCH_CHECK();
 }
 

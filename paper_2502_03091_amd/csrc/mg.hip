@@ -42,6 +42,11 @@ void validate(const Lattice* L, const crk_mg_params& p) {
   CRK_REQUIRE(p.n_levels == 2 || p.n_levels == 3, "n_levels must be 2 or 3");
   CRK_REQUIRE(p.setup_form == CRK_FORM_FP64 || p.setup_form == CRK_FORM_FP32, "setup_form must be FP64 or FP32");
   CRK_REQUIRE(p.smooth_chunk >= 0 && p.svd_batch >= 0, "smooth_chunk and svd_batch must be >= 0");
+  CRK_REQUIRE(p.coarse_init == 0 || p.coarse_init == 1, "coarse_init must be 0 or 1");
+  static_assert(CRK_MAX_LEVELS == 3, "coarse_init restricts from the fine step only");
+  for (int l = 1; p.coarse_init && l < p.n_levels - 1; ++l)
+    CRK_REQUIRE(p.init_vectors[l] != nullptr || p.m_prime[l] <= p.m_prime[l - 1],
+                "coarse_init: m' of a step must not exceed m' of the step before");
   CRK_REQUIRE(L->V % kVL == 0, "the fine lattice volume must be a multiple of 64 for a hierarchy");
   int dims[4];
   std::memcpy(dims, L->dims, sizeof(dims));
@@ -183,6 +188,13 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
       CRK_LAUNCH_CHECK();
     }
     CRK_HIP(hipStreamSynchronize(st));  // h is freed at scope exit
+  } else if (inner && p.coarse_init) {
+    // coarse test vectors of the previous step: P^dag (psi_i / ||psi_i||) for
+    // its first m vectors.  Only the step from the fine level precedes a coarse
+    // step (at most three levels); its vectors are rhs-outer, so the first m
+    // are contiguous, and kept in the setup form both steps share.
+    level_restrict(H, l - 1, form, H->vectors[l - 1].p, psi.p, m, st);
+    scale_rhs_inner(form, psi.p, H->inv_norm[l - 1].as<double>(), n, m, st);
   } else {
     gaussian_fill(form, psi.p, n * m, p.seed, uint32_t(l), st);
   }

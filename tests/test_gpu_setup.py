@@ -232,6 +232,41 @@ def test_three_level_setup_matches_oracle(crk):
     assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
 
 
+@pytest.mark.parametrize("form", [0, 1])
+def test_coarse_test_vectors_start_the_second_step(crk, form):
+    """coarse_init: the second coarsening step starts from P^dag of the first m'_1
+    normalised fine test vectors, the coarse test vectors Sigma_k V_k^dag of
+    Sec. 3 (after Eq. (5)).  With no sweeps on the second step its kept vectors
+    are those (the oracle computes them from its SVD blocks); with sweeps the
+    level-2 singular values follow the oracle's.  FP64 setup to 1e-11; FP32 to
+    1e-3: the FP32 smoother's vectors are within 1e-4 of the oracle's (as in the
+    one-step FP32 setup tests), and the kept basis P carries that difference,
+    up to the gaps between singular values, into the coarse vectors."""
+    dims = [4, 4, 4, 4]
+    U = synth.gauge_field(dims, 0.3, 0, config=61)
+    iv0 = synth.gaussian_vectors(16, 256, 12, config=61, level=0)
+    lat = crk.Lattice(dims, -0.4, 1.0)
+    lat.load_gauge(U)
+    op = WilsonOp(U, dims, -0.4, 1.0)
+    blocks = [[2, 2, 2, 2], [2, 2, 2, 2]]
+    tol = 1e-11 if form == 0 else 1e-3
+    for ns in ([10, 0], [10, 6]):
+        H = crk.Hierarchy(lat, m_prime=[16, 12], k=[8, 8], block=blocks, n_smooth=ns, setup_form=form,
+                          init_vectors=[iv0, None], coarse_init=True)
+        ref = omg.mg_setup(op, [16, 12], [8, 8], blocks, ns, [as_columns(iv0), None], keep_vectors=True,
+                           coarse_init=True)
+        v1 = H.vectors(1)
+        vo = as_fields(ref[1].vectors)
+        err = (np.abs(v1 - vo).max(axis=(1, 2)) / np.abs(vo).max(axis=(1, 2))).max()
+        print("coarse_init", form, ns, "vector error", err, flush=True)
+        assert err <= tol, (ns, err)
+        assert np.abs(H.sigma(1) - ref[1].sigma).max() <= tol * ref[1].sigma.max()
+        H.close()
+    with pytest.raises(crk.CrkError):
+        crk.Hierarchy(lat, m_prime=[16, 24], k=[8, 8], block=blocks, n_smooth=[2, 2], init_vectors=[iv0, None],
+                      coarse_init=True)
+
+
 def test_chunked_smoother_and_batched_svd_equal_full(crk):
     """Smoothing the fine-level test vectors in chunks and running the block SVDs
     in batches (what the library does when device memory is short) gives the same

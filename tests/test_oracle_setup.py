@@ -210,3 +210,46 @@ def test_three_level_galerkin_dense():
     assert np.abs(D2.dense() - ref).max() <= 1e-13 * np.abs(ref).max()
     s3 = np.diag(D2.chirality())
     assert np.abs(ref.conj().T - s3 @ ref @ s3).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- coarse test vectors
+def test_coarse_test_vectors_are_sigma_vdag():
+    """Sigma_k V_k^dag = U_k^dag A (Sec. 3, after Eq. (5)): per block and chirality its
+    rows are orthogonal with norms sigma_1..sigma_k of LAPACK's singular values of A,
+    and U_k (Sigma_k V_k^dag) leaves exactly the discarded tail, sum_{i>k} sigma_i^2
+    (Eckart-Young).  The coarse field puts chirality a in components a k .. a k + k - 1,
+    and it equals the restriction P^dag psi of the same vectors."""
+    op = _c1(config=5)
+    block, k, m = [2, 2, 2, 2], 8, 16
+    psi = mr.normalize_columns(mr.mr_null(op, _vectors(op, m, config=5), 10))
+    A = chiral.chiral_blocks(psi, op.dims, block)
+    Pb, _ = chiral.prolongator_blocks(A, k)
+    C = chiral.coarse_test_vectors(A, Pb)
+    d = A.shape[0]
+    assert C.shape == (d, 2 * k, m)
+    for j in range(d):
+        for a in range(2):
+            s = np.linalg.svd(A[j, a], compute_uv=False)
+            Ca = C[j, a * k:(a + 1) * k]
+            G = Ca @ Ca.conj().T
+            assert np.abs(G - np.diag(s[:k] ** 2)).max() <= 1e-12 * s[0] ** 2
+            tail = np.linalg.norm(A[j, a] - Pb[j, a] @ Ca) ** 2
+            assert abs(tail - (s[k:] ** 2).sum()) <= 1e-12 * s[0] ** 2
+    assert np.abs(C - chiral.restrict(Pb, psi, op.dims, block)).max() <= 1e-13
+
+
+def test_three_level_setup_from_coarse_test_vectors():
+    """With coarse_init the second step starts from the first m'_1 coarse test vectors
+    of the first: with no sweeps its kept (normalised) vectors are those, and an
+    m'_1 above m'_0 is refused."""
+    dims = [4, 4, 4, 4]
+    op = _c1(config=61)
+    iv0 = _vectors(op, 16, config=61)
+    L = mg.mg_setup(op, [16, 12], [8, 8], [[2, 2, 2, 2], [2, 2, 2, 2]], [10, 0], [iv0, None],
+                    keep_vectors=True, coarse_init=True)
+    A = chiral.chiral_blocks(L[0].vectors, dims, [2, 2, 2, 2])
+    C = chiral.coarse_test_vectors(A, L[0].Pb)[:, :, :12]
+    ref = mr.normalize_columns(C)
+    assert np.abs(L[1].vectors - ref).max() <= 1e-14
+    with pytest.raises(ValueError):
+        mg.mg_setup(op, [16, 24], [8, 8], [[2, 2, 2, 2], [2, 2, 2, 2]], [10, 0], [iv0, None], coarse_init=True)
