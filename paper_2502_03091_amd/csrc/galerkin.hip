@@ -126,7 +126,9 @@ constexpr int kSiteBatch = 5;
 template <int TI>
 __global__ __launch_bounds__(kT) void galerkin_kernel(GalerkinArgs A) {
   constexpr int N = 16 * TI;  // 2k
-  constexpr int S = kSiteBatch;
+  // at 2k = 64 five sites would take 96 KB of LDS and leave one workgroup per
+  // CU; four keep two (the summation order does not depend on the batch)
+  constexpr int S = TI == 4 ? 4 : kSiteBatch;
   __shared__ double2 T[S][12][N];
   __shared__ double2 Pc[S][6][N];
   __shared__ int list[kGalerkinMaxNb];

@@ -122,6 +122,26 @@ def test_setup_fp64_matches_oracle(crk, dims, block, m, k, ns):
         assert np.abs(ca_g - ca_o).max() <= 1e-11 * np.abs(ca_o).max()
 
 
+@pytest.mark.parametrize("k", [8, 16, 32])
+def test_galerkin_identity_every_tile_height(crk, k):
+    """D_c v = P^dag D P v on 8^4 with 4^4 blocks for 2k = 16, 32 and 64 (every
+    tile height of the fine Galerkin kernel), all through the GPU operators in FP64."""
+    dims, block = [8, 8, 8, 8], [4, 4, 4, 4]
+    print("galerkin identity 8^4 k =", k, flush=True)
+    U = synth.gauge_field(dims, 0.3, 1, config=9)
+    lat = crk.Lattice(dims, -0.3, 1.0)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[32], k=[k], block=[block], n_smooth=[6], setup_form=1)
+    try:
+        vc = synth.gaussian_vectors(3, H.volume(1), 2 * k, config=9, level=5)
+        lhs = H.coarse_apply(1, vc)
+        rhs = H.restrict(0, lat.dirac_apply(H.prolong(0, vc), 0))
+        err = np.abs(lhs - rhs).max() / np.abs(rhs).max()
+        assert err <= 1e-12, err
+    finally:
+        H.close()
+
+
 def test_galerkin_identity_and_sigma3_full_size(crk):
     """16^3x32, xi = 3.5, 4^4 blocks, m' = 48 -> k = 24 (the anisotropic workload), FP32 smoother."""
     dims, block = [16, 16, 16, 32], [4, 4, 4, 4]
