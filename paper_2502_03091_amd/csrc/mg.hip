@@ -189,8 +189,8 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
     }
     CRK_HIP(hipStreamSynchronize(st));  // h is freed at scope exit
   } else if (inner && p.coarse_init) {
-    // coarse test vectors of the previous step: P^dag (psi_i / ||psi_i||) for
-    // its first m vectors.  Only the step from the fine level precedes a coarse
+    // coarse test vectors Sigma_k V_k^dag of the previous step (Sec. 3, after
+    // Eq. (5)), i.e. P^dag (psi_i / ||psi_i||), for its first m vectors.  Only the step from the fine level precedes a coarse
     // step (at most three levels); its vectors are rhs-outer, so the first m
     // are contiguous, and kept in the setup form both steps share.
     level_restrict(H, l - 1, form, H->vectors[l - 1].p, psi.p, m, st);
