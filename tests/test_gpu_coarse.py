@@ -9,13 +9,18 @@ S = sum_j |A_ij| |v_j| (the oracle's stencil applied to |links| and |v|):
 
   * FP64 and FP32 forms: |err| <= sqrt(2) (n + 4) u S  (rounded inputs, complex
     products and the sum; standard forward bound of a dot product);
-  * FP16 links (binary16 of x/s, one FP32 scale s per link block, FP32
-    accumulation): each stored entry is off by at most u16 |A_ij| plus the
-    subnormal spacing 2^-24 s / 2, so |err| <= (u16 + sqrt(2) (n + 4) u32) S
-    + 2^-25 s_max sum_j |v_j|.
+  * FP16S (binary16 links of x/s with one FP32 scale s per link block, and
+    the neighbour's vector column rounded to binary16 of v/w per link and RHS,
+    w its largest |Re|, |Im|; exact binary16 products, FP32 accumulation):
+    both factors carry a relative rounding u16 (or 2^-25 of their scale below
+    the normal range), so
+    |err| <= (2 u16 + u16^2) S + sqrt(2) (n + 6) u32 (1 + 3 u16) S
+             + 2^-25 (1 + u16) (stencil(|A|) W + s_max sum|v|) + tiny,
+    W the per-site w broadcast over components (parity_bounds.coarse_apply_bounds).
 
 A dropped, mis-signed or transposed block changes an entry by a whole term,
-about S / n, which these bounds (at most 0.25 S / n for FP16) exclude.
+about S / n, which these bounds exclude (FP64/FP32 at most 0.05 S / n; FP16S at
+most 0.75 S / n plus its subnormal terms).
 RHS counts 1, 5 and 13 leave MFMA tile columns empty.
 
 Transfers: a coarse entry of P^dag v sums n = 6 |block| terms, a fine entry of
@@ -28,6 +33,7 @@ import pytest
 import synth
 from oracle import chiral
 from oracle.stencil import StencilOp, as_columns, as_fields
+from parity_bounds import coarse_apply_bounds
 
 pytestmark = pytest.mark.gpu
 
@@ -62,24 +68,18 @@ def test_coarse_operator_forms_match_oracle(crk, m_prime, k):
         assert N == 2 * k
         cdims = [2, 2, 2, 4]
         op = StencilOp(cdims, X, Yp, Ym)
-        op_abs = StencilOp(cdims, np.abs(X), np.abs(Yp), np.abs(Ym))
-        smax = max(np.abs(X).max(), np.abs(Yp).max(), np.abs(Ym).max())
-        n = 9 * N
         for nrhs in (1, 5, 13):
             v = synth.gaussian_vectors(nrhs, Vc, N, config=30 + nrhs, level=1)
             ref = as_fields(op.apply(as_columns(v)))
-            S = as_fields(op_abs.apply(as_columns(np.abs(v))))
-            vsum = np.abs(v).sum(axis=(1, 2))[:, None, None]
-            for form, bound in (
-                    (crk.FORM_FP64, np.sqrt(2) * (n + 4) * U64 * S),
-                    (crk.FORM_FP32, np.sqrt(2) * (n + 4) * U32 * S),
-                    (crk.FORM_FP16S, (U16 + np.sqrt(2) * (n + 4) * U32) * S + 2.0 ** -25 * smax * vsum)):
+            bounds, S, n = coarse_apply_bounds(X, Yp, Ym, cdims, v)
+            for form in (crk.FORM_FP64, crk.FORM_FP32, crk.FORM_FP16S):
                 out = H.coarse_apply(1, v, form=form)
-                err = np.abs(out - ref)
-                worst = (err / bound).max()
+                worst = (np.abs(out - ref) / bounds[form]).max()
                 assert worst <= 1.0, (form, nrhs, worst)
-                # and not trivially: a dropped term would be about S / n
-                assert (bound <= 0.25 * S / n + 2.0 ** -25 * smax * vsum).all()
+            # and not trivially: a dropped term would be about S / n
+            assert (bounds[1] <= 0.05 * S / n).all()
+            sub = bounds[2] - ((2 * U16 + U16 ** 2) * S + np.sqrt(2) * (n + 6) * U32 * (1 + 3 * U16) * S)
+            assert (bounds[2] <= 0.75 * S / n + sub).all()
     finally:
         H.close()
 

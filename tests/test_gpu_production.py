@@ -1,0 +1,296 @@
+"""GPU parity at the shapes the benchmarks run, against the FP64 oracle.
+
+* The chiral SVD on 4^4 blocks (N_r = 1536 rows per chirality) with m' = 48 and
+  64 test vectors truncated to k = 24 and 32 (paper, Sec. 3, Eq. (5)): singular
+  values, projectors (Wedin bound), every column of P (phase convention),
+  restriction / prolongation and the Galerkin links of D_c = P^dag D P
+  (Sec. 2, Eq. (4)) element by element with a tolerance derived from the
+  columns' measured difference, and again after Procrustes alignment of the
+  bases, which does not depend on the basis inside the kept subspace.
+* The fine operator of the hierarchy, the kernel the setup smoother and the
+  K-cycle run, at its benchmark launch: 16^3x32 in 4^4 blocks (512 workgroups)
+  with 48 right-hand sides in FP32 and FP16 storage, through the device entry
+  point, on sampled sites against the oracle's operator.
+* The level-2 shapes of the three-level volume workload: the second coarsening
+  step on 2^4 coarse blocks of a 2k = 48 level with m' = 48 -> k = 32 (N_r = 384
+  rows), its 2k = 64 Galerkin operator on the matrix cores in FP32 and FP16
+  storage with multi-tile right-hand-side counts, and the FP32 setup whose
+  level-1 smoother applies the 2k = 48 coarse operator to 48 vectors at once.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lattice as olat, mg as omg
+from oracle.stencil import StencilOp, as_columns, as_fields
+from oracle.wilson import WilsonOp
+from parity_bounds import (U16, U32, SUB16, coarse_apply_bounds, compare_coarse_links, compare_prolongators,
+                           wilson_norm_bound)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def crk():
+    import paper_2502_03091_amd as m
+    m.lib()
+    return m
+
+
+def _restrict_prolong(crk, H, Po, dims, block, dcol, config):
+    """Transfers against the oracle's with the columns' measured difference:
+    (P^dag v)_i = p_i^dag v_block moves by at most ||dp_i|| ||v_block||, and
+    (P c)(x) by at most sum_i |dp_i(x)| |c_i| <= ||dp|| ||c_block||_1."""
+    from oracle import chiral
+    V = olat.volume(dims)
+    v = synth.gaussian_rhs(2, V, config=config)
+    rc_g = H.restrict(0, v)
+    rc_o = as_fields(chiral.restrict(Po, as_columns(v), dims, block))
+    vb = np.sqrt((np.abs(v) ** 2).sum(axis=2)).max() * np.sqrt(olat.volume(block))
+    assert np.abs(rc_g - rc_o).max() <= dcol * vb + 1e-12 * np.abs(rc_o).max()
+    pv_g = H.prolong(0, rc_o)
+    pv_o = as_fields(chiral.prolong(Po, as_columns(rc_o), dims, block))
+    c1 = np.abs(rc_o).sum(axis=2).max()
+    assert np.abs(pv_g - pv_o).max() <= dcol * c1 + 1e-12 * np.abs(pv_o).max()
+
+
+@pytest.mark.parametrize("m,k", [(48, 24), (64, 24), (64, 32)])
+def test_setup_fp64_production_blocks(crk, m, k):
+    """8^3x16, 4^4 blocks (32 coarse sites on a 2x2x2x4 coarse lattice), FP64 setup."""
+    dims, block, ns, m0 = [8, 8, 8, 16], [4, 4, 4, 4], 4, -0.4
+    print(f"production-shape setup parity m'={m} k={k}", flush=True)
+    U = synth.gauge_field(dims, 0.3, 1, config=81)
+    V = olat.volume(dims)
+    v0 = synth.gaussian_vectors(m, V, 12, config=81, level=0)
+    lat = crk.Lattice(dims, m0, 1.0)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[m], k=[k], block=[block], n_smooth=[ns], setup_form=crk.FORM_FP64,
+                      init_vectors=[v0])
+    try:
+        op = WilsonOp(U, dims, m0, 1.0)
+        ref = omg.mg_setup(op, [m], [k], [block], [ns], [as_columns(v0)], keep_vectors=True)
+        vg, vo = H.vectors(0), as_fields(ref[0].vectors)
+        assert (np.abs(vg - vo).max(axis=(1, 2)) / np.abs(vo).max(axis=(1, 2))).max() <= 1e-12
+        Pg, Po = H.prolongator(0), ref[0].Pb
+        dcol = compare_prolongators(Pg, Po, H.sigma(0), ref[0].sigma, k)
+        print("largest column difference", dcol, flush=True)
+        L1 = ref[1].op
+        rel = compare_coarse_links(H.coarse_links(0), (L1.X, L1.Yp, L1.Ym), dcol, wilson_norm_bound(m0, 1.0),
+                                   L1.dims, Pg, Po)
+        print("coarse links, largest relative difference", rel, flush=True)
+        _restrict_prolong(crk, H, Po, dims, block, dcol, config=82)
+    finally:
+        H.close()
+        lat.close()
+
+
+# ------------------------------------------------------------------ fine operator at its benchmark launch
+
+def _native_index(pos, V):
+    """Complex-element offsets (within one RHS) of every (site, component) in the
+    site-vectorised device layout, sites placed at their device positions."""
+    Vp = (V + 63) // 64 * 64
+    base = (pos // 64) * 768 + pos % 64
+    return base[:, None] + 64 * np.arange(12)[None, :], Vp
+
+
+def _pack(psi, pos, form):
+    """Host fields [nrhs, V, 12] -> bytes of the level-0 device layout (FP32: float2;
+    FP16S: half2 of x/scale, then one float scale per (RHS, device position), the
+    scale being the largest |Re|, |Im| of the site's twelve components)."""
+    nrhs, V, _ = psi.shape
+    idx, Vp = _native_index(pos, V)
+    if form == 1:
+        flat = np.zeros((nrhs, Vp * 12), dtype=np.complex64)
+        flat[:, idx] = psi
+        return flat.view(np.uint8).reshape(-1), psi.astype(np.complex64).astype(np.complex128)
+    scale = np.maximum(np.abs(psi.real), np.abs(psi.imag)).max(axis=2).astype(np.float32)  # [nrhs, V]
+    q = psi / scale[:, :, None]
+    h = np.zeros((nrhs, Vp * 12, 2), dtype=np.float16)
+    h[:, idx, 0] = q.real.astype(np.float16)
+    h[:, idx, 1] = q.imag.astype(np.float16)
+    sc = np.zeros((nrhs, Vp), dtype=np.float32)
+    sc[:, pos] = scale
+    stored = (h[:, idx, 0].astype(np.float64) + 1j * h[:, idx, 1].astype(np.float64)) * scale[:, :, None]
+    return np.concatenate([h.view(np.uint8).reshape(-1), sc.view(np.uint8).reshape(-1)]), stored
+
+
+def _unpack(raw, pos, form, nrhs, V):
+    idx, Vp = _native_index(pos, V)
+    if form == 1:
+        flat = raw.view(np.complex64).reshape(nrhs, Vp * 12)
+        return flat[:, idx].astype(np.complex128), None
+    nd = nrhs * Vp * 12 * 4
+    h = raw[:nd].view(np.float16).reshape(nrhs, Vp * 12, 2)
+    sc = raw[nd:].view(np.float32).reshape(nrhs, Vp)[:, pos]
+    vals = (h[:, idx, 0].astype(np.float64) + 1j * h[:, idx, 1].astype(np.float64)) * sc[:, :, None]
+    return vals, sc
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_fine_operator_benchmark_launch(crk, form):
+    """16^3x32, xi = 3.5, 4^4 blocks, 48 RHS through crk_mg_apply_dev at level 0.
+
+    Bounds: each output component sums n = 9 terms of 12-component products in
+    FP32, |err| <= sqrt(2) (n_eff + 4) u32 S with n_eff = 8 * 6 + 1 terms per
+    component (six link-times-half-spinor products per hop) and S <= the
+    largest |(D psi)| bound ||D||_2-free: the sum of absolute values, taken
+    here as (|m0 + sum w| + 2 sum w) max|psi| * 6.  The oracle applies D with
+    the links as the form stores them (FP32, or binary16 for FP16S) to the
+    input as the form stores it (for FP16S quantised on the host exactly as the
+    kernel stores it); the FP16S output rounding adds at most (u16 + 2^-25) of
+    the site's stored scale per component."""
+    import torch
+    dims, nrhs, m0, xi = [16, 16, 16, 32], 48, -0.05, 3.5
+    V = olat.volume(dims)
+    print(f"fine operator, benchmark launch, form={form}", flush=True)
+    U = synth.gauge_field(dims, 0.2, 3, config=2)
+    lat = crk.Lattice(dims, m0, xi)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[8], k=[8], block=[[4, 4, 4, 4]], n_smooth=[0], setup_form=crk.FORM_FP32)
+    try:
+        pos = H.get(0, crk.GET_DEVICE_ORDER).astype(np.int64)
+        assert np.array_equal(np.sort(pos), np.arange(V))
+        psi = synth.gaussian_vectors(nrhs, V, 12, config=2, level=3)
+        raw, stored = _pack(psi, pos, form)
+        nb = H.field_bytes(0, form, nrhs)
+        assert nb == raw.size, (nb, raw.size)
+        dev = torch.device("cuda", 0)
+        a = torch.from_numpy(raw).to(dev)
+        b = torch.zeros_like(a)
+        H.apply_dev(0, a, b, nrhs, form)
+        torch.cuda.synchronize()
+        got, out_scale = _unpack(b.cpu().numpy(), pos, form, nrhs, V)
+        if form == 2:
+            # the FP16S form keeps the links as binary16 (rounded via FP32, as the device converts them)
+            Uh = (U.real.astype(np.float32).astype(np.float16).astype(np.float64)
+                  + 1j * U.imag.astype(np.float32).astype(np.float16).astype(np.float64))
+        else:
+            Uh = U.astype(np.complex64).astype(np.complex128)
+        op = WilsonOp(Uh, dims, m0, xi)
+        rng = np.random.default_rng(17)
+        # sampled sites, plus the corners of a block (every face and edge case of the LDS tile)
+        sites = np.unique(np.concatenate([rng.choice(V, 384, replace=False), np.arange(4), [3 + 16 * 3 + 256 * 3],
+                                          [V - 1]]))
+        ref = op.apply_at(as_columns(stored), sites)  # [sites, 12, nrhs]
+        g = got[:, sites].transpose(1, 2, 0)
+        err = np.abs(g - ref)
+        S = (abs(m0 + 3 + 1 / xi) + 2 * (3 + 1 / xi)) * np.abs(stored).max() * 6
+        b32 = np.sqrt(2) * (8 * 6 + 1 + 4) * U32 * S
+        if form == 1:
+            assert err.max() <= b32, (err.max(), b32)
+        else:
+            site_scale = out_scale[:, sites].T[:, None, :]  # [sites, 1, nrhs]
+            bound = (U16 + SUB16) * site_scale * (1 + U16) + b32
+            assert (err <= bound).all(), (err / bound).max()
+        print("largest error", err.max(), "relative", err.max() / np.abs(ref).max(), flush=True)
+    finally:
+        H.close()
+        lat.close()
+
+
+# ------------------------------------------------------------------ three-level shapes
+
+def _three_level(crk, form):
+    dims, m0 = [8, 8, 8, 16], -0.4
+    blocks = [[4, 4, 4, 4], [2, 2, 2, 2]]
+    U = synth.gauge_field(dims, 0.3, 1, config=71)
+    V = olat.volume(dims)
+    iv0 = synth.gaussian_vectors(64, V, 12, config=71, level=0)
+    iv1 = synth.gaussian_vectors(48, V // 256, 48, config=71, level=1)
+    lat = crk.Lattice(dims, m0, 1.0)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[64, 48], k=[24, 32], block=blocks, n_smooth=[3, 3], setup_form=form,
+                      init_vectors=[iv0, iv1])
+    op = WilsonOp(U, dims, m0, 1.0)
+    ref = omg.mg_setup(op, [64, 48], [24, 32], blocks, [3, 3], [as_columns(iv0), as_columns(iv1)],
+                       keep_vectors=True)
+    return lat, H, ref, m0
+
+
+def test_three_level_fp64_level2_shapes(crk):
+    """Level 2 of the volume workload: m' = 48 -> k = 32 on 2^4 blocks of the
+    2k = 48 coarse lattice (N_r = 16 * 24 = 384), 2k = 64 coarsest operator."""
+    print("three-level FP64 parity, level-2 shapes", flush=True)
+    lat, H, ref, m0 = _three_level(crk, crk.FORM_FP64)
+    try:
+        assert H.prolongator(1).shape == (2, 2, 384, 32)
+        normD = wilson_norm_bound(m0, 1.0)
+        d0 = compare_prolongators(H.prolongator(0), ref[0].Pb, H.sigma(0), ref[0].sigma, 24)
+        L1 = ref[1].op
+        compare_coarse_links(H.coarse_links(0), (L1.X, L1.Yp, L1.Ym), d0, normD, L1.dims,
+                             H.prolongator(0), ref[0].Pb)
+        # level-1 smoothed vectors start from the same inputs on the GPU's and the
+        # oracle's coarse operators, which differ by the links' difference above
+        v1, vo = H.vectors(1), as_fields(ref[1].vectors)
+        e1 = (np.abs(v1 - vo).max(axis=(1, 2)) / np.abs(vo).max(axis=(1, 2))).max()
+        assert e1 <= 1e-11, e1
+        # level 2: the oracle's SVD of the GPU's own level-1 vectors isolates the
+        # SVD and Galerkin steps from the level-1 operator's rounding
+        from oracle import chiral, galerkin
+        A = chiral.chiral_blocks(as_columns(v1), L1.dims, [2, 2, 2, 2])
+        Pb2, S2 = chiral.prolongator_blocks(A, 32)
+        d1 = compare_prolongators(H.prolongator(1), Pb2, H.sigma(1), S2, 32)
+        gpu_l1 = StencilOp(L1.dims, *H.coarse_links(0))
+        D2 = galerkin.galerkin(gpu_l1, Pb2, [2, 2, 2, 2])
+        compare_coarse_links(H.coarse_links(1), (D2.X, D2.Yp, D2.Ym), d1, normD, D2.dims, H.prolongator(1), Pb2)
+        # and the whole chain against the oracle's own level 2 (basis independent: spectrum)
+        D2o = ref[2].op.dense()
+        D2g = StencilOp(D2.dims, *H.coarse_links(1)).dense()
+        eo, eg = np.sort_complex(np.linalg.eigvals(D2o)), np.sort_complex(np.linalg.eigvals(D2g))
+        from scipy.optimize import linear_sum_assignment
+        cost = np.abs(eo[:, None] - eg[None, :])
+        r, c = linear_sum_assignment(cost)
+        assert cost[r, c].max() <= 1e-9 * np.abs(D2o).max(), cost[r, c].max()
+    finally:
+        H.close()
+        lat.close()
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_coarse_operator_multitile_forms(crk, level):
+    """2k = 48 (level 1) and 2k = 64 (level 2) coarse operators on the matrix
+    cores, 20 and 48 right-hand sides (two and three 16-column tiles, the last
+    one partly empty), FP64 / FP32 / FP16S against the oracle's stencil built
+    from the same links, within the bounds of coarse_apply_bounds."""
+    lat, H, ref, m0 = _three_level(crk, crk.FORM_FP64)
+    try:
+        X, Yp, Ym = H.coarse_links(level - 1)
+        cd = H.dims[level]
+        op = StencilOp(cd, X, Yp, Ym)
+        Vc, N = X.shape[0], X.shape[-1]
+        assert N == (48 if level == 1 else 64)
+        for nrhs in (20, 48):
+            v = synth.gaussian_vectors(nrhs, Vc, N, config=90 + nrhs, level=level)
+            ref_out = as_fields(op.apply(as_columns(v)))
+            bounds, S, n = coarse_apply_bounds(X, Yp, Ym, cd, v)
+            for form in (0, 1, 2):
+                out = H.coarse_apply(level, v, form=form)
+                worst = (np.abs(out - ref_out) / bounds[form]).max()
+                print(f"level {level} 2k={N} nrhs={nrhs} form={form} worst/bound={worst:.3f}", flush=True)
+                assert worst <= 1.0, (level, nrhs, form, worst)
+            # not trivially: a dropped term is about S / n
+            assert (bounds[1] <= 0.05 * S / n).all()
+    finally:
+        H.close()
+        lat.close()
+
+
+def test_three_level_fp32_setup_multitile_smoother(crk):
+    """FP32 setup: the level-1 smoother applies the 2k = 48 coarse operator in FP32
+    to 48 vectors at once (three MFMA tiles).  Its vectors follow the FP64 oracle's
+    within the FP32 smoother's stated bound (1e-4 relative, as for the fine
+    FP32 smoother), and the level-2 singular values within 1e-4 sigma_1."""
+    print("three-level FP32 setup", flush=True)
+    lat, H, ref, m0 = _three_level(crk, crk.FORM_FP32)
+    try:
+        for l in (0, 1):
+            vg, vo = H.vectors(l), as_fields(ref[l].vectors)
+            e = (np.abs(vg - vo).max(axis=(1, 2)) / np.abs(vo).max(axis=(1, 2))).max()
+            print(f"FP32 setup level {l} vector error {e:.2e}", flush=True)
+            assert e <= 1e-4, (l, e)
+            so = ref[l].sigma
+            assert np.abs(H.sigma(l) - so).max() <= 1e-4 * so[..., 0].max()
+    finally:
+        H.close()
+        lat.close()
