@@ -5,7 +5,7 @@
  *   T. Whyte, A. Stathopoulos, E. Romero, "Chiral rank-k truncations for the
  *   multigrid preconditioner of Wilson fermions in lattice QCD" (LATTICE2024),
  * for the Wilson-Dirac operator D on a periodic 4-D lattice:
- *   setup (Sec. 2 Eq. (1); Sec. 3 Eqs. (2), (5), (6); Sec. 2 Eq. (4)):
+ *   setup (Sec. 2, Eqs. (1), (2) and (4); Sec. 3, Eqs. (5) and (6)):
  *     MR smoother on D psi_i ~ 0 for m' random vectors -> chiral split per block
  *     -> per-(block, chirality) SVD truncated to k left singular vectors = P
  *     (R = P^dag, gamma5 P = P sigma3) -> Galerkin coarse stencil D_c = R D P;
@@ -74,18 +74,28 @@ int crk_device_info(char* name, int32_t n, int64_t* hbm_bytes, int32_t* n_cu);
 
 /* ------------------------------------------------------------------ lattice */
 
-/* Create a lattice of extent dims[4] (each >= 2) with Wilson mass m0 and
- * temporal anisotropy xi > 0.  Allocates the device gauge storage (all
- * forms) and the lexicographic neighbour table. */
+/* Create the lattice on which the Wilson-Dirac operator D of Sec. 2 (the
+ * operator of D x = b in Sec. 1) acts: extent dims[4] (each >= 2), periodic,
+ * Wilson mass m0 and temporal anisotropy xi > 0 (the temporal hop weighted by
+ * 1/xi).  Allocates the device gauge storage (all forms) and the
+ * lexicographic neighbour table.  *out receives a library-owned handle
+ * (free with crk_lattice_destroy).  CRK_EINVAL for an extent < 2 or xi <= 0,
+ * CRK_ENOMEM if the device storage does not fit. */
 int crk_create_lattice(const int32_t dims[4], double m0, double xi, crk_lattice_t* out);
 
-/* Upload the gauge field (host complex128 [V][4][3][3], n_doubles = 2*V*36).
- * Converted on the device to every precision form. */
+/* Upload the SU(3) gauge links U_mu(x) that define D (Sec. 2): host
+ * complex128 [V][4][3][3] (entry [x][mu][a][b] = U_mu(x)[a][b]),
+ * n_doubles = 2*V*36.  Copied before the call returns and converted on the
+ * device to every precision form.  CRK_EINVAL if n_doubles does not match
+ * the lattice or U is NULL. */
 int crk_load_gauge(crk_lattice_t lat, const double* U, int64_t n_doubles);
 
-/* Apply D to nrhs host-layout fields (complex128 [nrhs][V][12]) in the given
- * form; in and out are host pointers and may not alias.  FP32/FP16S round the
- * input to the form, apply, and widen the result. */
+/* Apply the Wilson-Dirac operator D of Sec. 2 (formula above) to nrhs
+ * host-layout fields (complex128 [nrhs][V][12]) in the given form; in and
+ * out are caller-owned host pointers and may not alias.  FP32/FP16S round
+ * the input to the form, apply, and widen the result.  nrhs = 0 is a no-op.
+ * CRK_ESTATE before crk_load_gauge, CRK_EINVAL for a bad form, nrhs < 0 or
+ * NULL pointers. */
 int crk_dirac_apply(crk_lattice_t lat, int32_t form, const double* in, double* out, int32_t nrhs);
 
 /* Device-resident variant on the lattice's native device layout of the form
@@ -171,7 +181,12 @@ typedef struct {
 
 void crk_solve_info_default(crk_solve_info* info);
 
-/* Solve D x = b for nrhs host-layout right-hand sides (complex128 [nrhs][V][12]). */
+/* Solve D x = b (Sec. 1) for nrhs host-layout right-hand sides (complex128
+ * [nrhs][V][12], caller-owned, copied in and out) with flexible GCR
+ * preconditioned by the K-cycle of the hierarchy (Sec. 2, last paragraph),
+ * to the relative TRUE residual info->tol in FP64.  Blocks until done.
+ * CRK_ENOCONV when max_iter is reached (x and info hold the best iterate),
+ * CRK_EINVAL for nrhs outside [1, 64], tol <= 0 or NULL pointers. */
 int crk_mg_solve(crk_mg_t mg, const double* b, double* x, int32_t nrhs, crk_solve_info* info);
 
 /* Same with device buffers in host layout (complex128 [nrhs][V][12]), stream ordered;
@@ -182,6 +197,12 @@ int crk_mg_solve_dev(crk_mg_t mg, const void* b_dev, void* x_dev, int32_t nrhs, 
 
 /* Per-RHS outer iteration counts and true residuals of the last solve. */
 int crk_mg_last_solve_rhs(crk_mg_t mg, int32_t* iters, double* true_rel_resid, int32_t nrhs);
+
+/* Per-RHS time to solution of the last solve (Sec. 2, last paragraph: the
+ * outer flexible GCR): host wall seconds from the start of the solve to the
+ * outer iteration at which that right-hand side's true residual was verified
+ * (or it stopped).  nrhs must equal the last solve's; CRK_EINVAL otherwise. */
+int crk_mg_last_solve_rhs_seconds(crk_mg_t mg, double* seconds, int32_t nrhs);
 
 /* ------------------------------------------------------------------ inspection */
 
@@ -196,7 +217,11 @@ enum crk_mg_what {
   CRK_GET_DEVICE_ORDER = 7 /* int32 [V_l]  device position of every site */
 };
 /* Copy a hierarchy quantity of step l (0 = fine -> first coarse) to host memory
- * of exactly n_bytes. */
+ * of exactly n_bytes (caller-owned): the prolongator blocks U_k of Sec. 3,
+ * Eqs. (5)-(6), their singular values, the Galerkin links of D_{l+1} = R D_l P
+ * (Sec. 2, Eq. (4)), the smoothed test vectors of Eq. (1), and the block maps
+ * of the domains Lambda_j (Sec. 2).  CRK_EINVAL for an unknown quantity, a
+ * level out of range or n_bytes != crk_mg_get_bytes. */
 int crk_mg_get(crk_mg_t mg, int32_t level, int32_t what, void* out, int64_t n_bytes);
 
 /* Bytes a quantity of crk_mg_get needs. */

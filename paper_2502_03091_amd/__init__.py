@@ -158,6 +158,7 @@ def _load():
         "crk_mg_solve": (i32, [vp, vp, vp, i32, C.POINTER(SolveInfo)]),
         "crk_mg_solve_dev": (i32, [vp, vp, vp, i32, vp, C.POINTER(SolveInfo)]),
         "crk_mg_last_solve_rhs": (i32, [vp, C.POINTER(i32), C.POINTER(dbl), i32]),
+        "crk_mg_last_solve_rhs_seconds": (i32, [vp, C.POINTER(dbl), i32]),
         "crk_mg_get": (i32, [vp, i32, i32, vp, i64]),
         "crk_mg_get_bytes": (i64, [vp, i32, i32]),
         "crk_mg_get_timing": (i32, [vp, i32, C.POINTER(dbl)]),
@@ -193,10 +194,11 @@ def exported_symbols():
     """Names the binding expects the shared library to export."""
     return [
         "crk_version", "crk_last_error", "crk_device_info", "crk_create_lattice", "crk_load_gauge",
-        "crk_dirac_apply", "crk_dirac_apply_dev", "crk_field_bytes", "crk_field_import_dev",
+        "crk_dirac_apply", "crk_dirac_apply_dev",
+        "crk_field_bytes", "crk_field_import_dev",
         "crk_field_export_dev", "crk_lattice_get_map", "crk_lattice_destroy", "crk_mg_params_default",
         "crk_mg_setup", "crk_solve_info_default", "crk_mg_solve", "crk_mg_solve_dev",
-        "crk_mg_last_solve_rhs", "crk_mg_get", "crk_mg_get_bytes", "crk_mg_get_timing",
+        "crk_mg_last_solve_rhs", "crk_mg_last_solve_rhs_seconds", "crk_mg_get", "crk_mg_get_bytes", "crk_mg_get_timing",
         "crk_mg_coarse_apply", "crk_mg_apply_dev", "crk_mg_field_bytes", "crk_mg_restrict", "crk_mg_prolong",
         "crk_mg_footprint_bytes", "crk_mg_destroy",
     ]
@@ -472,13 +474,16 @@ class Hierarchy:
             _check(rc)
         d = info.as_dict()
         d["converged"] = rc == OK
+        d["rhs"] = self.last_solve_rhs(int(nrhs))
         return d
 
     def last_solve_rhs(self, nrhs):
         it = (C.c_int32 * nrhs)()
         rr = (C.c_double * nrhs)()
+        ts = (C.c_double * nrhs)()
         _check(_load().crk_mg_last_solve_rhs(self.handle, it, rr, nrhs))
-        return {"iters": list(it), "true_rel_resid": list(rr)}
+        _check(_load().crk_mg_last_solve_rhs_seconds(self.handle, ts, nrhs))
+        return {"iters": list(it), "true_rel_resid": list(rr), "seconds": list(ts)}
 
     def footprint_bytes(self, nrhs, form=FORM_FP32):
         return int(_load().crk_mg_footprint_bytes(self.handle, int(nrhs), int(form)))

@@ -38,6 +38,15 @@ struct crk_mg_s { crk::Hierarchy* H; };
 
 using namespace crk;
 
+namespace crk {
+
+size_t lattice_dirac_stage_bytes(const Lattice* L, int form, int64_t nrhs) {
+  auto up = [](size_t n) { return (n + 255) & ~size_t(255); };
+  return up(sizeof(double2) * 12 * size_t(L->V) * size_t(nrhs)) + 2 * up(fine_field_bytes(form, L->V, nrhs));
+}
+
+}  // namespace crk
+
 extern "C" {
 
 int crk_version(void) { return 1 * 10000 + 0 * 100 + 0; }
@@ -97,23 +106,37 @@ static void dirac_native(Lattice* L, int form, const void* in, void* out, int nr
   wilson_apply(a, st);
 }
 
+}  // extern "C"
+
+namespace crk {
+
+void lattice_dirac_apply_staged(Lattice* L, int form, const double* in, double* out, int nrhs, void* h, void* a,
+                                void* b) {
+  const size_t hb = sizeof(double2) * 12 * size_t(L->V) * nrhs;
+  CRK_HIP(hipMemcpyAsync(h, in, hb, hipMemcpyHostToDevice, L->stream));
+  field_import(form, static_cast<const double2*>(h), a, nullptr, L->V, 12, nrhs, L->stream);
+  dirac_native(L, form, a, b, nrhs, L->stream);
+  field_export(form, b, static_cast<double2*>(h), nullptr, L->V, 12, nrhs, L->stream);
+  CRK_HIP(hipMemcpyAsync(out, h, hb, hipMemcpyDeviceToHost, L->stream));
+  CRK_HIP(hipStreamSynchronize(L->stream));
+}
+
+}  // namespace crk
+
+extern "C" {
+
 int crk_dirac_apply(crk_lattice_t lat, int32_t form, const double* in, double* out, int32_t nrhs) {
   return guarded([&] {
     CRK_REQUIRE(lat && lat->L, "lattice handle is NULL");
     Lattice* L = lat->L;
     check_form(form);
-    CRK_REQUIRE(L->gauge_loaded, "gauge field not loaded");
+    CRK_REQUIRE_STATE(L->gauge_loaded, "gauge field not loaded");
     CRK_REQUIRE(nrhs >= 0, "nrhs must be >= 0");
     CRK_REQUIRE(nrhs == 0 || (in && out), "NULL field pointer");
     if (nrhs == 0) return CRK_OK;
     const size_t hb = sizeof(double2) * 12 * size_t(L->V) * nrhs;
     DevBuf h(hb), a(fine_field_bytes(form, L->V, nrhs)), b(fine_field_bytes(form, L->V, nrhs));
-    CRK_HIP(hipMemcpyAsync(h.p, in, hb, hipMemcpyHostToDevice, L->stream));
-    field_import(form, h.as<double2>(), a.p, nullptr, L->V, 12, nrhs, L->stream);
-    dirac_native(L, form, a.p, b.p, nrhs, L->stream);
-    field_export(form, b.p, h.as<double2>(), nullptr, L->V, 12, nrhs, L->stream);
-    CRK_HIP(hipMemcpyAsync(out, h.p, hb, hipMemcpyDeviceToHost, L->stream));
-    CRK_HIP(hipStreamSynchronize(L->stream));
+    lattice_dirac_apply_staged(L, form, in, out, nrhs, h.p, a.p, b.p);
     return CRK_OK;
   });
 }
@@ -122,7 +145,7 @@ int crk_dirac_apply_dev(crk_lattice_t lat, int32_t form, const void* in, void* o
   return guarded([&] {
     CRK_REQUIRE(lat && lat->L, "lattice handle is NULL");
     check_form(form);
-    CRK_REQUIRE(lat->L->gauge_loaded, "gauge field not loaded");
+    CRK_REQUIRE_STATE(lat->L->gauge_loaded, "gauge field not loaded");
     CRK_REQUIRE(nrhs >= 0, "nrhs must be >= 0");
     if (nrhs == 0) return CRK_OK;
     CRK_REQUIRE(in && out, "NULL field pointer");

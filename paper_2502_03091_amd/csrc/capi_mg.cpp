@@ -141,6 +141,17 @@ int crk_mg_last_solve_rhs(crk_mg_t mg, int32_t* iters, double* resid, int32_t nr
   });
 }
 
+int crk_mg_last_solve_rhs_seconds(crk_mg_t mg, double* seconds, int32_t nrhs) {
+  crk_clear_error_();
+  return guarded_mg([&] {
+    Hierarchy* H = hier(mg);
+    CRK_REQUIRE(seconds != nullptr, "seconds is NULL");
+    CRK_REQUIRE(size_t(nrhs) == H->last_seconds.size(), "nrhs does not match the last solve");
+    for (int r = 0; r < nrhs; ++r) seconds[r] = H->last_seconds[r];
+    return CRK_OK;
+  });
+}
+
 int64_t crk_mg_get_bytes(crk_mg_t mg, int32_t level, int32_t what) {
   if (!mg || !mg->H) return -1;
   Hierarchy* H = mg->H;

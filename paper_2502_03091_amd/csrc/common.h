@@ -44,6 +44,12 @@ struct Error : std::runtime_error {
     if (!(cond)) ::crk::fail(CRK_EINVAL, std::string(msg));     \
   } while (0)
 
+// A call made out of order (e.g. an operator before the gauge field is loaded).
+#define CRK_REQUIRE_STATE(cond, msg)                            \
+  do {                                                          \
+    if (!(cond)) ::crk::fail(CRK_ESTATE, std::string(msg));     \
+  } while (0)
+
 #define CRK_LAUNCH_CHECK() CRK_HIP(hipGetLastError())
 
 // ------------------------------------------------------------------ device buffer

@@ -18,6 +18,7 @@ Lattice* lattice_create(const int32_t dims[4], double m0, double xi) {
     L->xi = xi;
     L->w[0] = L->w[1] = L->w[2] = 1.0;
     L->w[3] = 1.0 / xi;
+    CRK_HIP(hipGetDevice(&L->device));
     CRK_HIP(hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking));
     L->geo.build(L->dims, nullptr, L->stream);
     L->U64.alloc(sizeof(double2) * 36 * V);

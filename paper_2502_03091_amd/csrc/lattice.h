@@ -40,6 +40,7 @@ struct Lattice {
   DevBuf gauge[3];           // per form, [mu][9][V] lexicographic
   bool gauge_loaded = false;
   hipStream_t stream = nullptr;
+  int device = 0;            // HIP device current when the lattice was created
   std::atomic<int> refs{1};
 
   double diag() const { return m0 + w[0] + w[1] + w[2] + w[3]; }
@@ -49,5 +50,14 @@ struct Lattice {
 Lattice* lattice_create(const int32_t dims[4], double m0, double xi);
 void lattice_load_gauge(Lattice* L, const double* U_host);
 void lattice_release(Lattice* L);
+
+// D applied to nrhs host-layout fields (complex128 [nrhs][V][12], host memory)
+// through device staging the caller provides: h holds the complex128 host
+// layout, a and b the form's native layout (fine_field_bytes each).  Runs on
+// the lattice's stream and waits for it.
+void lattice_dirac_apply_staged(Lattice* L, int form, const double* in, double* out, int nrhs, void* h, void* a,
+                                void* b);
+// Bytes of the three staging buffers above, each rounded up to 256 bytes.
+size_t lattice_dirac_stage_bytes(const Lattice* L, int form, int64_t nrhs);
 
 }  // namespace crk

@@ -64,6 +64,7 @@ struct Hierarchy {
   std::unique_ptr<Workspace> ws;
   std::vector<int> last_iters;
   std::vector<double> last_resid;
+  std::vector<double> last_seconds;  // per RHS: admission to convergence (host wall time)
   std::atomic<int> refs{1};          // handle + every server that holds the hierarchy
 
   Hierarchy();

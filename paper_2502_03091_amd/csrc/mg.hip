@@ -355,7 +355,7 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
 }  // namespace
 
 Hierarchy* mg_setup(Lattice* L, const crk_mg_params& p) {
-  CRK_REQUIRE(L->gauge_loaded, "gauge field not loaded");
+  CRK_REQUIRE_STATE(L->gauge_loaded, "gauge field not loaded");
   validate(L, p);
   auto H = std::make_unique<Hierarchy>();
   H->lat = L;

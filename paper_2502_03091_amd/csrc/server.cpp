@@ -83,6 +83,7 @@ void Server::open_lanes_locked() {
       Lane* ln = new Lane();
       ln->srv = this;
       ln->lattice = int(&ep - &lat_[0]);
+      ln->entry = &e;
       ln->id = e.next_lane_id++;
       ln->bytes = e.lane_bytes;
       ln->free_slots = p_.slots_per_lane;  // reserved until the lane is ready
@@ -193,7 +194,9 @@ Server::~Server() {
 // ------------------------------------------------------------------ lane thread
 
 void lane_main(Server* s, Lane* lane) {
-  LatticeEntry& L = *s->lat_[lane->lattice];
+  // The entry pointer was stored under the lock when the lane opened: lat_
+  // itself may grow (and reallocate) while this thread runs.
+  LatticeEntry& L = *lane->entry;
   Hierarchy* H = L.H;
   const int cap = s->p_.slots_per_lane;
   const int64_t per = 12 * H->V(0);  // complex entries per RHS

@@ -49,8 +49,11 @@ class Server;
 struct Lane;
 void lane_main(Server* s, Lane* lane);
 
+struct LatticeEntry;
+
 struct Lane {
   Server* srv = nullptr;
+  LatticeEntry* entry = nullptr;  // set under the server lock when the lane opens; the entry never moves
   int lattice = 0, id = 0;
   bool ready = false, dead = false, exited = false;
   int free_slots = 0;      // mirrored under the server lock

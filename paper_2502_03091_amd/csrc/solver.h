@@ -106,6 +106,9 @@ class OuterSolver {
   // occupied slot.  Converged slots already carry the value of their final check.
   void refresh_residuals();
   double true_rel(int s) const { return tres_[s]; }
+  // Host wall time from a slot's admission to the outer iteration at which it
+  // converged or stopped (the step that decided it has synchronised the stream).
+  double seconds(int s) const { return t_done_[s] - t_admit_[s]; }
   // Copy x of slots s0 .. s0+n-1 into x_dev (complex128 host layout [n][V][12]), stream ordered.
   void export_x(int s0, int n, void* x_dev);
   // Iteration counts of slots s0 .. s0+n-1: out[0] outer, out[l] summed inner iterations on level l.
@@ -120,7 +123,7 @@ class OuterSolver {
   int cap_, nslots_;
   int ring_ = 0, used_ = 0;  // ring position of the next direction; stored directions
   std::vector<int> state_, iters_, nbasis_;
-  std::vector<double> bn_, tres_;
+  std::vector<double> bn_, tres_, t_admit_, t_done_;
   DevBuf nbd_;  // per-slot window lengths for materialize
   void upload_active();
   int width() const;

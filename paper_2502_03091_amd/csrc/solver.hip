@@ -12,6 +12,8 @@
 // All right-hand sides advance together; per-RHS scalars, active flags and a
 // ring of stored directions with per-RHS valid windows reproduce, RHS by RHS,
 // the single-RHS recursion.
+#include <chrono>
+
 #include "solver.h"
 
 #include <algorithm>
@@ -268,8 +270,16 @@ OuterSolver::OuterSolver(Hierarchy* H, Workspace* w, const crk_solve_info& p, hi
   nbasis_.assign(cap_, 0);
   bn_.assign(cap_, 0.0);
   tres_.assign(cap_, 0.0);
+  t_admit_.assign(cap_, 0.0);
+  t_done_.assign(cap_, 0.0);
   nbd_.alloc(sizeof(int) * size_t(cap_));
 }
+
+namespace {
+double wall_now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
 
 int OuterSolver::free_slots() const { return int(std::count(state_.begin(), state_.end(), int(kSlotFree))); }
 
@@ -324,6 +334,8 @@ void OuterSolver::admit(int s0, int n, const void* b_dev) {
     nbasis_[q] = 0;
     tres_[q] = 0.0;
     state_[q] = bn_[q] > 0 ? kSlotRunning : kSlotConverged;  // b = 0: x = 0 is exact
+    t_admit_[q] = wall_now();
+    t_done_[q] = t_admit_[q];
   }
   upload_active();
 }
@@ -340,6 +352,8 @@ void OuterSolver::true_residual(int wd) {
 int OuterSolver::step() {
   const int wd = width();
   if (running() == 0) return 0;
+  std::vector<char> was_running(wd);
+  for (int r = 0; r < wd; ++r) was_running[r] = state_[r] == kSlotRunning;
   Workspace& w = *w_;
   OuterWork& o = w.ow;
   GcrScalars& s = o.s;
@@ -431,6 +445,9 @@ int OuterSolver::step() {
   }
   for (int r = 0; r < wd; ++r)
     if (state_[r] == kSlotRunning && iters_[r] >= p_.max_iter) state_[r] = kSlotStopped;
+  const double t = wall_now();
+  for (int r = 0; r < wd; ++r)
+    if (was_running[r] && state_[r] != kSlotRunning) t_done_[r] = t;
   upload_active();
   ring_ = (ring_ + 1) % nslots_;
   return running();
@@ -534,11 +551,13 @@ int mg_solve_dev(Hierarchy* H, const void* b_dev, void* x_dev, int nrhs, hipStre
   for (int l = 0; l < CRK_MAX_LEVELS; ++l) info->level_iters[l] = 0;
   H->last_iters.assign(nrhs, 0);
   H->last_resid.assign(nrhs, 0);
+  H->last_seconds.assign(nrhs, 0);
   bool all_conv = true;
   for (int r = 0; r < nrhs; ++r) {
     const double rr = os.true_rel(r);
     H->last_iters[r] = os.iters(r);
     H->last_resid[r] = rr;
+    H->last_seconds[r] = os.seconds(r);
     info->iters = std::max(info->iters, os.iters(r));
     info->true_rel_resid = std::max(info->true_rel_resid, rr);
     all_conv &= rr <= p.tol;
