@@ -98,6 +98,21 @@ int crk_load_gauge(crk_lattice_t lat, const double* U, int64_t n_doubles);
  * NULL pointers. */
 int crk_dirac_apply(crk_lattice_t lat, int32_t form, const double* in, double* out, int32_t nrhs);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation as crk_dirac_apply, staged through a fixed device array of
+ * crk_dirac_apply_noalloc_max_bytes() bytes (64 MiB) that the library holds
+ * on every GPU it runs on until the process ends, instead of three device
+ * buffers allocated per call.  It calls no hipMalloc, hipFree or allocating
+ * library routine.  The staging a call needs, 16*12*V*nrhs bytes plus twice
+ * crk_field_bytes(lat, form, nrhs) (each rounded up to 256), must fit in the
+ * array; larger calls return CRK_EINVAL and do nothing.  Results are bitwise
+ * those of crk_dirac_apply.  All calls on one GPU share its array: calls that
+ * overlap on one GPU (several host threads) race and must be serialised by
+ * the caller.  Other errors as crk_dirac_apply. */
+int crk_dirac_apply_noalloc(crk_lattice_t lat, int32_t form, const double* in, double* out, int32_t nrhs);
+int64_t crk_dirac_apply_noalloc_max_bytes(void);
+
 /* Device-resident variant on the lattice's native device layout of the form
  * (site-vectorised): with Vp = V rounded up to a multiple of 64, entry
  * (rhs r, component c, lexicographic site s) is complex element

@@ -147,6 +147,8 @@ def _load():
         "crk_load_gauge": (i32, [vp, vp, i64]),
         "crk_dirac_apply": (i32, [vp, i32, vp, vp, i32]),
         "crk_dirac_apply_dev": (i32, [vp, i32, vp, vp, i32, vp]),
+        "crk_dirac_apply_noalloc": (i32, [vp, i32, vp, vp, i32]),
+        "crk_dirac_apply_noalloc_max_bytes": (i64, []),
         "crk_field_bytes": (i64, [vp, i32, i32]),
         "crk_field_import_dev": (i32, [vp, i32, vp, vp, i32, vp]),
         "crk_field_export_dev": (i32, [vp, i32, vp, vp, i32, vp]),
@@ -194,7 +196,7 @@ def exported_symbols():
     """Names the binding expects the shared library to export."""
     return [
         "crk_version", "crk_last_error", "crk_device_info", "crk_create_lattice", "crk_load_gauge",
-        "crk_dirac_apply", "crk_dirac_apply_dev",
+        "crk_dirac_apply", "crk_dirac_apply_dev", "crk_dirac_apply_noalloc", "crk_dirac_apply_noalloc_max_bytes",
         "crk_field_bytes", "crk_field_import_dev",
         "crk_field_export_dev", "crk_lattice_get_map", "crk_lattice_destroy", "crk_mg_params_default",
         "crk_mg_setup", "crk_solve_info_default", "crk_mg_solve", "crk_mg_solve_dev",
@@ -280,6 +282,17 @@ class Lattice:
         assert psi.shape[1:] == (self.V, 12)
         out = np.empty_like(psi)
         _check(_load().crk_dirac_apply(self.handle, int(form), _cptr(psi), _cptr(out), psi.shape[0]))
+        return out
+
+    def dirac_apply_noalloc(self, psi, form=FORM_FP64):
+        """As dirac_apply, staged through the library's fixed device scratch array
+        (no device allocation; crk_dirac_apply_noalloc)."""
+        psi = _as_c128(psi)
+        if psi.ndim == 2:
+            psi = psi[None]
+        assert psi.shape[1:] == (self.V, 12)
+        out = np.empty_like(psi)
+        _check(_load().crk_dirac_apply_noalloc(self.handle, int(form), _cptr(psi), _cptr(out), psi.shape[0]))
         return out
 
     def field_bytes(self, form, nrhs):

@@ -31,6 +31,7 @@ SOURCES = [
     "capi.cpp",
     "capi_mg.cpp",
     "server.cpp",
+    "noalloc.hip",
 ]
 
 ARCH = os.environ.get("CRK_OFFLOAD_ARCH", "gfx950")
