@@ -60,7 +60,7 @@ void validate(const Lattice* L, const crk_mg_params& p) {
     }
     const int nb = p.block[l][0] * p.block[l][1] * p.block[l][2] * p.block[l][3];
     const int nr = (N / 2) * nb;
-    CRK_REQUIRE(p.m_prime[l] >= 1 && p.m_prime[l] <= 64, "m' must be in [1, 64]");
+    CRK_REQUIRE(p.m_prime[l] >= 1 && p.m_prime[l] <= 128, "m' must be in [1, 128]");
     CRK_REQUIRE(p.k[l] >= 8 && p.k[l] % 8 == 0 && p.k[l] <= 32,
                 "k must be a multiple of 8 in [8, 32] (2k is the MFMA tile height)");
     CRK_REQUIRE(p.k[l] <= p.m_prime[l], "k must not exceed m'");

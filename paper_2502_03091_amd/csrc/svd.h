@@ -24,6 +24,11 @@ struct SvdWork {
   double2 *G, *V, *G2, *W, *B;
   double *lam, *lam2;
   int* sweeps;
+  // m' > 64 only: packed Gram matrix, eigenvectors being accumulated (mm x mm),
+  // recorded rotations of one Jacobi segment, per-matrix segment state
+  double2 *Gp, *Vg;
+  void* rec;
+  int* state;
 };
 
 size_t svd_work_bytes(int m, int nr, int64_t nblocks);

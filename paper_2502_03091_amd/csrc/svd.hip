@@ -31,6 +31,7 @@ namespace crk {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kBigMax = 128;  // largest m' (columns of a block matrix)
 
 template <class T2>
 __device__ __forceinline__ double2 ld2(const T2* p, int64_t i) {
@@ -91,15 +92,24 @@ __device__ __forceinline__ void gram_store(double2* G, int m, int ti, int tj, co
 
 constexpr int kChunk = 32;
 
-template <class T2, int TI>
-__global__ __launch_bounds__(kThreads) void gram_kernel(ChiralSrc src, const T2* __restrict__ base,
-                                                        const double* __restrict__ inv_norm,
-                                                        double2* __restrict__ G) {
+// Rows [r0, r0+nrows) of a plain row-major matrix [N_r][m] (the rotated B = A V).
+__device__ void load_plain_rows(const double2* Bp, int r0, int nrows, int m, double2* lds) {
+  const int total = nrows * m;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) lds[e] = Bp[int64_t(r0) * m + e];
+}
+
+// G = A^dag A per (block, chirality): a GW x GW thread grid, each thread a
+// TI x TI tile of G (GW = 16 for m <= 64, 32 for m <= 128).  PLAIN: A is a
+// plain row-major [pair][N_r][m] matrix instead of the test vectors.
+template <class T2, int TI, int GW, bool PLAIN>
+__global__ __launch_bounds__(GW * GW) void gram_kernel(ChiralSrc src, const T2* __restrict__ base,
+                                                       const double* __restrict__ inv_norm,
+                                                       double2* __restrict__ G) {
   extern __shared__ double2 lds[];
   const int pair = blockIdx.x, alpha = pair & 1;
   const int64_t j = src.j0 + (pair >> 1);
   const int m = src.m, nr = src.h * src.nb;
-  const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
+  const int ti = threadIdx.x / GW, tj = threadIdx.x % GW;
   double2 acc[TI][TI];
 #pragma unroll
   for (int x = 0; x < TI; ++x)
@@ -108,7 +118,8 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(ChiralSrc src, const T2*
   for (int r0 = 0; r0 < nr; r0 += kChunk) {
     const int nrows = min(kChunk, nr - r0);
     __syncthreads();
-    load_block_rows(src, base, inv_norm, j, alpha, r0, nrows, m, lds, m);
+    if constexpr (PLAIN) load_plain_rows(reinterpret_cast<const double2*>(base) + int64_t(pair) * nr * m, r0, nrows, m, lds);
+    else load_block_rows(src, base, inv_norm, j, alpha, r0, nrows, m, lds, m);
     __syncthreads();
     gram_accumulate<TI>(lds, m, nrows, ti, tj, m, acc);
   }
@@ -283,7 +294,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int m, int nr, int k
   double2* Bs = T + m * k;      // [kFinChunk][m + 1]
   __shared__ double2 phase[64];
   __shared__ double sig[64];
-  __shared__ double2 colsum[64];
+  __shared__ double2 colsum[kBigMax];
   const double2* Vb = Vin + int64_t(pair) * m * m;
   const double2* Wb = Win + int64_t(pair) * m * m;
   // s_i = sum_x (V W)[x][i] = sum_y (sum_x V[x][y]) W[y][i]
@@ -331,6 +342,246 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int m, int nr, int k
   }
 }
 
+// ---------------------------------------------------------------- m' in (64, 128]
+// The m x m Gram matrix and its eigenvectors no longer fit in LDS together
+// (2 x 264 KiB at m = 128), so the eigendecomposition is split:
+//   * jacobi_seg_kernel keeps G in LDS as a packed Hermitian upper triangle
+//     (132 KiB at m = 128), runs up to kSegSweeps sweeps of the same cyclic
+//     round-robin Jacobi as jacobi_kernel, records every round's rotations in
+//     global memory and writes G back (packed) for the next segment;
+//   * replay_kernel applies the recorded rotations to V (global, mm x mm):
+//     one wavefront per row of V, the row staged in LDS, lane k rotating the
+//     columns of pair k in every round (the rounds of a row run in order within
+//     the wavefront; the pairs of one round are disjoint);
+//   * jacobi_sort_kernel orders the eigenvalues descending and writes the
+//     permuted eigenvectors in the layout jacobi_kernel writes.
+// The segments repeat until a sweep makes no rotation (or the sweep limit):
+// the result equals that of one Jacobi over all sweeps.
+constexpr int kBigThreads = 1024;
+constexpr int kSegSweeps = 4;
+constexpr int kReplayRounds = 32;  // rounds of rotations staged in LDS per chunk
+
+struct RotRec { double c, s, ex, ey; };
+
+__device__ __forceinline__ int tri_idx(int i, int j, int n) {  // i <= j, packed upper triangle of n x n
+  return i * (2 * n - i + 1) / 2 + (j - i);
+}
+__device__ __forceinline__ double2 tri_get(const double2* T, int i, int j, int n) {
+  return i <= j ? T[tri_idx(i, j, n)] : cconj(T[tri_idx(j, i, n)]);
+}
+__device__ __forceinline__ void tri_set(double2* T, int i, int j, int n, double2 v) {
+  if (i <= j) T[tri_idx(i, j, n)] = v;
+  else T[tri_idx(j, i, n)] = cconj(v);
+}
+
+// state[3*b]: 1 once converged; state[3*b+1]: rounds recorded by the last
+// segment; state[3*b+2]: sweeps done so far.
+__global__ __launch_bounds__(kBigThreads) void jacobi_seg_kernel(const double2* __restrict__ Gin,
+                                                                 double2* __restrict__ Gp, RotRec* __restrict__ rec,
+                                                                 int* __restrict__ state, int m, int first,
+                                                                 int max_sweeps, double tol) {
+  extern __shared__ double2 sh[];
+  const int mm = m + (m & 1), np = mm / 2, ntri = mm * (mm + 1) / 2;
+  double2* T = sh;
+  Rot* rot = reinterpret_cast<Rot*>(T + ntri);
+  int* prs = reinterpret_cast<int*>(rot + np);
+  __shared__ int n_rot;
+  const int64_t b = blockIdx.x;
+  int* st = state + 3 * b;
+  if (!first && (st[0] || st[2] >= max_sweeps)) {
+    if (threadIdx.x == 0) st[1] = 0;
+    return;
+  }
+  double2* Gpb = Gp + b * ntri;
+  if (first) {
+    const double2* Gb = Gin + b * m * m;
+    for (int e = threadIdx.x; e < mm * mm; e += blockDim.x) {
+      const int r = e / mm, c = e % mm;
+      if (r <= c) T[tri_idx(r, c, mm)] = (r < m && c < m) ? Gb[r * m + c] : make_double2(0, 0);
+    }
+  } else {
+    for (int e = threadIdx.x; e < ntri; e += blockDim.x) T[e] = Gpb[e];
+  }
+  const int done0 = first ? 0 : st[2];
+  RotRec* rb = rec + b * int64_t(kSegSweeps) * (mm - 1) * np;
+  int sweep = 0;
+  bool converged = false;
+  for (; sweep < kSegSweeps && done0 + sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) n_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < mm - 1; ++round) {
+      if (threadIdx.x < np) {
+        int p, q;
+        pair_of(round, threadIdx.x, mm, p, q);
+        prs[2 * threadIdx.x] = p;
+        prs[2 * threadIdx.x + 1] = q;
+        const double a = T[tri_idx(p, p, mm)].x, d = T[tri_idx(q, q, mm)].x;
+        const double2 g = T[tri_idx(p, q, mm)];
+        const double ag = hypot(g.x, g.y);
+        Rot R{1.0, 0.0, make_double2(1.0, 0.0)};
+        if (ag > tol * sqrt(fabs(a * d)) && ag > 0.0) {
+          const double zeta = (d - a) / (2.0 * ag);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t);
+          R.c = c;
+          R.s = t * c;
+          R.e = make_double2(g.x / ag, -g.y / ag);
+          atomicAdd(&n_rot, 1);
+        }
+        rot[threadIdx.x] = R;
+        rb[(int64_t(sweep) * (mm - 1) + round) * np + threadIdx.x] = RotRec{R.c, R.s, R.e.x, R.e.y};
+      }
+      __syncthreads();
+      // G <- J^dag G J on the 2x2 blocks of pair a (rows) and pair b (columns),
+      // each unordered block pair once; the block (b, a) is its conjugate transpose
+      for (int e = threadIdx.x; e < np * np; e += blockDim.x) {
+        const int ia = e / np, ib = e % np;
+        if (ia > ib) continue;
+        const Rot Ra = rot[ia], Rb = rot[ib];
+        const int pa = prs[2 * ia], qa = prs[2 * ia + 1], pb = prs[2 * ib], qb = prs[2 * ib + 1];
+        const double2 m00 = tri_get(T, pa, pb, mm), m01 = tri_get(T, pa, qb, mm);
+        const double2 m10 = tri_get(T, qa, pb, mm), m11 = tri_get(T, qa, qb, mm);
+        const double2 eb = Rb.e;
+        const double2 se_b = make_double2(Rb.s * eb.x, Rb.s * eb.y), ce_b = make_double2(Rb.c * eb.x, Rb.c * eb.y);
+        double2 t00 = cscale(m00, Rb.c) - cmul(m01, se_b);
+        double2 t01 = cscale(m00, Rb.s) + cmul(m01, ce_b);
+        double2 t10 = cscale(m10, Rb.c) - cmul(m11, se_b);
+        double2 t11 = cscale(m10, Rb.s) + cmul(m11, ce_b);
+        const double2 ea = cconj(Ra.e);
+        const double2 se_a = make_double2(Ra.s * ea.x, Ra.s * ea.y), ce_a = make_double2(Ra.c * ea.x, Ra.c * ea.y);
+        const double2 n00 = cscale(t00, Ra.c) - cmul(se_a, t10);
+        const double2 n01 = cscale(t01, Ra.c) - cmul(se_a, t11);
+        const double2 n10 = cscale(t00, Ra.s) + cmul(ce_a, t10);
+        const double2 n11 = cscale(t01, Ra.s) + cmul(ce_a, t11);
+        tri_set(T, pa, pb, mm, n00);
+        tri_set(T, pa, qb, mm, n01);
+        if (ia != ib) tri_set(T, qa, pb, mm, n10);  // on the diagonal block it is conj(n01)
+        tri_set(T, qa, qb, mm, n11);
+      }
+      __syncthreads();
+    }
+    const bool none = n_rot == 0;
+    __syncthreads();
+    if (none) { converged = true; break; }  // that sweep's rotations are all 1: not replayed
+  }
+  for (int e = threadIdx.x; e < ntri; e += blockDim.x) Gpb[e] = T[e];
+  if (threadIdx.x == 0) {
+    st[0] = converged ? 1 : 0;
+    st[1] = sweep * (mm - 1);
+    st[2] = done0 + sweep;
+  }
+}
+
+// One wavefront per row x of V (mm x mm, global), kBigThreads / 64 rows per
+// workgroup; the rows of matrix b are spread over ceil(mm / 16) workgroups.
+__global__ __launch_bounds__(kBigThreads) void replay_kernel(double2* __restrict__ Vg, const RotRec* __restrict__ rec,
+                                                             const int* __restrict__ state, int m, int first,
+                                                             int wg_per_matrix) {
+  __shared__ double2 row[kBigThreads / 64][kBigMax];
+  __shared__ RotRec prm[kReplayRounds][kBigMax / 2];
+  const int mm = m + (m & 1), np = mm / 2;
+  const int64_t b = blockIdx.x / wg_per_matrix;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int x = (blockIdx.x % wg_per_matrix) * (kBigThreads / 64) + w;
+  const int nrounds = state[3 * b + 1];
+  double2* Vb = Vg + b * mm * mm;
+  if (nrounds == 0 && !first) return;  // uniform over the workgroup
+  const bool live = x < mm;
+  if (live)  // the first segment starts from V = 1
+    for (int c = lane; c < mm; c += 64)
+      row[w][c] = first ? make_double2(x == c ? 1.0 : 0.0, 0.0) : Vb[int64_t(x) * mm + c];
+  const RotRec* rb = rec + b * int64_t(kSegSweeps) * (mm - 1) * np;
+  for (int t0 = 0; t0 < nrounds; t0 += kReplayRounds) {
+    const int nr = min(kReplayRounds, nrounds - t0);
+    __syncthreads();  // every wavefront is done with the previous chunk of parameters
+    for (int e = threadIdx.x; e < nr * np; e += blockDim.x) prm[e / np][e % np] = rb[int64_t(t0) * np + e];
+    __syncthreads();
+    if (!live) continue;
+    for (int t = 0; t < nr; ++t) {
+      const int round = (t0 + t) % (mm - 1);
+      if (lane < np) {
+        int p, q;
+        pair_of(round, lane, mm, p, q);
+        const RotRec R = prm[t][lane];
+        const double2 se = make_double2(R.s * R.ex, R.s * R.ey), ce = make_double2(R.c * R.ex, R.c * R.ey);
+        const double2 vp = row[w][p], vq = row[w][q];
+        row[w][p] = cscale(vp, R.c) - cmul(vq, se);
+        row[w][q] = cscale(vp, R.s) + cmul(vq, ce);
+      }
+      // the next round reads columns other lanes of this wavefront wrote
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  if (live)
+    for (int c = lane; c < mm; c += 64) Vb[int64_t(x) * mm + c] = row[w][c];
+}
+
+// Eigenvalues descending (ties by index) and the permuted eigenvectors, as jacobi_kernel writes them.
+__global__ __launch_bounds__(kBigMax) void jacobi_sort_kernel(const double2* __restrict__ Gp,
+                                                             const double2* __restrict__ Vg, double* __restrict__ lam,
+                                                             double2* __restrict__ Vout, const int* __restrict__ state,
+                                                             int* __restrict__ sweeps_out, int m) {
+  const int mm = m + (m & 1), ntri = mm * (mm + 1) / 2;
+  const int64_t b = blockIdx.x;
+  const double2* T = Gp + b * ntri;
+  const double2* Vb = Vg + b * mm * mm;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double li = T[tri_idx(i, i, mm)].x;
+    int rank = 0;
+    for (int jj = 0; jj < m; ++jj) {
+      const double lj = T[tri_idx(jj, jj, mm)].x;
+      rank += (lj > li) || (lj == li && jj < i);
+    }
+    lam[b * m + rank] = li;
+    for (int x = 0; x < m; ++x) Vout[b * m * m + int64_t(x) * m + rank] = Vb[int64_t(x) * mm + i];
+  }
+  if (threadIdx.x == 0 && sweeps_out) sweeps_out[b] = state[3 * b + 2];
+}
+
+// B = A V for m <= 128: kRotBigRows rows of A per pass in LDS, each thread one
+// column c and kRotBigRows / 8 rows (V read from global, reused across them).
+constexpr int kRotBigRows = 64;
+
+template <class T2>
+__global__ __launch_bounds__(kBigThreads) void rotate_big_kernel(ChiralSrc src, const T2* __restrict__ base,
+                                                                 const double* __restrict__ inv_norm,
+                                                                 const double2* __restrict__ Vin,
+                                                                 double2* __restrict__ B) {
+  extern __shared__ double2 lds[];  // [kRotBigRows][m]
+  const int m = src.m, nr = src.h * src.nb;
+  const int pair = blockIdx.x, alpha = pair & 1;
+  const int64_t j = src.j0 + (pair >> 1);
+  const double2* Vb = Vin + int64_t(pair) * m * m;
+  double2* Bp = B + int64_t(pair) * nr * m;
+  const int c = threadIdx.x % kBigMax, g = threadIdx.x / kBigMax;  // g in [0, 8)
+  constexpr int kRows = kRotBigRows / (kBigThreads / kBigMax);
+  for (int r0 = 0; r0 < nr; r0 += kRotBigRows) {
+    const int nrows = min(kRotBigRows, nr - r0);
+    __syncthreads();
+    load_block_rows(src, base, inv_norm, j, alpha, r0, nrows, m, lds, m);
+    __syncthreads();
+    if (c >= m) continue;
+    double2 acc[kRows];
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) acc[u] = make_double2(0, 0);
+    for (int i = 0; i < m; ++i) {
+      const double2 v = Vb[int64_t(i) * m + c];
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) {
+        const int rr = g + 8 * u;
+        if (rr < nrows) cfma(acc[u], lds[rr * m + i], v);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) {
+      const int rr = g + 8 * u;
+      if (rr < nrows) Bp[int64_t(r0 + rr) * m + c] = acc[u];
+    }
+  }
+}
+
 // Allow dynamic LDS beyond the 64 KiB default (gfx950 has 160 KiB per CU).
 // Dynamic LDS above 64 KiB must be enabled per kernel (gfx950: 160 KiB per workgroup,
 // static LDS included).
@@ -340,15 +591,17 @@ template <class K> void allow_lds(K kernel, size_t bytes) {
                               int(bytes)));
 }
 
-template <class T2>
+template <class T2, bool PLAIN>
 void launch_gram(const ChiralSrc& s, const void* base, const double* inv_norm, double2* G, hipStream_t st) {
   const size_t lds = sizeof(double2) * kChunk * s.m;
   const dim3 grid = dim3(unsigned(2 * s.nblocks));
   const T2* b = static_cast<const T2*>(base);
-  if (s.m <= 16) hipLaunchKernelGGL((gram_kernel<T2, 1>), grid, dim3(kThreads), lds, st, s, b, inv_norm, G);
-  else if (s.m <= 32) hipLaunchKernelGGL((gram_kernel<T2, 2>), grid, dim3(kThreads), lds, st, s, b, inv_norm, G);
-  else if (s.m <= 48) hipLaunchKernelGGL((gram_kernel<T2, 3>), grid, dim3(kThreads), lds, st, s, b, inv_norm, G);
-  else hipLaunchKernelGGL((gram_kernel<T2, 4>), grid, dim3(kThreads), lds, st, s, b, inv_norm, G);
+  if (s.m <= 16) hipLaunchKernelGGL((gram_kernel<T2, 1, 16, PLAIN>), grid, dim3(256), lds, st, s, b, inv_norm, G);
+  else if (s.m <= 32) hipLaunchKernelGGL((gram_kernel<T2, 2, 16, PLAIN>), grid, dim3(256), lds, st, s, b, inv_norm, G);
+  else if (s.m <= 48) hipLaunchKernelGGL((gram_kernel<T2, 3, 16, PLAIN>), grid, dim3(256), lds, st, s, b, inv_norm, G);
+  else if (s.m <= 64) hipLaunchKernelGGL((gram_kernel<T2, 4, 16, PLAIN>), grid, dim3(256), lds, st, s, b, inv_norm, G);
+  else if (s.m <= 96) hipLaunchKernelGGL((gram_kernel<T2, 3, 32, PLAIN>), grid, dim3(1024), lds, st, s, b, inv_norm, G);
+  else hipLaunchKernelGGL((gram_kernel<T2, 4, 32, PLAIN>), grid, dim3(1024), lds, st, s, b, inv_norm, G);
   CRK_LAUNCH_CHECK();
 }
 
@@ -374,42 +627,101 @@ size_t jacobi_lds(int m) {
 
 }  // namespace
 
+namespace {
+
+// Eigendecomposition of the batch's m x m Hermitian matrices for 64 < m <= 128:
+// Jacobi segments (G packed in LDS) alternating with the replay of their
+// rotations onto V, then the sort.  Converged matrices skip the later segments.
+void big_eig(const SvdWork& w, const double2* Gin, double* lam, double2* Vout, int* sweeps_out, int m, unsigned npair,
+             double tol, hipStream_t st) {
+  const int mm = m + (m & 1), ntri = mm * (mm + 1) / 2;
+  const size_t lds = sizeof(double2) * ntri + sizeof(Rot) * (mm / 2) + sizeof(int) * mm;
+  allow_lds(jacobi_seg_kernel, lds);
+  const int wgpm = (mm + kBigThreads / 64 - 1) / (kBigThreads / 64);
+  const int max_sweeps = 40;
+  for (int seg = 0; seg * kSegSweeps < max_sweeps; ++seg) {
+    hipLaunchKernelGGL(jacobi_seg_kernel, dim3(npair), dim3(kBigThreads), lds, st, Gin, w.Gp,
+                       static_cast<RotRec*>(w.rec), w.state, m,
+                       int(seg == 0), max_sweeps, tol);
+    CRK_LAUNCH_CHECK();
+    hipLaunchKernelGGL(replay_kernel, dim3(npair * unsigned(wgpm)), dim3(kBigThreads), 0, st, w.Vg,
+                       static_cast<const RotRec*>(w.rec), w.state, m,
+                       int(seg == 0), wgpm);
+    CRK_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(jacobi_sort_kernel, dim3(npair), dim3(kBigMax), 0, st, w.Gp, w.Vg, lam, Vout, w.state,
+                     sweeps_out, m);
+  CRK_LAUNCH_CHECK();
+}
+
+}  // namespace
+
 void chiral_svd(const ChiralSrc& s, int src_is_double, const void* base, const double* inv_norm, int k,
                 const SvdWork& w, int64_t wcap, double2* P, double* sigma, hipStream_t st) {
-  CRK_REQUIRE(s.m >= 1 && s.m <= 64, "m' must be in [1, 64]");
+  CRK_REQUIRE(s.m >= 1 && s.m <= kBigMax, "m' must be in [1, 128]");
   const int nr = s.h * s.nb;
   CRK_REQUIRE(k >= 1 && k <= s.m && k <= nr, "k must satisfy 1 <= k <= min(m', N_r)");
+  CRK_REQUIRE(k <= 64, "k above 64 is not supported by the SVD finaliser");
   CRK_REQUIRE(wcap >= 1, "SVD work space must hold at least one block");
   const int m = s.m;
   const double tol = 1e-15;
   const int nsig = m < nr ? m : nr;
+  const bool big = m > 64;
   const size_t lds = sizeof(double2) * (size_t(m) * k + size_t(kFinChunk) * (m + 1));
-  allow_lds(jacobi_kernel, jacobi_lds(m));
+  CRK_REQUIRE(lds <= 160 * 1024, "SVD finaliser: m' * k too large for LDS");
+  if (!big) allow_lds(jacobi_kernel, jacobi_lds(m));
   allow_lds(finalize_kernel, lds);
   for (int64_t j0 = 0; j0 < s.nblocks; j0 += wcap) {
     ChiralSrc b = s;
     b.j0 = j0;
     b.nblocks = std::min(wcap, s.nblocks - j0);
     const unsigned npair = unsigned(2 * b.nblocks);
-    if (src_is_double) launch_gram<double2>(b, base, inv_norm, w.G, st);
-    else launch_gram<float2>(b, base, inv_norm, w.G, st);
-    hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kJacobiThreads), jacobi_lds(m), st, w.G, w.lam, w.V, m, 40, tol,
-                       w.sweeps);
-    CRK_LAUNCH_CHECK();
-    if (src_is_double) launch_rotate<double2>(b, base, inv_norm, w.V, w.B, w.G2, st);
-    else launch_rotate<float2>(b, base, inv_norm, w.V, w.B, w.G2, st);
-    hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kJacobiThreads), jacobi_lds(m), st, w.G2, w.lam2, w.W, m, 40, tol,
-                       w.sweeps ? w.sweeps + npair : nullptr);
-    CRK_LAUNCH_CHECK();
+    if (src_is_double) launch_gram<double2, false>(b, base, inv_norm, w.G, st);
+    else launch_gram<float2, false>(b, base, inv_norm, w.G, st);
+    if (!big) {
+      hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kJacobiThreads), jacobi_lds(m), st, w.G, w.lam, w.V, m, 40,
+                         tol, w.sweeps);
+      CRK_LAUNCH_CHECK();
+      if (src_is_double) launch_rotate<double2>(b, base, inv_norm, w.V, w.B, w.G2, st);
+      else launch_rotate<float2>(b, base, inv_norm, w.V, w.B, w.G2, st);
+      hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kJacobiThreads), jacobi_lds(m), st, w.G2, w.lam2, w.W, m,
+                         40, tol, w.sweeps ? w.sweeps + npair : nullptr);
+      CRK_LAUNCH_CHECK();
+    } else {
+      big_eig(w, w.G, w.lam, w.V, w.sweeps, m, npair, tol, st);
+      const size_t rl = sizeof(double2) * kRotBigRows * m;
+      if (src_is_double) {
+        allow_lds(rotate_big_kernel<double2>, rl);
+        hipLaunchKernelGGL(rotate_big_kernel<double2>, dim3(npair), dim3(kBigThreads), rl, st, b,
+                           static_cast<const double2*>(base), inv_norm, w.V, w.B);
+      } else {
+        allow_lds(rotate_big_kernel<float2>, rl);
+        hipLaunchKernelGGL(rotate_big_kernel<float2>, dim3(npair), dim3(kBigThreads), rl, st, b,
+                           static_cast<const float2*>(base), inv_norm, w.V, w.B);
+      }
+      CRK_LAUNCH_CHECK();
+      launch_gram<double2, true>(b, w.B, nullptr, w.G2, st);
+      big_eig(w, w.G2, w.lam2, w.W, w.sweeps ? w.sweeps + npair : nullptr, m, npair, tol, st);
+    }
     hipLaunchKernelGGL(finalize_kernel, dim3(npair), dim3(kThreads), lds, st, m, nr, k, w.V, w.W, w.lam2, w.B,
                        P + 2 * j0 * int64_t(k) * nr, sigma + 2 * j0 * int64_t(nsig), nsig);
     CRK_LAUNCH_CHECK();
   }
 }
 
+namespace {
+size_t big_bytes_per_pair(int m) {
+  if (m <= 64) return 0;
+  const size_t mm = size_t(m + (m & 1)), ntri = mm * (mm + 1) / 2;
+  return sizeof(double2) * (ntri + mm * mm) + sizeof(RotRec) * kSegSweeps * (mm - 1) * (mm / 2) + 3 * sizeof(int) +
+         3 * 256;
+}
+}  // namespace
+
 size_t svd_work_bytes(int m, int nr, int64_t nblocks) {
   const size_t np = size_t(2 * nblocks);
-  return np * (sizeof(double2) * (4 * size_t(m) * m + size_t(nr) * m) + sizeof(double) * 2 * m + 2 * sizeof(int)) + 256 * 8;
+  return np * (sizeof(double2) * (4 * size_t(m) * m + size_t(nr) * m) + sizeof(double) * 2 * m + 2 * sizeof(int) +
+               big_bytes_per_pair(m)) + 256 * 12;
 }
 
 SvdWork svd_work_carve(void* p, int m, int nr, int64_t nblocks) {
@@ -425,6 +737,17 @@ SvdWork svd_work_carve(void* p, int m, int nr, int64_t nblocks) {
   w.lam = reinterpret_cast<double*>(take(sizeof(double) * np * m));
   w.lam2 = reinterpret_cast<double*>(take(sizeof(double) * np * m));
   w.sweeps = reinterpret_cast<int*>(take(sizeof(int) * 2 * np));
+  w.Gp = nullptr;
+  w.Vg = nullptr;
+  w.rec = nullptr;
+  w.state = nullptr;
+  if (m > 64) {
+    const size_t mm = size_t(m + (m & 1)), ntri = mm * (mm + 1) / 2;
+    w.Gp = reinterpret_cast<double2*>(take(sizeof(double2) * np * ntri));
+    w.Vg = reinterpret_cast<double2*>(take(sizeof(double2) * np * mm * mm));
+    w.rec = take(sizeof(RotRec) * np * kSegSweeps * (mm - 1) * (mm / 2));
+    w.state = reinterpret_cast<int*>(take(sizeof(int) * 3 * np));
+  }
   return w;
 }
 
