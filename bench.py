@@ -1,28 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the chiral rank-k multigrid hot path on one MI355X.
 
-Default workload (anisotropic 16^3x32 lattice, xi = 3.5): smoothed random SU(3)
-links exp(i 0.2 H) + 3 APE-like projections, m0 placed just above the critical
-mass located by the oracle (tests/golden/m0_tuned.json), m' = 48 test vectors
-with 60 MR sweeps in FP32, 4^4 blocks, chiral SVD truncation to k = 24 per
-chirality (FP64), Galerkin coarse operator (FP64), then an MG-preconditioned
-GCR solve of 10 Gaussian right-hand sides to a true relative residual of 1e-10
-(FP64 outer GCR, FP32 K-cycle with 8 MR post-smoothing steps).
+Default workload (isotropic 32^4): smoothed random SU(3) links exp(i 0.25 H) +
+3 APE-like projections, m0 close to the critical mass (its smallest singular
+value sigma_min(D) is measured on the device and reported), two-level
+hierarchy with m' = 64 test vectors given 60 MR sweeps, 4^4 blocks, chiral SVD
+truncation to k = 24 per chirality (FP64), Galerkin coarse operator (FP64),
+then an MG-preconditioned GCR solve of the 12 point sources (one per spin and
+colour) to a true relative residual of 1e-10 (FP64 outer GCR, K-cycle with 8
+MR post-smoothing steps).
 
-One step = one full setup + one 10-RHS solve, inputs resident in device memory.
-The JSON line reports the MG setup seconds (value), the dslash bandwidth of the
-smoother's launches, solve throughput and latency, the same workload in the
-plain FP64 form and with the conventional basis (m' = k = 24), a short run of
-the serving loop, the kernel's roofline position and the FP64 CPU oracle timed
-on a bounded sample of the same workload.
+One step = one full setup (FP32 smoother) + one 12-RHS solve (FP32 K-cycle),
+inputs resident in device memory.  The JSON line reports the MG setup seconds
+(value) split by stage, solves/s, per-right-hand-side time-to-solution
+percentiles, the same workload in the plain FP64 form and the FP16-storage
+form and with the conventional basis (m' = k = 24), the dslash bandwidth over
+volumes, precisions and RHS counts, the anisotropic 16^3x32 workload as a
+labelled sub-result, a short run of the serving loop, the smoother dslash's
+roofline position and the FP64 CPU oracle timed on a bounded sample.
 
-Other workloads (one JSON line each): --workload iso32 (32^4, m' = 64 -> k = 24,
-12 point sources, FP64 / FP32 / FP16S forms), --workload volume (three-level
-hierarchies on 24^3x48, 32^3x64, 48^3x96, rank-k vs conventional) and
---workload serve (Poisson arrival-rate sweep of the serving loop over resident
-16^3x32, 24^3x48 and 32^4 hierarchies), --workload kernels (operator launches
-per form and RHS count) and --workload params (setup and solve over m', k and
-the number of setup sweeps on the default workload).
+Other workloads (one JSON line each): --workload c2 (anisotropic 16^3x32,
+m' = 48 -> k = 24, 10 Gaussian RHS), --workload volume (three-level
+hierarchies on 24^3x48, 32^3x64, 48^3x96), --workload serve (Poisson arrival
+sweep of the serving loop over resident 16^3x32, 24^3x48 and 32^4
+hierarchies), --workload kernels (operator launches per form and RHS count),
+--workload params (setup and solve over m', k and the number of setup sweeps)
+and --workload mass (sigma_min(D) against m0 on the 16^3x32 and 32^4 lattices).
 """
 from __future__ import annotations
 
@@ -39,13 +42,17 @@ sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
 
+# anisotropic 16^3x32 (stands in for the paper's anisotropic ensemble)
 DIMS = [16, 16, 16, 32]
 XI, EPS, N_APE, CONFIG = 3.5, 0.2, 3, 2
 M_PRIME, K, BLOCK, N_SMOOTH, NRHS = 48, 24, [4, 4, 4, 4], 60, 10
+# isotropic 32^4 (stands in for the paper's isotropic ensemble)
+C3_DIMS, C3_MPRIME, C3_K, C3_NRHS = [32, 32, 32, 32], 64, 24, 12
 SOLVE = dict(nu_post=8, tau=0.1, restart=8, max_iter=500)
 ISO = dict(xi=1.0, eps=0.25, n_ape=3, config=4)
 HBM_PEAK_GBPS = 8000.0
 METRIC = "MG setup s & dslash GB/s; solves/s, p50/p99 at 1e-10 vs plain FP64 form"
+SEED = 0x2502030910
 
 
 def log(*a):
@@ -66,12 +73,15 @@ def dslash_bytes(V, nrhs, form):
     return V * (2 * spinor * nrhs + link)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "wilson_tile_fp32_32x32x32x32_64rhs.json")
+
+
 def measured_traffic():
-    """HBM bytes per 48-RHS smoother launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE counters, or None when the kernel source changed since they were taken."""
-    path = os.path.join(ROOT, "profiles", "wilson_tile_fp32_16x16x16x32_48rhs.json")
+    """HBM bytes per 64-RHS smoother launch at 32^4 from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE counters (scaled by the copy-kernel calibration), or
+    None when the kernel source changed since they were taken."""
     try:
-        with open(path) as f:
+        with open(PROFILE) as f:
             rec = json.load(f)
     except OSError:
         return None
@@ -94,39 +104,436 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def cpu_baseline(U, m0, V):
-    """Time the oracle (one thread) on a bounded sample of one setup and scale to a full setup."""
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
+
+
+# ------------------------------------------------------------------ smallest singular value of D
+
+def sigma_min(crk, lat, H, p=8, max_it=12, rtol=1e-4, solve_tol=1e-9, seed=11, tag=""):
+    """Smallest singular values of D (the smallest |eigenvalues| of the Hermitian
+    gamma5 D) by block inverse iteration on (D^dag D)^-1 = D^-1 gamma5 D^-1 gamma5:
+    every step is two batched MG solves (FP32 K-cycle, FP64 outer GCR to
+    solve_tol), followed by Rayleigh-Ritz on D^dag D with the FP64 operator.
+    Returns the p smallest estimates, the relative residual
+    ||D^dag D x - s^2 x|| / s^2 of the smallest Ritz pair and the iterations."""
+    import torch
+    dev = torch.device("cuda", 0)
+    V = lat.V
+    n = 12 * V
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    g5 = torch.tensor([1.0] * 6 + [-1.0] * 6, dtype=torch.float64, device=dev).repeat(V)
+
+    def dirac(X):
+        pp = X.shape[0]
+        hl = torch.view_as_real(X.contiguous()).reshape(-1)
+        a = torch.empty(lat.field_bytes(0, pp), dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        out = torch.empty_like(hl)
+        lat.import_dev(hl, a, pp, 0)
+        lat.dirac_apply_dev(a, b, pp, 0)
+        lat.export_dev(b, out, pp, 0)
+        return torch.view_as_complex(out.view(pp, n, 2))
+
+    def solve(B):
+        pp = B.shape[0]
+        bd = torch.view_as_real(B.contiguous()).reshape(-1)
+        xd = torch.empty_like(bd)
+        info = H.solve_dev(bd, xd, pp, form=crk.FORM_FP32, raise_on_noconv=False, **dict(SOLVE, tol=solve_tol))
+        return torch.view_as_complex(xd.view(pp, n, 2)), info
+
+    X = torch.complex(torch.randn(p, n, generator=g, device=dev, dtype=torch.float64),
+                      torch.randn(p, n, generator=g, device=dev, dtype=torch.float64))
+    prev, hist, solve_iters = None, [], []
+    t0 = time.perf_counter()
+    for it in range(max_it):
+        Q, _ = torch.linalg.qr(X.T)
+        X = Q.T.contiguous()
+        Z = dirac(X)
+        M = Z.conj() @ Z.T
+        M = 0.5 * (M + M.conj().T)
+        w, Wv = torch.linalg.eigh(M)
+        X = (Wv.T @ X).contiguous()
+        Z = (Wv.T @ Z).contiguous()
+        s = torch.sqrt(torch.clamp(w, min=0)).cpu().numpy()
+        hist.append(float(s[0]))
+        log(f"{tag}sigma_min step {it}: {np.array2string(s[:4], precision=6)}")
+        if prev is not None and abs(s[0] - prev) <= rtol * s[0]:
+            break
+        prev = float(s[0])
+        Y, i1 = solve(g5 * X)
+        X, i2 = solve(g5 * Y)
+        solve_iters.append([i1["iters"], i2["iters"]])
+    # D^dag D x = gamma5 D gamma5 (D x) for the smallest Ritz pair
+    r = g5 * dirac((g5 * Z[0])[None])[0] - float(w[0]) * X[0]
+    res = float(torch.linalg.vector_norm(r)) / max(float(w[0]), 1e-300)
+    return {"sigma_min": float(s[0]), "smallest": [float(v) for v in s[:4]], "ritz_residual": res,
+            "steps": it + 1, "history": hist, "outer_iters_per_solve": solve_iters,
+            "seconds": time.perf_counter() - t0, "block": p}
+
+
+# ------------------------------------------------------------------ CPU baseline (the oracle)
+
+def cpu_baseline(U32, m0):
+    """The FP64 oracle timed on the host cores on a bounded sample of one 32^4
+    setup, scaled to the whole setup:
+      * smoother: the oracle's mr_null on the full 32^4 lattice for 1 of the 64
+        vectors and 1 sweep (two operator applications), scaled by 64 vectors x
+        61 applications;
+      * SVD and Galerkin: the oracle's chiral_blocks, prolongator_blocks and
+        galerkin on an 8^4 lattice with the same 4^4 blocks, m' = 64 -> k = 24
+        (32 block SVDs of 1536 x 64, 16 coarse sites), scaled per block and per
+        coarse site to the 8192 SVDs and 4096 coarse sites of 32^4.
+    Each sample runs with the BLAS threads at the host's CPU count and at 1.  The
+    tiny 4^4 workload (setup and solve) is timed in full."""
     from threadpoolctl import threadpool_limits
 
-    from oracle import chiral, galerkin, mr
+    from oracle import chiral, galerkin, mg as omg, mr
+    from oracle.stencil import as_columns
     from oracle.wilson import WilsonOp
-    with threadpool_limits(limits=1):
-        op = WilsonOp(U, DIMS, m0, XI)
-        v = synth.gaussian_vectors(M_PRIME, V, 12, config=CONFIG, level=0)
-        cols = np.ascontiguousarray(np.transpose(v, (1, 2, 0)))
-        t0 = time.perf_counter()
-        q = op.apply(cols)                                  # one sweep's operator application, all 48 vectors
-        a = mr.cdot(q, cols) / mr.cdot(q, q).real
-        cols = cols + a * cols
-        t_sweep = time.perf_counter() - t0
-        psi = mr.normalize_columns(cols)
-        A = chiral.chiral_blocks(psi, DIMS, BLOCK)
-        nsvd = 64
-        t0 = time.perf_counter()
-        Pb, _ = chiral.prolongator_blocks(A[:nsvd // 2], K)  # nsvd (block, chirality) SVDs
-        t_svd = (time.perf_counter() - t0) / nsvd
-        Pfull = np.zeros((A.shape[0], 2, A.shape[2], K), dtype=np.complex128)
-        Pfull[:nsvd // 2] = Pb
-        t0 = time.perf_counter()
-        galerkin.galerkin(op, Pfull, BLOCK, blocks=[0, 1])   # two coarse sites
-        t_gal = (time.perf_counter() - t0) / 2
-    nblocks = A.shape[0]
-    est = (N_SMOOTH + 1) * t_sweep + 2 * nblocks * t_svd + nblocks * t_gal
-    sample = (f"oracle FP64, 1 thread: 1 of {N_SMOOTH + 1} smoother operator passes over all {M_PRIME} vectors, "
-              f"{nsvd} of {2 * nblocks} block SVDs, 2 of {nblocks} Galerkin coarse sites; "
-              f"scaled to one full setup")
-    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle", "sample": sample,
-            "sample_seconds": t_sweep + nsvd * t_svd + 2 * t_gal, "host_cpus": os.cpu_count()}
+    ncpu = os.cpu_count() or 1
+    V = int(np.prod(C3_DIMS))
+    op = WilsonOp(U32, C3_DIMS, m0, 1.0)
+    psi1 = as_columns(synth.gaussian_vectors(1, V, 12, config=ISO["config"], level=0))
+    dims8 = [8, 8, 8, 8]
+    U8 = synth.gauge_field(dims8, ISO["eps"], ISO["n_ape"], config=ISO["config"])
+    op8 = WilsonOp(U8, dims8, m0, 1.0)
+    psi8 = mr.normalize_columns(mr.mr_null(op8, as_columns(synth.gaussian_vectors(64, 4096, 12, config=ISO["config"],
+                                                                                   level=0)), 2))
+    out = {"kind": "oracle", "unit": "s", "host_cpus": ncpu}
+    for threads in (ncpu, 1):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            mr.mr_null(op, psi1, 1)
+            t_app = (time.perf_counter() - t0) / 2.0         # one application to one vector
+            t0 = time.perf_counter()
+            A = chiral.chiral_blocks(psi8, dims8, BLOCK)
+            Pb, _ = chiral.prolongator_blocks(A, C3_K)
+            t_svd = (time.perf_counter() - t0) / (2 * A.shape[0])
+            t0 = time.perf_counter()
+            galerkin.galerkin(op8, Pb, BLOCK)
+            t_gal = (time.perf_counter() - t0) / A.shape[0]
+            # C1 in full: 4^4, m' = 16 -> k = 8, 2^4 blocks, 20 MR sweeps, one RHS to 1e-10
+            t0 = time.perf_counter()
+            U1 = synth.gauge_field([4, 4, 4, 4], 0.3, 0, config=1)
+            op1 = WilsonOp(U1, [4, 4, 4, 4], -0.4, 1.0)
+            lev = omg.mg_setup(op1, [16], [8], [[2, 2, 2, 2]], [20],
+                               [as_columns(synth.gaussian_vectors(16, 256, 12, config=1, level=0))])
+            omg.mg_solve(lev, as_columns(synth.gaussian_rhs(1, 256, config=1)), tol=1e-10)
+            t_c1 = time.perf_counter() - t0
+        nblk = V // 256
+        est = (N_SMOOTH + 1) * C3_MPRIME * t_app + 2 * nblk * t_svd + nblk * t_gal
+        key = "threads_all" if threads == ncpu else "threads_1"
+        out[key] = {"setup_s": est, "cores": threads, "smoother_application_s": t_app, "svd_per_block_s": t_svd,
+                    "galerkin_per_coarse_site_s": t_gal, "tiny_4x4x4x4_setup_and_solve_s": t_c1}
+        log("cpu baseline", key, json.dumps(out[key]))
+    best = min((out["threads_all"], out["threads_1"]), key=lambda r: r["setup_s"])
+    out.update({"value": best["setup_s"], "cores": best["cores"],
+                "sample": "oracle FP64: mr_null on 32^4 for 1 of 64 vectors and 1 sweep (scaled x64 vectors x61 "
+                          "applications); chiral_blocks + prolongator_blocks + galerkin on 8^4 with 4^4 blocks, "
+                          "m'=64 -> k=24 (32 SVDs, 16 coarse sites; scaled per block to 8192 SVDs and 4096 coarse "
+                          "sites); scaled to one 32^4 setup; 'cores' is the thread count of the faster run"})
+    return out
+
+
+# ------------------------------------------------------------------ dslash over volumes, forms and RHS counts
+
+def dslash_sweep(crk, extents=(32, 48), forms=(0, 1, 2), counts=(1, 12, 64), reps=10):
+    """The fine operator of a 4^4-blocked hierarchy (tile kernel for FP32 and
+    FP16S, direction-split kernel for FP64) through crk_mg_apply_dev, HIP events
+    around each launch on the stream it runs on, a 1 GiB buffer overwritten before
+    every launch so that no input is served from the 256 MB last-level cache."""
+    import torch
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(20250305)
+    sizes = {16: [16, 16, 16, 32], 32: [32, 32, 32, 32], 48: [48, 48, 48, 96]}
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    rows = []
+    for ext in extents:
+        dims = sizes[ext]
+        V = int(np.prod(dims))
+        U = synth.gauge_field_device(dims, ISO["eps"], ISO["n_ape"], config=ISO["config"])
+        lat = crk.Lattice(dims, tuned_m0("iso_xi1_eps0.25"), ISO["xi"])
+        lat.load_gauge(U)
+        del U
+        torch.cuda.empty_cache()
+        H = crk.Hierarchy(lat, m_prime=[8], k=[8], block=[BLOCK], n_smooth=[0], setup_form=crk.FORM_FP32, seed=SEED)
+        for form in forms:
+            for nrhs in counts:
+                nb = H.field_bytes(0, form, nrhs)
+                free, _ = torch.cuda.mem_get_info()
+                row = {"lattice": dims, "form": FORM_NAMES[form], "nrhs": nrhs}
+                if 2 * nb > 0.8 * free:
+                    row["skipped"] = "fields do not fit"
+                    rows.append(row)
+                    continue
+                a = _device_field(torch, nb, form, nrhs, V, dev, gen)
+                b = torch.empty_like(a)
+                t = _time_apply(torch, H, 0, a, b, nrhs, form, reps=reps, flush=flush)
+                alg = dslash_bytes(V, nrhs, form)
+                row.update({"us": t * 1e6, "alg_GBps": alg / t / 1e9, "frac_of_8TBps": alg / t / 1e9 / HBM_PEAK_GBPS})
+                log("dslash", json.dumps(row))
+                rows.append(row)
+                del a, b
+                torch.cuda.empty_cache()
+        H.close()
+        lat.close()
+    del flush
+    torch.cuda.empty_cache()
+    return rows
+
+
+# ------------------------------------------------------------------ default: isotropic 32^4
+
+def c3_lattice(crk, progress=log):
+    m0 = tuned_m0("iso_xi1_eps0.25")
+    U = synth.gauge_field_device(C3_DIMS, ISO["eps"], ISO["n_ape"], config=ISO["config"], progress=progress)
+    lat = crk.Lattice(C3_DIMS, m0, ISO["xi"])
+    lat.load_gauge(U)
+    return lat, U, m0
+
+
+def c3_step(crk, lat, b, x, setup_form, form, m_prime=C3_MPRIME, k=C3_K, keep=False):
+    """One setup + one solve of the 12 point sources; returns the record (and the hierarchy if keep)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = crk.Hierarchy(lat, m_prime=[m_prime], k=[k], block=[BLOCK], n_smooth=[N_SMOOTH], setup_form=setup_form,
+                      seed=SEED)
+    t1 = time.perf_counter()
+    info = H.solve_dev(b, x, C3_NRHS, form=form, raise_on_noconv=False, **SOLVE)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    tim = H.timing(0)
+    rec = {"setup_s": t1 - t0, "setup_device_s": tim["total"],
+           "setup_stages_s": {k_: tim[k_] for k_ in ("smoother", "svd", "galerkin")},
+           "smoother_dslash_launch_s": tim["dslash_avg"], "smoother_dslash_launches": int(tim["dslash_count"]),
+           "solve_s": t2 - t1, "rhs_seconds": info["rhs"]["seconds"], "rhs_iters": info["rhs"]["iters"],
+           "iters": info["iters"], "level_iters": info["level_iters"], "true_rel_resid": info["true_rel_resid"],
+           "converged": info["converged"]}
+    if keep:
+        return rec, H
+    H.close()
+    return rec
+
+
+def form_summary(recs, V, setup_form, m_prime=C3_MPRIME):
+    """Mean setup and solve over steps; per-RHS time-to-solution percentiles pooled over steps."""
+    rhs = [t for r in recs for t in r["rhs_seconds"]]
+    setup = float(np.mean([r["setup_s"] for r in recs]))
+    solve = float(np.mean([r["solve_s"] for r in recs]))
+    launch = float(np.mean([r["smoother_dslash_launch_s"] for r in recs]))
+    sform = 0 if setup_form == 0 else 1
+    return {
+        "setup_s": setup,
+        "setup_stages_s": {k_: float(np.mean([r["setup_stages_s"][k_] for r in recs]))
+                           for k_ in ("smoother", "svd", "galerkin")},
+        "solve_s": solve, "solves_per_s": C3_NRHS / solve, "time_to_solution_s": setup + solve,
+        "rhs_time_to_solution_p50_s": pct(rhs, 50), "rhs_time_to_solution_p99_s": pct(rhs, 99),
+        "iters": max(r["iters"] for r in recs), "level_iters": recs[-1]["level_iters"],
+        "true_rel_resid": max(r["true_rel_resid"] for r in recs), "converged": all(r["converged"] for r in recs),
+        "smoother_dslash_GBps": dslash_bytes(V, m_prime, sform) / launch / 1e9,
+        "smoother_dslash_launch_ms": 1e3 * launch,
+        "steps": len(recs),
+    }
+
+
+def workload_c3(crk, args):
+    import torch
+    dev = torch.device("cuda", 0)
+    V = int(np.prod(C3_DIMS))
+    lat, U, m0 = c3_lattice(crk)
+    b = torch.from_numpy(synth.point_sources(V).view(np.float64)).to(dev)
+    x = torch.empty_like(b)
+    for _ in range(args.warmup):
+        c3_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP32)
+    torch.cuda.synchronize()
+    recs = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        r = c3_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP32)
+        log(f"step: setup {r['setup_s']:.4f} s, solve {r['solve_s']:.4f} s, iters {r['iters']}")
+        recs.append(r)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    fp32 = form_summary(recs, V, crk.FORM_FP32)
+    launch = float(np.mean([r["smoother_dslash_launch_s"] for r in recs]))
+    alg = dslash_bytes(V, C3_MPRIME, 1)
+    achieved = alg / launch / 1e9
+    result = {
+        "metric": METRIC,
+        "value": fp32["setup_s"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "32^4 isotropic, smoothed random SU(3) links (eps=0.25, 3 APE-like projections, generated "
+                        "on the device); chiral rank-k setup m'=64 -> k=24, 4^4 blocks, 60 FP32 MR sweeps, FP64 "
+                        "SVD + Galerkin; two-level MG-GCR solve of the 12 point sources to 1e-10 (FP32 K-cycle, "
+                        "FP64 outer GCR); value = MG setup seconds of that form",
+            "lattice": C3_DIMS, "m0": m0, "m_prime": C3_MPRIME, "k": C3_K, "block": BLOCK, "setup_sweeps": N_SMOOTH,
+            "global_batch": C3_NRHS, "solve": SOLVE, "parallelism": "none (1 GPU)",
+        },
+        "fp32": fp32,
+    }
+    rec, H = c3_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP32, keep=True)
+    if not args.no_mass:
+        result["config"]["sigma_min"] = sigma_min(crk, lat, H, tag="32^4 ")
+        log("sigma_min", json.dumps(result["config"]["sigma_min"]))
+    H.close()
+    result["roofline"] = {
+        "kernel": "wilson_tile_kernel<FP32> (64 RHS, 32^4 in 4^4 blocks, MR setup sweep)",
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
+        "algorithmic_bytes_per_launch": alg, "avg_launch_s": launch,
+        "launch_timing": "HIP events on the setup stream around every smoother dslash launch (library-side)",
+    }
+    if not args.no_fp64:
+        fp64 = [c3_step(crk, lat, b, x, crk.FORM_FP64, crk.FORM_FP64)]
+        result["fp64_plain"] = form_summary(fp64, V, crk.FORM_FP64)
+        log("fp64_plain", json.dumps(result["fp64_plain"]))
+        f16 = [c3_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP16S)]
+        result["fp16s"] = form_summary(f16, V, crk.FORM_FP32)
+        log("fp16s", json.dumps(result["fp16s"]))
+        conv = [c3_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP32, m_prime=C3_K, k=C3_K)]
+        result["conventional_m24"] = form_summary(conv, V, crk.FORM_FP32, m_prime=C3_K)
+        log("conventional", json.dumps(result["conventional_m24"]))
+        p = result["fp64_plain"]
+        result["speedup_vs_fp64_plain"] = {
+            "fp32_time_to_solution": p["time_to_solution_s"] / fp32["time_to_solution_s"],
+            "fp16s_time_to_solution": p["time_to_solution_s"] / result["fp16s"]["time_to_solution_s"],
+            "fp32_setup": p["setup_s"] / fp32["setup_s"], "fp32_solve": p["solve_s"] / fp32["solve_s"]}
+    lat.close()
+    del b, x
+    torch.cuda.empty_cache()
+    if not args.no_sweep:
+        result["dslash_sweep"] = dslash_sweep(crk, extents=(32, 48))
+    if not args.no_c2:
+        result["c2_aniso_16x16x16x32"] = c2_summary(crk, args)
+    if not args.no_serve:
+        hier, _ = serve_hierarchies(crk, SERVE_LATTICES)
+        result["serving"] = [serve_run(crk, hier, rate, 10.0, n, seed_index=i)
+                             for i, (rate, n) in enumerate(((5.0, 30), (50.0, 30)))]
+        for H_ in hier:
+            H_.close()
+        log("serving", json.dumps(result["serving"]))
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(U, m0)
+    return result
+
+
+# ------------------------------------------------------------------ anisotropic 16^3x32
+
+def c2_lattice(crk):
+    m0 = tuned_m0("aniso_xi3.5_eps0.2")
+    U = synth.gauge_field(DIMS, EPS, N_APE, config=CONFIG)
+    lat = crk.Lattice(DIMS, m0, XI)
+    lat.load_gauge(U)
+    return lat, m0
+
+
+def c2_step(crk, lat, b, x, setup_form, solve_form, m_prime=M_PRIME, k=K, keep=False):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = crk.Hierarchy(lat, m_prime=[m_prime], k=[k], block=[BLOCK], n_smooth=[N_SMOOTH],
+                      setup_form=setup_form, seed=SEED)
+    t1 = time.perf_counter()
+    info = H.solve_dev(b, x, NRHS, form=solve_form, raise_on_noconv=False, **SOLVE)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    tim = H.timing(0)
+    rec = {"setup_s": t1 - t0, "setup_stages_s": {k_: tim[k_] for k_ in ("smoother", "svd", "galerkin")},
+           "solve_s": t2 - t1, "solves_per_s": NRHS / (t2 - t1),
+           "rhs_time_to_solution_p50_s": pct(info["rhs"]["seconds"], 50),
+           "rhs_time_to_solution_p99_s": pct(info["rhs"]["seconds"], 99),
+           "iters": info["iters"], "level_iters": info["level_iters"], "true_rel_resid": info["true_rel_resid"],
+           "converged": info["converged"], "smoother_dslash_launch_ms": 1e3 * tim["dslash_avg"],
+           "smoother_dslash_GBps": dslash_bytes(int(np.prod(DIMS)), m_prime, 0 if setup_form == 0 else 1)
+           / tim["dslash_avg"] / 1e9}
+    if keep:
+        return rec, H
+    H.close()
+    return rec
+
+
+def c2_summary(crk, args):
+    """The anisotropic 16^3x32 workload (rank-k FP32, plain FP64, conventional m' = k = 24),
+    one setup + 10-RHS solve each after one warm-up, and sigma_min(D) at its m0.
+    Its fields (1.2 GB of FP32 test vectors) largely fit the 256 MB last-level
+    cache only per vector chunk, so its dslash rate is reported as cache-assisted."""
+    import torch
+    dev = torch.device("cuda", 0)
+    V = int(np.prod(DIMS))
+    lat, m0 = c2_lattice(crk)
+    b = torch.from_numpy(synth.gaussian_rhs(NRHS, V, config=CONFIG).view(np.float64)).to(dev)
+    x = torch.empty_like(b)
+    c2_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP32)
+    out = {"workload": "16^3x32 xi=3.5 (eps=0.2, 3 APE), m'=48 -> k=24, 4^4 blocks, 60 MR sweeps, 10 Gaussian RHS "
+                       "to 1e-10; dslash rates partly served from the last-level cache", "m0": m0}
+    out["fp32"], H = c2_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP32, keep=True)
+    if not args.no_mass:
+        out["sigma_min"] = sigma_min(crk, lat, H, tag="16^3x32 ")
+    H.close()
+    out["fp64_plain"] = c2_step(crk, lat, b, x, crk.FORM_FP64, crk.FORM_FP64)
+    out["conventional_m24"] = c2_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP32, m_prime=K, k=K)
+    log("c2", json.dumps(out))
+    lat.close()
+    return out
+
+
+def workload_c2(crk, args):
+    out = c2_summary(crk, args)
+    f = out["fp32"]
+    return {"metric": METRIC, "value": f["setup_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": out["workload"], "m0": out["m0"], "lattice": DIMS, "parallelism": "none (1 GPU)"},
+            "c2": out}
+
+
+# ------------------------------------------------------------------ sigma_min(D) against m0
+
+def workload_mass(crk, args):
+    """sigma_min(D) at a list of masses on the 16^3x32 and 32^4 lattices (each mass
+    its own FP32 hierarchy), for placing m0 where sigma_min ~ 1e-3."""
+    import torch
+    rows = []
+    for name in args.mass_lattices.split(","):
+        if name == "c2":
+            lat, m0 = c2_lattice(crk)
+            dims, xi = DIMS, XI
+            U = None
+        else:
+            lat, U, m0 = c3_lattice(crk)
+            dims, xi = C3_DIMS, 1.0
+        masses = [float(v) for v in args.masses.split(",")] if args.masses else [m0]
+        for m in masses:
+            lat_m = crk.Lattice(dims, m, xi)
+            if U is None:
+                lat_m.load_gauge(synth.gauge_field(DIMS, EPS, N_APE, config=CONFIG))
+            else:
+                lat_m.load_gauge(U)
+            H = crk.Hierarchy(lat_m, m_prime=[M_PRIME if name == "c2" else C3_MPRIME], k=[K], block=[BLOCK],
+                              n_smooth=[N_SMOOTH], setup_form=crk.FORM_FP32, seed=SEED)
+            r = sigma_min(crk, lat_m, H, tag=f"{name} m0={m:+.5f} ")
+            r.update({"lattice": dims, "m0": m})
+            log("mass", json.dumps(r))
+            rows.append(r)
+            H.close()
+            lat_m.close()
+            torch.cuda.empty_cache()
+        lat.close()
+    return {"metric": "sigma_min(D) against m0", "value": None, "unit": "", "n_gpus": 1, "rows": rows,
+            "data": "synthetic", "config": {"workload": "16^3x32 xi=3.5 and 32^4 xi=1 synthetic ensembles"}}
 
 
 # ------------------------------------------------------------------ serving loop
@@ -138,13 +545,13 @@ def serve_hierarchies(crk, lattices, n_smooth=60):
     m0 = tuned_m0("iso_xi1_eps0.25")
     out = []
     for d in lattices:
-        U = synth.gauge_field(d, ISO["eps"], ISO["n_ape"], config=ISO["config"])
+        U = synth.gauge_field_device(d, ISO["eps"], ISO["n_ape"], config=ISO["config"])
         lat = crk.Lattice(d, m0, ISO["xi"])
         lat.load_gauge(U)
         del U
         t0 = time.perf_counter()
         H = crk.Hierarchy(lat, m_prime=[64], k=[24], block=[[4, 4, 4, 4]], n_smooth=[n_smooth],
-                          setup_form=crk.FORM_FP32, seed=0x2502030910)
+                          setup_form=crk.FORM_FP32, seed=SEED)
         log(f"serve: hierarchy {d} set up in {time.perf_counter() - t0:.2f} s")
         out.append(H)
     return out, m0
@@ -210,49 +617,6 @@ def workload_serve(crk, args):
     }
 
 
-# ------------------------------------------------------------------ isotropic 32^4
-
-def workload_iso32(crk, args):
-    import torch
-    dims = [32, 32, 32, 32]
-    V = int(np.prod(dims))
-    m0 = tuned_m0("iso_xi1_eps0.25")
-    U = synth.gauge_field(dims, ISO["eps"], ISO["n_ape"], config=ISO["config"])
-    lat = crk.Lattice(dims, m0, ISO["xi"])
-    lat.load_gauge(U)
-    del U
-    dev = torch.device("cuda", 0)
-    b = torch.from_numpy(synth.point_sources(V).view(np.float64)).to(dev)
-    x = torch.empty_like(b)
-    out = {}
-    for name, sform, form in (("fp64_plain", crk.FORM_FP64, crk.FORM_FP64), ("fp32", crk.FORM_FP32, crk.FORM_FP32),
-                              ("fp16s", crk.FORM_FP32, crk.FORM_FP16S)):
-        t0 = time.perf_counter()
-        H = crk.Hierarchy(lat, m_prime=[64], k=[24], block=[BLOCK], n_smooth=[N_SMOOTH], setup_form=sform,
-                          seed=0x2502030910)
-        t1 = time.perf_counter()
-        info = H.solve_dev(b, x, 12, form=form, raise_on_noconv=False, **SOLVE)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        tim = H.timing(0)
-        out[name] = {"setup_s": t1 - t0, "setup_stages_s": {k_: tim[k_] for k_ in ("smoother", "svd", "galerkin")},
-                     "solve_s": t2 - t1, "time_to_solution_s": t2 - t0, "iters": info["iters"],
-                     "level_iters": info["level_iters"], "true_rel_resid": info["true_rel_resid"],
-                     "converged": info["converged"],
-                     "dslash_GBps": dslash_bytes(V, 64, 0 if sform == crk.FORM_FP64 else 1) / tim["dslash_avg"] / 1e9}
-        log(name, json.dumps(out[name]))
-        H.close()
-    return {
-        "metric": "time-to-solution at 1e-10, 12 point sources: FP32 / FP16S forms vs plain FP64",
-        "value": out["fp32"]["solve_s"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
-        "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "32^4 xi=1 smoothed random SU(3) (eps=0.25, 3 APE), m0 = m_c + 0.01; m'=64 -> "
-                               "k=24, 4^4 blocks, 60 MR sweeps; 12 point sources; FP64 outer GCR to 1e-10",
-                   "m0": m0, "parallelism": "none (1 GPU)"},
-        "forms": out,
-    }
-
-
 # ------------------------------------------------------------------ three-level volume sweep
 
 # (name, m' per step, k per step, sweeps per step, level-2 setup from the coarse test vectors)
@@ -285,7 +649,7 @@ def workload_volume(crk, args):
             try:
                 t0 = time.perf_counter()
                 H = crk.Hierarchy(lat, m_prime=mp, k=k, block=[BLOCK, [2, 2, 2, 2]], n_smooth=ns,
-                                  setup_form=crk.FORM_FP32, seed=0x2502030910, coarse_init=ci)
+                                  setup_form=crk.FORM_FP32, seed=SEED, coarse_init=ci)
                 t1 = time.perf_counter()
                 info = H.solve_dev(b, x, 1, form=crk.FORM_FP32, raise_on_noconv=False, **SOLVE)
                 torch.cuda.synchronize()
@@ -338,7 +702,7 @@ def workload_params(crk, args):
     b = torch.from_numpy(synth.gaussian_rhs(NRHS, V, config=CONFIG).view(np.float64)).to(dev)
     x = torch.empty_like(b)
     H = crk.Hierarchy(lat, m_prime=[M_PRIME], k=[K], block=[BLOCK], n_smooth=[N_SMOOTH],
-                      setup_form=crk.FORM_FP32, seed=0x2502030910)   # warm-up of every kernel
+                      setup_form=crk.FORM_FP32, seed=SEED)   # warm-up of every kernel
     H.solve_dev(b, x, NRHS, form=crk.FORM_FP32, raise_on_noconv=False, **SOLVE)
     H.close()
     rows = []
@@ -347,7 +711,7 @@ def workload_params(crk, args):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             H = crk.Hierarchy(lat, m_prime=[pt["m_prime"]], k=[pt["k"]], block=[BLOCK], n_smooth=[pt["n_smooth"]],
-                              setup_form=crk.FORM_FP32, seed=0x2502030910)
+                              setup_form=crk.FORM_FP32, seed=SEED)
             t1 = time.perf_counter()
             info = H.solve_dev(b, x, NRHS, form=crk.FORM_FP32, raise_on_noconv=False, **SOLVE)
             torch.cuda.synchronize()
@@ -434,9 +798,9 @@ def workload_kernels(crk, args):
         torch.cuda.empty_cache()
         big = ext == 16  # the 16^3x32 hierarchy is the benchmark's own (2k = 48) for the coarse sweep
         H = crk.Hierarchy(lat, m_prime=[48 if big else 8], k=[24 if big else 8], block=[BLOCK],
-                          n_smooth=[10 if big else 0], setup_form=crk.FORM_FP32, seed=0x2502030910)
-        for form in (0, 1, 2):
-            for nrhs in (1, 12, 64):
+                          n_smooth=[10 if big else 0], setup_form=crk.FORM_FP32, seed=SEED)
+        for form in (int(f) for f in args.kernel_forms.split(",")):
+            for nrhs in (int(c) for c in args.kernel_counts.split(",")):
                 nb = H.field_bytes(0, form, nrhs)
                 free, _ = torch.cuda.mem_get_info()
                 row = {"lattice": dims, "form": FORM_NAMES[form], "nrhs": nrhs}
@@ -453,7 +817,7 @@ def workload_kernels(crk, args):
                 rows.append(row)
                 del a, b
                 torch.cuda.empty_cache()
-        if big:
+        if big and not args.no_coarse:
             Vc, N = H.volume(1), H.ncomp[1]
             for form in (0, 1, 2):
                 for nrhs in (1, 12, 32, 48):
@@ -471,8 +835,21 @@ def workload_kernels(crk, args):
                     coarse.append(row)
         H.close()
         lat.close()
+    copy = None
+    if args.copy_calibration:
+        # a plain 1 GiB device-to-device copy: reads and writes 2^30 bytes, the
+        # reference for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        copy = {"bytes_read": 1 << 30, "bytes_written": 1 << 30, "launches": 3}
+        del src, dst
     return {
         "metric": "fine operator GB/s (algorithmic) and coarse MFMA TFLOP/s vs volume, form and RHS count",
+        "copy_calibration": copy,
         "value": None, "unit": "GB/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f64/f32/f16s",
         "data": "synthetic",
         "config": {"workload": "tile dslash on 4^4 block-major layouts of 16^3x32, 32^4, 48^3x96 (xi=1, eps=0.25 "
@@ -485,130 +862,31 @@ def workload_kernels(crk, args):
     }
 
 
-# ------------------------------------------------------------------ default: anisotropic 16^3x32
-
-def workload_aniso16(crk, args):
-    import torch
-    dev = torch.device("cuda", 0)
-    V = int(np.prod(DIMS))
-    m0 = tuned_m0("aniso_xi3.5_eps0.2")
-    U = synth.gauge_field(DIMS, EPS, N_APE, config=CONFIG)
-    lat = crk.Lattice(DIMS, m0, XI)
-    lat.load_gauge(U)
-    b_host = synth.gaussian_rhs(NRHS, V, config=CONFIG)
-    b = torch.from_numpy(b_host.view(np.float64)).to(dev)
-    x = torch.empty_like(b)
-    torch.cuda.synchronize()
-
-    def step(setup_form, solve_form, m_prime=M_PRIME, k=K):
-        t0 = time.perf_counter()
-        H = crk.Hierarchy(lat, m_prime=[m_prime], k=[k], block=[BLOCK], n_smooth=[N_SMOOTH],
-                          setup_form=setup_form, seed=0x2502030910)
-        t1 = time.perf_counter()
-        info = H.solve_dev(b, x, NRHS, form=solve_form, raise_on_noconv=False, **SOLVE)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        tim = H.timing(0)
-        H.close()
-        return t1 - t0, t2 - t1, info, tim
-
-    for _ in range(args.warmup):
-        step(crk.FORM_FP32, crk.FORM_FP32)
-    torch.cuda.synchronize()
-    setups, solves, infos, tims = [], [], [], []
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        s, v, info, tim = step(crk.FORM_FP32, crk.FORM_FP32)
-        setups.append(s)
-        solves.append(v)
-        infos.append(info)
-        tims.append(tim)
-        log(f"step: setup {s:.4f} s, solve {v:.4f} s, iters {info['iters']}")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-
-    dslash_avg = float(np.mean([t["dslash_avg"] for t in tims]))
-    alg = dslash_bytes(V, M_PRIME, 1)
-    achieved = alg / dslash_avg / 1e9
-    result = {
-        "metric": METRIC,
-        "value": float(np.mean(setups)),
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * total / args.steps,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {
-            "workload": "16^3x32 xi=3.5 smoothed random SU(3) (eps=0.2, 3 APE), m0 = m_c + 0.01 "
-                        "(oracle-located critical mass); chiral rank-k setup m'=48 -> k=24, 4^4 blocks, "
-                        "60 FP32 MR sweeps, FP64 SVD+Galerkin; two-level MG-GCR solve of 10 RHS to 1e-10 "
-                        "(FP32 K-cycle, FP64 outer GCR)",
-            "m0": m0, "global_batch": NRHS, "lattice": DIMS, "parallelism": "none (1 GPU)",
-        },
-        "setup_s": float(np.mean(setups)),
-        "setup_device_s": float(np.mean([t["total"] for t in tims])),
-        "setup_stages_s": {k_: float(np.mean([t[k_] for t in tims])) for k_ in ("smoother", "svd", "galerkin")},
-        "dslash_GBps": achieved,
-        "dslash_launch_ms": 1e3 * dslash_avg,
-        "solve_s": float(np.mean(solves)),
-        "solves_per_s": NRHS / float(np.mean(solves)),
-        "solve_p50_s": float(np.percentile(solves, 50)),
-        "solve_p99_s": float(np.percentile(solves, 99)),
-        "solve_iters": infos[-1]["iters"],
-        "solve_level_iters": infos[-1]["level_iters"],
-        "true_rel_resid": max(i["true_rel_resid"] for i in infos),
-        "converged": all(i["converged"] for i in infos),
-        "roofline": {
-            "kernel": "wilson_tile_kernel<FP32> (48 RHS, 16^3x32 in 4^4 blocks, MR setup sweep)",
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
-            "algorithmic_bytes_per_launch": alg,
-        },
-    }
-    if not args.no_fp64:
-        s, v, info, tim = step(crk.FORM_FP64, crk.FORM_FP64)
-        result["fp64_plain"] = {"setup_s": s, "solve_s": v, "solves_per_s": NRHS / v, "iters": info["iters"],
-                                "level_iters": info["level_iters"], "true_rel_resid": info["true_rel_resid"],
-                                "converged": info["converged"],
-                                "dslash_GBps": dslash_bytes(V, M_PRIME, 0) / tim["dslash_avg"] / 1e9}
-        log("fp64_plain", json.dumps(result["fp64_plain"]))
-        s, v, info, tim = step(crk.FORM_FP32, crk.FORM_FP32, m_prime=K, k=K)
-        result["conventional_m24"] = {"setup_s": s, "solve_s": v, "iters": info["iters"],
-                                      "level_iters": info["level_iters"], "true_rel_resid": info["true_rel_resid"],
-                                      "converged": info["converged"]}
-        log("conventional", json.dumps(result["conventional_m24"]))
-    lat.close()
-    if not args.no_serve:
-        hier, _ = serve_hierarchies(crk, SERVE_LATTICES[:1])
-        result["serving_16x32"] = serve_run(crk, hier, 2.0, 10.0, 40)
-        for H in hier:
-            H.close()
-        log("serving", json.dumps(result["serving_16x32"]))
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(U, m0, V)
-    return result
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="aniso16",
-                    choices=["aniso16", "iso32", "volume", "serve", "kernels", "params"])
+    ap.add_argument("--workload", default="c3",
+                    choices=["c3", "c2", "volume", "serve", "kernels", "params", "mass"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="c3: skip the FP64 / FP16S / conventional forms")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="c3: skip the dslash sweep over volumes")
+    ap.add_argument("--no-c2", action="store_true", help="c3: skip the 16^3x32 sub-result")
+    ap.add_argument("--no-mass", action="store_true", help="skip the sigma_min(D) measurement")
     ap.add_argument("--volumes", default=None,
                     help="spatial extents to run: volume sweep 24,32,48 (default); kernel sweep 16,32,48 (default)")
-    ap.add_argument("--serve-rates", default="0.25,0.5,1,2,5")
-    ap.add_argument("--serve-seconds", type=float, default=40.0)
-    ap.add_argument("--serve-max-requests", type=int, default=80)
+    ap.add_argument("--serve-rates", default="5,10,20,50,100,200")
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-max-requests", type=int, default=60)
+    ap.add_argument("--kernel-forms", default="0,1,2", help="--workload kernels: forms of the fine operator")
+    ap.add_argument("--kernel-counts", default="1,12,64", help="--workload kernels: RHS counts of the fine operator")
+    ap.add_argument("--no-coarse", action="store_true", help="--workload kernels: skip the coarse operator")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="--workload kernels: also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--mass-lattices", default="c2,c3")
+    ap.add_argument("--masses", default=None, help="comma-separated m0 values for --workload mass")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU domain "
@@ -617,8 +895,8 @@ def main():
         sys.exit(2)
 
     import paper_2502_03091_amd as crk
-    fn = {"aniso16": workload_aniso16, "iso32": workload_iso32, "volume": workload_volume,
-          "serve": workload_serve, "kernels": workload_kernels, "params": workload_params}[args.workload]
+    fn = {"c3": workload_c3, "c2": workload_c2, "volume": workload_volume, "serve": workload_serve,
+          "kernels": workload_kernels, "params": workload_params, "mass": workload_mass}[args.workload]
     if args.volumes is None:
         args.volumes = "16,32,48" if args.workload == "kernels" else "24,32,48"
     print(json.dumps(fn(crk, args)), flush=True)
