@@ -11,6 +11,8 @@ weight w_mu = (1, 1, 1, 1/xi) on the temporal hops and in the Wilson diagonal:
 With xi = 1 the diagonal is m0 + 4.  In the free field (U = 1) a plane wave
 e^{ipx} chi is mapped to e^{ipx} D(p) chi with
 D(p) = m0 + sum_mu w_mu (1 - cos p_mu) + i sum_mu w_mu gamma_mu sin p_mu.
+With c_sw != 0 the site term becomes (m0 + sum_mu w_mu) 1 + C(x), C the clover
+term of oracle.clover (the Wilson-clover operator of the paper's ensembles).
 
 Vectors are [V, 12, C] (component index 3*spin + colour).
 """
@@ -30,7 +32,7 @@ def weights(xi):
 class WilsonOp:
     """D in hopping form; same interface as StencilOp (diag_apply / hop / apply)."""
 
-    def __init__(self, U, dims, m0, xi=1.0):
+    def __init__(self, U, dims, m0, xi=1.0, c_sw=0.0):
         self.dims = [int(d) for d in dims]
         self.U = np.asarray(U, dtype=np.complex128)
         self.V = lattice.volume(self.dims)
@@ -44,13 +46,22 @@ class WilsonOp:
         self.Ubwd = [
             np.conj(np.swapaxes(self.U[self.nbr[:, 2 * mu + 1], mu], -1, -2)) for mu in range(4)
         ]
+        self.c_sw = float(c_sw)
+        self.site = None  # [V, 12, 12] site term when the clover term is on
+        if self.c_sw != 0.0:
+            from .clover import clover_term
+            self.site = self.diag * np.eye(12, dtype=np.complex128)[None] + clover_term(self.U, self.dims, self.c_sw,
+                                                                                        self.xi)
 
     @property
     def diag(self):
         return self.m0 + self.w.sum()
 
     def diag_apply(self, v, sites=None):
-        return self.diag * v
+        if self.site is None:
+            return self.diag * v
+        X = self.site if sites is None else self.site[sites]
+        return X @ v
 
     def hop(self, mu, sign, v_nb, sites=None):
         """-1/2 w_mu (1 -+ gamma_mu) (x) U  applied to v_nb[x] = v(x + sign*mu)."""
@@ -79,7 +90,7 @@ class WilsonOp:
     def apply_at(self, v, sites):
         """(D v)(x) for the listed sites only (v given on the whole lattice)."""
         sites = np.asarray(sites, dtype=np.int64)
-        out = self.diag * v[sites]
+        out = self.diag_apply(v[sites], sites=sites)
         for mu in range(4):
             out = out + self.hop(mu, +1, v[self.nbr[sites, 2 * mu]], sites=sites)
             out = out + self.hop(mu, -1, v[self.nbr[sites, 2 * mu + 1]], sites=sites)
@@ -91,7 +102,10 @@ class WilsonOp:
     def to_stencil(self):
         """Explicit StencilOp with X = diag * 1, Y_{+-mu}(x) = -w/2 (1 -+ gamma_mu) (x) link."""
         V = self.V
-        X = np.broadcast_to(self.diag * np.eye(12, dtype=np.complex128), (V, 12, 12)).copy()
+        if self.site is None:
+            X = np.broadcast_to(self.diag * np.eye(12, dtype=np.complex128), (V, 12, 12)).copy()
+        else:
+            X = self.site.copy()
         Yp = np.empty((4, V, 12, 12), dtype=np.complex128)
         Ym = np.empty((4, V, 12, 12), dtype=np.complex128)
         for mu in range(4):
