@@ -83,6 +83,20 @@ int crk_device_info(char* name, int32_t n, int64_t* hbm_bytes, int32_t* n_cu);
  * CRK_ENOMEM if the device storage does not fit. */
 int crk_create_lattice(const int32_t dims[4], double m0, double xi, crk_lattice_t* out);
 
+/* Turn the Wilson-clover operator on (c_sw != 0) or off (c_sw = 0).  The
+ * paper's ensembles are clover actions (Sec. 4, both ensembles); its site term
+ * becomes (m0 + sum_mu w_mu) 1 + C(x) with
+ *   C(x) = -(c_sw/2) sum_{mu<nu} w_mu w_nu sigma_{mu nu} (x) F_{mu nu}(x),
+ *   sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu],
+ *   F_{mu nu}(x) = [(Q - Q^dag) - tr(Q - Q^dag)/3] / (8i),
+ * Q_{mu nu}(x) the four plaquettes of the (mu, nu) plane at x.  C(x) is two
+ * Hermitian 6 x 6 blocks per site (one per chirality of Eq. (2)), so
+ * gamma5 D gamma5 = D^dag still holds.  May be called before or after
+ * crk_load_gauge (the blocks are computed on the device from the FP64 links
+ * when both are set).  A hierarchy keeps the clover blocks of its lattice at
+ * the time of crk_mg_setup.  CRK_EINVAL for a NULL handle or a non-finite c_sw. */
+int crk_lattice_set_clover(crk_lattice_t lat, double c_sw);
+
 /* Upload the SU(3) gauge links U_mu(x) that define D (Sec. 2): host
  * complex128 [V][4][3][3] (entry [x][mu][a][b] = U_mu(x)[a][b]),
  * n_doubles = 2*V*36.  Copied before the call returns and converted on the

@@ -145,6 +145,7 @@ def _load():
         "crk_device_info": (i32, [C.c_char_p, i32, C.POINTER(i64), C.POINTER(i32)]),
         "crk_create_lattice": (i32, [C.POINTER(i32), dbl, dbl, C.POINTER(vp)]),
         "crk_load_gauge": (i32, [vp, vp, i64]),
+        "crk_lattice_set_clover": (i32, [vp, dbl]),
         "crk_dirac_apply": (i32, [vp, i32, vp, vp, i32]),
         "crk_dirac_apply_dev": (i32, [vp, i32, vp, vp, i32, vp]),
         "crk_dirac_apply_noalloc": (i32, [vp, i32, vp, vp, i32]),
@@ -196,6 +197,7 @@ def exported_symbols():
     """Names the binding expects the shared library to export."""
     return [
         "crk_version", "crk_last_error", "crk_device_info", "crk_create_lattice", "crk_load_gauge",
+        "crk_lattice_set_clover",
         "crk_dirac_apply", "crk_dirac_apply_dev", "crk_dirac_apply_noalloc", "crk_dirac_apply_noalloc_max_bytes",
         "crk_field_bytes", "crk_field_import_dev",
         "crk_field_export_dev", "crk_lattice_get_map", "crk_lattice_destroy", "crk_mg_params_default",
@@ -243,16 +245,23 @@ def _as_c128(a, shape=None):
 
 
 class Lattice:
-    """Periodic 4-D lattice with Wilson mass m0 and temporal anisotropy xi."""
+    """Periodic 4-D lattice with Wilson mass m0, temporal anisotropy xi and
+    clover coefficient c_sw (0: the plain Wilson operator)."""
 
-    def __init__(self, dims, m0, xi=1.0):
+    def __init__(self, dims, m0, xi=1.0, c_sw=0.0):
         self.dims = [int(d) for d in dims]
         self.V = int(np.prod(self.dims))
-        self.m0, self.xi = float(m0), float(xi)
+        self.m0, self.xi, self.c_sw = float(m0), float(xi), float(c_sw)
         h = C.c_void_p()
         d = (C.c_int32 * 4)(*self.dims)
         _check(_load().crk_create_lattice(d, self.m0, self.xi, C.byref(h)))
         self._h = h
+        if self.c_sw != 0.0:
+            self.set_clover(self.c_sw)
+
+    def set_clover(self, c_sw):
+        self.c_sw = float(c_sw)
+        _check(_load().crk_lattice_set_clover(self.handle, self.c_sw))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "libcrk.so")
 
 SOURCES = [
     "geometry.hip",
+    "clover.hip",
     "dslash.hip",
     "blas.hip",
     "svd.hip",

@@ -77,6 +77,14 @@ int crk_create_lattice(const int32_t dims[4], double m0, double xi, crk_lattice_
   });
 }
 
+int crk_lattice_set_clover(crk_lattice_t lat, double c_sw) {
+  return guarded([&] {
+    CRK_REQUIRE(lat && lat->L, "lattice handle is NULL");
+    lattice_set_clover(lat->L, c_sw);
+    return CRK_OK;
+  });
+}
+
 int crk_load_gauge(crk_lattice_t lat, const double* U, int64_t n_doubles) {
   return guarded([&] {
     CRK_REQUIRE(lat && lat->L, "lattice handle is NULL");
@@ -103,6 +111,7 @@ static void dirac_native(Lattice* L, int form, const void* in, void* out, int nr
   L->hw(a.hw);
   a.partial = nullptr;
   a.rhs_per_thread = 4;
+  a.clover = L->c_sw != 0.0 ? L->clover[form].p : nullptr;
   wilson_apply(a, st);
 }
 

@@ -386,7 +386,7 @@ int64_t crk_mg_footprint_bytes(crk_mg_t mg, int32_t nrhs, int32_t form) {
   Hierarchy* H = mg->H;
   size_t b = 0;
   b += H->fine_geo.pos.bytes + H->fine_geo.inv.bytes + H->fine_geo.nbr.bytes;
-  for (int f = 0; f < 3; ++f) b += H->fine_gauge[f].bytes;
+  for (int f = 0; f < 3; ++f) b += H->fine_gauge[f].bytes + H->fine_clover[f].bytes;
   for (auto& c : H->coarse) {
     b += c.geo.pos.bytes + c.geo.inv.bytes + c.geo.nbr.bytes;
     for (int f = 0; f < 3; ++f) b += c.links[f].bytes;

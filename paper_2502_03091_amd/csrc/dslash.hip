@@ -93,6 +93,30 @@ __device__ __forceinline__ void link_mul(const C* u, const C* h, C* g) {
   }
 }
 
+// Clover site term (Wilson-clover operator): acc = sign * X(s) psi with X the
+// two 6 x 6 chirality blocks of site s (diagonal included), stored
+// site-vectorised with 72 components, entry 36*alpha + 6*r + c.
+template <class S, class C, class T>
+__device__ __forceinline__ void clover_site(const S* __restrict__ cl, int64_t Vp, int64_t s, const C (&psi)[12],
+                                            C (&acc)[12], T sign) {
+  const S* p = cl + aidx(0, 0, s, Vp, 72);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      C t = czero<C>();
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const S x = p[(36 * a + 6 * r + c) * kVL];
+        cfma(t, mk<C>(x.x, x.y), psi[6 * a + c]);
+      }
+      acc[6 * a + r] = cscale(t, sign);
+      // one row's six loads at a time: the kernels that call this already hold
+      // their links in registers, and hoisting all 72 loads would spill them
+      asm volatile("" ::: "memory");
+    }
+}
+
 template <int FORM, int R, int MU, int SIGN>
 __device__ __forceinline__ void hop(const FineView<FORM>& in, const GaugeView<FORM>& U, const int* __restrict__ nbr,
                                     int64_t V, int64_t s, int r0, int nrhs,
@@ -113,12 +137,13 @@ __device__ __forceinline__ void hop(const FineView<FORM>& in, const GaugeView<FO
   }
 }
 
-template <int FORM, int R>
+template <int FORM, int R, bool CL>
 __global__ __launch_bounds__(256) void wilson_kernel(FineView<FORM> in, FineView<FORM> out, GaugeView<FORM> U,
                                                      const int* __restrict__ nbr, int64_t V, int nrhs, int ngroups,
                                                      typename Prec<FORM>::real diag, float4 hw_f, double4 hw_d,
                                                      double* __restrict__ partial, int64_t nsb, int order,
-                                                     int swz) {
+                                                     int swz, const void* __restrict__ clv,
+                                                     typename Prec<FORM>::real csign) {
   using C = typename Prec<FORM>::cx;
   using T = typename Prec<FORM>::real;
   const uint32_t L = swz ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -141,8 +166,12 @@ __global__ __launch_bounds__(256) void wilson_kernel(FineView<FORM> in, FineView
       if (r0 + r < nrhs) {
         C psi[12];
         in.load(r0 + r, s, psi);
+        if constexpr (CL) {
+          clover_site(static_cast<const typename Prec<FORM>::cx*>(clv), in.Vp, s, psi, acc[r], csign);
+        } else {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) acc[r][c] = cscale(psi[c], diag);
+          for (int c = 0; c < 12; ++c) acc[r][c] = cscale(psi[c], diag);
+        }
       } else {
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[r][c] = czero<C>();
@@ -220,11 +249,13 @@ __device__ __forceinline__ void hop_reg(const FineView<FORM>& in, int64_t r, int
   accumulate<MU, SIGN>(acc, g, coef);
 }
 
-template <int FORM>
+template <int FORM, bool CL>
 __global__ __launch_bounds__(256) void wilson_rhsloop_kernel(FineView<FORM> in, FineView<FORM> out, GaugeView<FORM> U,
                                                              const int* __restrict__ nbr, int64_t V, int nrhs,
                                                              typename Prec<FORM>::real diag, float4 hw,
-                                                             double* __restrict__ partial, int swz) {
+                                                             double* __restrict__ partial, int swz,
+                                                             const void* __restrict__ clv,
+                                                             typename Prec<FORM>::real csign) {
   using C = typename Prec<FORM>::cx;
   using T = typename Prec<FORM>::real;
   using S = typename GaugeView<FORM>::S;
@@ -249,8 +280,12 @@ __global__ __launch_bounds__(256) void wilson_rhsloop_kernel(FineView<FORM> in, 
     {
       C psi[12];
       in.load(r, sl, psi);
+      if constexpr (CL) {
+        clover_site(static_cast<const typename Prec<FORM>::cx*>(clv), in.Vp, sl, psi, acc, csign);
+      } else {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) acc[c] = cscale(psi[c], diag);
+        for (int c = 0; c < 12; ++c) acc[c] = cscale(psi[c], diag);
+      }
     }
     hop_reg<FORM, 0, +1>(in, r, y[0], u[0], acc, hw0);
     hop_reg<FORM, 0, -1>(in, r, y[1], u[1], acc, hw0);
@@ -297,8 +332,14 @@ void launch_wilson_rhsloop(const WilsonArgs& a, hipStream_t st) {
   FineView<FORM> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
   GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), pad_sites(a.V)};
   const float4 hw = make_float4(float(a.hw[0]), float(a.hw[1]), float(a.hw[2]), float(a.hw[3]));
-  hipLaunchKernelGGL((wilson_rhsloop_kernel<FORM>), dim3(unsigned(nsb)), dim3(256), 0, st, in, out, U, a.nbr, a.V,
-                     a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle);
+  if (a.clover)
+    hipLaunchKernelGGL((wilson_rhsloop_kernel<FORM, true>), dim3(unsigned(nsb)), dim3(256), 0, st, in, out, U, a.nbr,
+                       a.V, a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle, a.clover,
+                       typename Prec<FORM>::real(a.clover_sign));
+  else
+    hipLaunchKernelGGL((wilson_rhsloop_kernel<FORM, false>), dim3(unsigned(nsb)), dim3(256), 0, st, in, out, U, a.nbr,
+                       a.V, a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle, a.clover,
+                       typename Prec<FORM>::real(a.clover_sign));
   CRK_LAUNCH_CHECK();
 }
 
@@ -341,11 +382,13 @@ __device__ __forceinline__ void hop_pair(const FineView<FORM>& in, int r, int64_
 // result and hands the other nine to their owners through LDS; after a barrier
 // it adds the diagonal term and the four partials of spin mu in a fixed order
 // and stores them.  A second barrier frees the LDS slots for the next RHS.
-template <int FORM>
+template <int FORM, bool CL>
 __global__ __launch_bounds__(256) void wilson_dir_kernel(FineView<FORM> in, FineView<FORM> out, GaugeView<FORM> U,
                                                          const int* __restrict__ nbr, int64_t V, int nrhs,
                                                          typename Prec<FORM>::real diag, double4 hw_d,
-                                                         double* __restrict__ partial, int swz) {
+                                                         double* __restrict__ partial, int swz,
+                                                         const void* __restrict__ clv,
+                                                         typename Prec<FORM>::real csign) {
   using C = typename Prec<FORM>::cx;
   using T = typename Prec<FORM>::real;
   using S = typename Prec<FORM>::store;
@@ -383,10 +426,29 @@ __global__ __launch_bounds__(256) void wilson_dir_kernel(FineView<FORM> in, Fine
     const S* pin = in.data + aidx(r, 3 * mu, sl, in.Vp, 12);
     S* pout = out.data + aidx(r, 3 * mu, sl, out.Vp, 12);
     double v0 = 0, v1 = 0, v2 = 0;
+    C site[3];
+    if constexpr (CL) {
+      // rows 3 (mu % 2) + c of the chirality-(mu / 2) clover block times that chirality's six components
+      const int al = mu >> 1, r0 = 3 * (mu & 1);
+      const C* pc = in.data + aidx(r, 6 * al, sl, in.Vp, 12);
+      const C* X = static_cast<const C*>(clv) + aidx(0, 36 * al + 6 * r0, sl, in.Vp, 72);
+      C ps[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) ps[j] = pc[j * kVL];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        C t = czero<C>();
+#pragma unroll
+        for (int j = 0; j < 6; ++j) cfma(t, X[(6 * c + j) * kVL], ps[j]);
+        site[c] = cscale(t, csign);
+      }
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const C x = pin[c * kVL];
-      C q = cscale(x, diag);
+      C q;
+      if constexpr (CL) q = site[c];
+      else q = cscale(x, diag);
 #pragma unroll
       for (int src = 0; src < 4; ++src)
         q = q + (src == mu ? mine[c] : xch[3 * src + (mu < src ? mu : mu - 1)][c][lane]);
@@ -421,8 +483,14 @@ void launch_wilson_dir(const WilsonArgs& a, hipStream_t st) {
   FineView<FORM> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
   GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), pad_sites(a.V)};
   const double4 hw = make_double4(a.hw[0], a.hw[1], a.hw[2], a.hw[3]);
-  hipLaunchKernelGGL((wilson_dir_kernel<FORM>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U, a.nbr, a.V,
-                     a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle);
+  if (a.clover)
+    hipLaunchKernelGGL((wilson_dir_kernel<FORM, true>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U, a.nbr,
+                       a.V, a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle, a.clover,
+                       typename Prec<FORM>::real(a.clover_sign));
+  else
+    hipLaunchKernelGGL((wilson_dir_kernel<FORM, false>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U, a.nbr,
+                       a.V, a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle, a.clover,
+                       typename Prec<FORM>::real(a.clover_sign));
   CRK_LAUNCH_CHECK();
 }
 
@@ -436,9 +504,14 @@ void launch_wilson(const WilsonArgs& a, hipStream_t st) {
   GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), pad_sites(a.V)};
   float4 hwf = make_float4(float(a.hw[0]), float(a.hw[1]), float(a.hw[2]), float(a.hw[3]));
   double4 hwd = make_double4(a.hw[0], a.hw[1], a.hw[2], a.hw[3]);
-  hipLaunchKernelGGL((wilson_kernel<FORM, R>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U, a.nbr, a.V,
-                     a.nrhs, ngroups, typename Prec<FORM>::real(a.diag), hwf, hwd, a.partial, nsb, a.order,
-                     a.swizzle);
+  if (a.clover)
+    hipLaunchKernelGGL((wilson_kernel<FORM, R, true>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U, a.nbr, a.V,
+                       a.nrhs, ngroups, typename Prec<FORM>::real(a.diag), hwf, hwd, a.partial, nsb, a.order,
+                       a.swizzle, a.clover, typename Prec<FORM>::real(a.clover_sign));
+  else
+    hipLaunchKernelGGL((wilson_kernel<FORM, R, false>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U, a.nbr,
+                       a.V, a.nrhs, ngroups, typename Prec<FORM>::real(a.diag), hwf, hwd, a.partial, nsb, a.order,
+                       a.swizzle, a.clover, typename Prec<FORM>::real(a.clover_sign));
   CRK_LAUNCH_CHECK();
 }
 
@@ -497,12 +570,14 @@ __device__ __forceinline__ void tile_hop(const float2 (*sp)[kTileSlots], int slo
   accumulate<MU, SIGN>(acc, g, coef);
 }
 
-template <int FORM>  // FP32, or FP16S storage (half spinors with a per-site scale, half links) in FP32 arithmetic
-__global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<FORM> in, FineView<FORM> out,
+// With the clover term the site blocks add to the live registers: that variant
+// runs one workgroup per CU (up to 512 registers) instead of spilling.
+template <int FORM, bool CL>  // FP32, or FP16S storage (half spinors with a per-site scale, half links) in FP32 arithmetic
+__global__ __launch_bounds__(kTile, CL ? 1 : 2) void wilson_tile_kernel(FineView<FORM> in, FineView<FORM> out,
                                                                GaugeView<FORM> U,
                                                                const int* __restrict__ nbr, int64_t V, int nrhs,
                                                                float diag, float4 hw, double* __restrict__ partial,
-                                                               int swz) {
+                                                               int swz, const float2* __restrict__ clv, float csign) {
   __shared__ float2 sp[12][kTileSlots];  // [component][slot], 72 KiB
   const int64_t blk = swz ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
   const int l = threadIdx.x, lane = l & 63, wid = l >> 6;
@@ -546,8 +621,15 @@ __global__ __launch_bounds__(kTile, 2) void wilson_tile_kernel(FineView<FORM> in
     }
     in.load(r + 1 < nrhs ? r + 1 : r, s, own);  // next RHS, in flight during the hops
     float2 acc[12];
+    if constexpr (CL) {
+      float2 ps[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = cscale(sp[c][l], diag);
+      for (int c = 0; c < 12; ++c) ps[c] = sp[c][l];
+      clover_site(clv, in.Vp, s, ps, acc, csign);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = cscale(sp[c][l], diag);
+    }
     tile_hop<0, +1>(sp, slot[0], u[0], acc, hw.x);
     tile_hop<0, -1>(sp, slot[1], u[1], acc, hw.x);
     tile_hop<1, +1>(sp, slot[2], u[2], acc, hw.y);
@@ -609,8 +691,14 @@ void launch_wilson_tile(const WilsonArgs& a, hipStream_t st) {
   FineView<FORM> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
   GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), pad_sites(a.V)};
   const float4 hw = make_float4(float(a.hw[0]), float(a.hw[1]), float(a.hw[2]), float(a.hw[3]));
-  hipLaunchKernelGGL(wilson_tile_kernel<FORM>, dim3(unsigned(nblk)), dim3(kTile), 0, st, in, out, U, a.nbr, a.V,
-                     a.nrhs, float(a.diag), hw, a.partial, a.swizzle);
+  if (a.clover)
+    hipLaunchKernelGGL((wilson_tile_kernel<FORM, true>), dim3(unsigned(nblk)), dim3(kTile), 0, st, in, out, U, a.nbr,
+                       a.V, a.nrhs, float(a.diag), hw, a.partial, a.swizzle, static_cast<const float2*>(a.clover),
+                       float(a.clover_sign));
+  else
+    hipLaunchKernelGGL((wilson_tile_kernel<FORM, false>), dim3(unsigned(nblk)), dim3(kTile), 0, st, in, out, U, a.nbr,
+                       a.V, a.nrhs, float(a.diag), hw, a.partial, a.swizzle, static_cast<const float2*>(a.clover),
+                       float(a.clover_sign));
   CRK_LAUNCH_CHECK();
 }
 }  // namespace

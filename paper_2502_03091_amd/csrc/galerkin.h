@@ -14,6 +14,8 @@ struct GalerkinArgs {
   int nr;                // 6*nb
   int k;
   double diag;           // m0 + sum w
+  const double2* clover; // Wilson-clover: FP64 site blocks diag 1 + C(x), [72][V] site-vectorised at the
+                         // fine device positions (NULL: plain Wilson, site term diag)
   double hw[4];          // -w_mu/2
   int64_t ncoarse;       // number of blocks (coarse sites)
   const int* pos_c;      // coarse device position of lexicographic coarse site (NULL = identity)

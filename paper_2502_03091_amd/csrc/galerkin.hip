@@ -4,6 +4,7 @@
 // With P(x) the 12 x 2k block of P at fine site x and H_{+-mu}(x) the Wilson hops
 // -w_mu/2 (1 -+ gamma_mu) (x) U:
 //   X(j)       = sum_{x in block j} P(x)^dag [ (m0 + sum w) P(x) + sum_{in-block hops} H P(x+-mu) ]
+//                (with the clover term the site term is the block diagonal diag 1 + C(x))
 //   Y_{+mu}(j) = sum_{x in block j, x+mu outside} P(x)^dag H_{+mu}(x) P(x+mu)
 //   Y_{-mu}(j) = sigma3 Y_{+mu}(j-mu)^dag sigma3          (gamma5-hermiticity of D)
 // One workgroup per (coarse site, part) with part 0 = X and parts 1..4 = Y_{+mu}.
@@ -187,14 +188,31 @@ __global__ __launch_bounds__(kT) void galerkin_kernel(GalerkinArgs A) {
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp) t[a][sp] = make_double2(0, 0);
       if (part == 0) {
-        // site term: (m0 + sum w) P(x)
+        // site term: (m0 + sum w) P(x), or with the clover term the site block
+        // X_beta(x) (6 x 6) of the column's chirality times P(x)'s six rows
         const int beta = col / k, i = col % k;
         const double2* p = A.P + ((2 * j + beta) * k + i) * int64_t(A.nr) + l;
         const double2 z = make_double2(0, 0);
+        double2 sv[6];
+        if (A.clover) {
+          double2 pc[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) pc[c] = p[int64_t(c) * A.nb];
+          const double2* X = A.clover + aidx(0, 36 * beta, x, pad_sites(A.V), 72);
+#pragma unroll
+          for (int r = 0; r < 6; ++r) {
+            double2 acc = z;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) cfma(acc, X[(6 * r + c) * kVL], pc[c]);
+            sv[r] = acc;
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) sv[c] = cscale(p[int64_t(c) * A.nb], A.diag);
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const double2 v0 = cscale(p[int64_t(a) * A.nb], A.diag);
-          const double2 v1 = cscale(p[int64_t(3 + a) * A.nb], A.diag);
+          const double2 v0 = sv[a], v1 = sv[3 + a];
           t[a][0] = beta == 0 ? v0 : z;
           t[a][1] = beta == 0 ? v1 : z;
           t[a][2] = beta == 0 ? z : v0;

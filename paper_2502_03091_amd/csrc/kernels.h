@@ -41,6 +41,11 @@ struct WilsonArgs {
   int order = 0;    // 0: RHS groups of a site block consecutive; 1: site blocks of a RHS group consecutive
   int swizzle = 1;  // XCD-contiguous workgroup mapping
   int tile4 = 0;    // device order is block-major in 4^4 blocks (every extent a multiple of 4)
+  // Wilson-clover: the site blocks diag 1 + C(x) in the form's storage (FP64
+  // double2, else float2), site-vectorised [72][V] at device positions; they
+  // replace the scalar diag.  clover_sign multiplies them (-1 for -D).
+  const void* clover = nullptr;
+  double clover_sign = 1.0;
 };
 void wilson_apply(const WilsonArgs& a, hipStream_t st);
 int64_t wilson_partial_blocks(int64_t V);

@@ -1,6 +1,8 @@
 // Lattice object: creation, gauge upload and conversion to every precision form.
 #include "lattice.h"
 
+#include "clover.h"
+
 namespace crk {
 
 Lattice* lattice_create(const int32_t dims[4], double m0, double xi) {
@@ -39,6 +41,25 @@ void lattice_load_gauge(Lattice* L, const double* U_host) {
     gauge_convert(f, L->U64.as<double2>(), L->gauge[f].p, L->geo.pos.as<int>(), L->V, L->stream);
   CRK_HIP(hipStreamSynchronize(L->stream));
   L->gauge_loaded = true;
+  lattice_set_clover(L, L->c_sw);
+}
+
+void lattice_set_clover(Lattice* L, double c_sw) {
+  CRK_REQUIRE(std::isfinite(c_sw), "c_sw must be finite");
+  L->c_sw = c_sw;
+  if (c_sw == 0.0) {
+    L->clover64.release();
+    for (int f = 0; f < 3; ++f) L->clover[f].release();
+    return;
+  }
+  if (!L->gauge_loaded) return;  // computed when the gauge field arrives
+  L->clover64.alloc(sizeof(double2) * 72 * size_t(L->V));
+  clover_compute(L->U64.as<double2>(), L->dims, c_sw, L->w, L->diag(), L->clover64.as<double2>(), L->stream);
+  for (int f = 0; f < 3; ++f) {
+    L->clover[f].alloc(clover_bytes(f, L->V));
+    clover_convert(f, L->clover64.as<double2>(), L->clover[f].p, L->geo.pos.as<int>(), L->V, L->stream);
+  }
+  CRK_HIP(hipStreamSynchronize(L->stream));
 }
 
 void lattice_release(Lattice* L) {

@@ -39,6 +39,9 @@ struct Lattice {
   DevBuf U64;                // complex128 host layout copy [V][4][3][3]
   DevBuf gauge[3];           // per form, [mu][9][V] lexicographic
   bool gauge_loaded = false;
+  double c_sw = 0.0;         // clover coefficient (0: plain Wilson)
+  DevBuf clover64;           // c_sw != 0: FP64 site blocks diag 1 + C(x), [V][72] lexicographic
+  DevBuf clover[3];          // per form, site-vectorised [72][V] lexicographic
   hipStream_t stream = nullptr;
   int device = 0;            // HIP device current when the lattice was created
   std::atomic<int> refs{1};
@@ -49,6 +52,8 @@ struct Lattice {
 
 Lattice* lattice_create(const int32_t dims[4], double m0, double xi);
 void lattice_load_gauge(Lattice* L, const double* U_host);
+// Set the clover coefficient; recomputes the clover blocks when the gauge field is loaded.
+void lattice_set_clover(Lattice* L, double c_sw);
 void lattice_release(Lattice* L);
 
 // D applied to nrhs host-layout fields (complex128 [nrhs][V][12], host memory)

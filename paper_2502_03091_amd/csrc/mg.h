@@ -54,6 +54,7 @@ struct Hierarchy {
   int nlev = 0;
   Geometry fine_geo;                 // block-major order of the fine lattice
   DevBuf fine_gauge[3];              // per form, fine device order
+  DevBuf fine_clover[3];             // Wilson-clover: site blocks per form, fine device order (empty if c_sw = 0)
   std::vector<CoarseLevel> coarse;   // levels 1..nlev-1 (index l-1)
   std::vector<Transfer> T;           // steps 0..nlev-2
   std::vector<DevBuf> vectors;       // smoothed test vectors per step (setup form / coarse FP64)

@@ -6,6 +6,7 @@
 // truncated to k per chirality (-> P, sigma), and the Galerkin coarse operator
 // D_{l+1} = P^dag D_l P stored in FP64 with FP32 / FP16S copies.
 #include "mg.h"
+#include "clover.h"
 
 #include <cmath>
 #include <cstring>
@@ -95,6 +96,8 @@ void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int n
       for (double& h : a.hw) h = -h;
     a.partial = partial;
     a.rhs_per_thread = 4;
+    a.clover = H->fine_clover[form].p;  // NULL without the clover term
+    a.clover_sign = negate ? -1.0 : 1.0;
     const Geometry& g = H->fine_geo;
     a.tile4 = g.blocked && g.block[0] == 4 && g.block[1] == 4 && g.block[2] == 4 && g.block[3] == 4;
     wilson_apply(a, st);
@@ -320,6 +323,7 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
     g.nr = t.nr;
     g.k = t.k;
     g.diag = H->lat->diag();
+    g.clover = H->fine_clover[0].as<double2>();
     H->lat->hw(g.hw);
     g.ncoarse = t.nblocks;
     g.pos_c = c.geo.pos.as<int>();
@@ -369,6 +373,10 @@ Hierarchy* mg_setup(Lattice* L, const crk_mg_params& p) {
     for (int f = 0; f < 3; ++f) {
       H->fine_gauge[f].alloc(gauge_bytes(f, L->V));
       gauge_convert(f, L->U64.as<double2>(), H->fine_gauge[f].p, H->fine_geo.pos.as<int>(), L->V, st);
+      if (L->c_sw != 0.0) {  // the lattice's clover blocks in this hierarchy's site order
+        H->fine_clover[f].alloc(clover_bytes(f, L->V));
+        clover_convert(f, L->clover64.as<double2>(), H->fine_clover[f].p, H->fine_geo.pos.as<int>(), L->V, st);
+      }
     }
     int dims[4];
     std::memcpy(dims, L->dims, sizeof(dims));
