@@ -160,8 +160,8 @@ void crk_lattice_destroy(crk_lattice_t lat);
 
 typedef struct {
   int32_t n_levels;                    /* 2 or 3 (levels including the fine one) */
-  int32_t m_prime[CRK_MAX_LEVELS];     /* test vectors per coarsening step (<= 64) */
-  int32_t k[CRK_MAX_LEVELS];           /* kept per chirality; multiple of 8, <= m', <= N_r */
+  int32_t m_prime[CRK_MAX_LEVELS];     /* test vectors per coarsening step (<= 128) */
+  int32_t k[CRK_MAX_LEVELS];           /* kept per chirality; multiple of 8 in [8, 32], <= m', <= N_r */
   int32_t block[CRK_MAX_LEVELS][4];    /* block extent per coarsening step */
   int32_t n_smooth[CRK_MAX_LEVELS];    /* MR sweeps on D psi ~ 0 per step */
   int32_t setup_form;                  /* precision of the setup smoother (FP64 or FP32) */

@@ -14,7 +14,8 @@ preconditioner of Wilson fermions in lattice QCD", LATTICE2024) it follows.
 Modules:
   lattice   -- site/neighbour/block maps (Sec. 2, domain decomposition Lambda_j)
   gamma     -- chiral-basis Dirac matrices (Sec. 2, Eq. (2) split)
-  wilson    -- Wilson-Dirac operator D (Sec. 1-2)
+  wilson    -- Wilson-Dirac operator D (Sec. 1-2), optionally with the clover term
+  clover    -- clover site term of the Wilson-clover operator (Sec. 4 ensembles)
   stencil   -- generic nearest-neighbour block-stencil operator (coarse levels)
   mr        -- minimal-residual smoother (Sec. 2, Eq. (1))
   chiral    -- chiral split, truncated SVD, prolongator (Sec. 3, Eqs. (2), (5), (6))

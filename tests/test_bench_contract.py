@@ -51,3 +51,5 @@ def test_tuned_masses_load():
     for ens in ("aniso_xi3.5_eps0.2", "iso_xi1_eps0.25"):
         m0 = bench.tuned_m0(ens)
         assert -0.5 < m0 < 0.5
+        # the benchmark masses sit between the small-lattice critical mass and m_c + 0.01
+        assert m0 - 0.01 < bench.LIGHT_M0[ens] < m0
