@@ -347,6 +347,7 @@ def form_summary(recs, V, setup_form, m_prime=C3_MPRIME):
         "iters": max(r["iters"] for r in recs), "level_iters": recs[-1]["level_iters"],
         "true_rel_resid": max(r["true_rel_resid"] for r in recs), "converged": all(r["converged"] for r in recs),
         "smoother_dslash_GBps": dslash_bytes(V, m_prime, sform) / launch / 1e9,
+        "smoother_dslash_frac_of_hbm_peak": dslash_bytes(V, m_prime, sform) / launch / 1e9 / HBM_PEAK_GBPS,
         "smoother_dslash_launch_ms": 1e3 * launch,
         "steps": len(recs),
     }
@@ -472,6 +473,7 @@ def c2_step(crk, lat, b, x, setup_form, solve_form, m_prime=M_PRIME, k=K, keep=F
            "converged": info["converged"], "smoother_dslash_launch_ms": 1e3 * tim["dslash_avg"],
            "smoother_dslash_GBps": dslash_bytes(int(np.prod(DIMS)), m_prime, 0 if setup_form == 0 else 1)
            / tim["dslash_avg"] / 1e9}
+    rec["smoother_dslash_frac_of_hbm_peak"] = rec["smoother_dslash_GBps"] / HBM_PEAK_GBPS
     if keep:
         return rec, H
     H.close()

@@ -38,6 +38,18 @@ void gcr_multiaxpy_w(int prec, const void* W, int64_t fstride, int nj, int j_fir
                      const FieldShape& f, hipStream_t st);
 void gcr_update_lazy(int prec, void* w, void* r, const double* dpart, int64_t dnch, const int* active, int* breakdown,
                      const FieldShape& f, double* partial, double* rn2, double* hinv, double2* ha, hipStream_t st);
+// The same step in one pass for rhs-inner (coarse) fields, one RHS included
+// (gcr_one_pass_shape): dpart holds the <w_i, r>, ||w_i||^2 partials of the
+// unmodified w_i, coef the multidot's c_ij (not read for nj = 0); ||w^||^2 and
+// <w^, r> follow from them (orthonormal stored directions, r orthogonal to
+// them), so w_i is orthogonalised, normalised and r updated in one kernel.
+// partial receives the ||r||^2 partials of the check, in the rhs-inner
+// chunks whatever the RHS count; returns their number of rows (gcr_check's
+// partial_rows).
+bool gcr_one_pass_shape(const FieldShape& f);
+int64_t gcr_gs_update(int prec, const void* W, int64_t fstride, int nj, void* w, void* r, const double2* coef,
+                   const double* dpart, int64_t dnch, const int* active, int* breakdown, const FieldShape& f,
+                   double* partial, double* hinv, double2* ha, hipStream_t st);
 // Inner solve of K iterations with records c_ij at hcoef[i][nrhs][kMaxCoef],
 // 1/||w_i|| and a_i at hinv/ha[i][nrhs]:
 // x = sum_{i<K} d_i z_i with the d_i of the recorded recursion (dcoef: [nrhs][kMaxCoef] work space).
@@ -51,10 +63,11 @@ void gcr_lazy_solution(int prec, const void* Z, int64_t fstride, int K, void* x,
 void gcr_ring_materialize(const void* Z, int64_t fstride, const int* nb, int last, int nslots, int cap, void* x,
                           const double2* hcoef, const double* hinv, double2* ha, double2* dcoef, const FieldShape& f,
                           hipStream_t st);
-// n_active_host (optional): pinned host memory that also receives the count of active RHS.
+// n_active_host (optional): pinned host memory that also receives the count of active RHS;
+// partial_rows (optional): rows of partial, when not the field shape's own chunking.
 void gcr_check(const double* partial, const FieldShape& f, double tol2, const double* b2, const int* breakdown,
                int* active, int* iters, double* rn2, int* n_active, int* level_iters, hipStream_t st,
-               int* n_active_host = nullptr);
+               int* n_active_host = nullptr, int64_t partial_rows = -1);
 void gcr_start(const double* sums3, int nrhs, double* b2, int* active, int* iters, int* n_active, hipStream_t st);
 void field_axpby(int prec, const void* x, void* y, double a, double b, int64_t total, hipStream_t st);
 void field_masked_copy(int prec, const void* x, void* y, const int* mask, const FieldShape& f, hipStream_t st);

@@ -64,16 +64,22 @@ __global__ __launch_bounds__(kT) void multidot_kernel(const C* __restrict__ Wb, 
   double acc[2 * kDotGroup];
 #pragma unroll
   for (int q = 0; q < 2 * kDotGroup; ++q) acc[q] = 0;
+  // members past the group's last direction issue no loads (the count is
+  // uniform over the workgroup, so the branches are too)
+  const int ng = min(kDotGroup, nj - j0);
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int64_t idx = int64_t(r) * rs + e * es;
     const C y = w[idx];
     C x[kDotGroup];
 #pragma unroll
-    for (int g = 0; g < kDotGroup; ++g) x[g] = Wg[g][idx];
+    for (int g = 0; g < kDotGroup; ++g)
+      if (g < ng) x[g] = Wg[g][idx];
 #pragma unroll
     for (int g = 0; g < kDotGroup; ++g) {
-      acc[2 * g] += double(x[g].x) * y.x + double(x[g].y) * y.y;
-      acc[2 * g + 1] += double(x[g].x) * y.y - double(x[g].y) * y.x;
+      if (g < ng) {
+        acc[2 * g] += double(x[g].x) * y.x + double(x[g].y) * y.y;
+        acc[2 * g + 1] += double(x[g].x) * y.y - double(x[g].y) * y.x;
+      }
     }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -413,6 +419,141 @@ __global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __re
   }
 }
 
+// One-pass step of an inner solve on rhs-inner (coarse) fields.  With the
+// Gram-Schmidt coefficients c_j = <W_j, w> of the stored orthonormal
+// directions (multidot) and the dots of the unmodified w (rhs_dot partials:
+// <w, r>, ||w||^2), the scalars of the step need no pass over the
+// orthogonalised direction w^ = w - sum_j c_j W_j:
+//   ||w^||^2 = ||w||^2 - sum_j |c_j|^2   (the W_j are orthonormal),
+//   <w^, r>  = <w, r>                    (r is orthogonal to every stored W_j),
+// so one pass forms w^, stores w^/||w^|| in place and updates
+// r -= (<w^, r>/||w^||) w^/||w^||, with the ||r||^2 partials of the check.
+// The recursion stays consistent whatever the rounding of these scalars:
+// the stored direction is exactly A p_i of the recorded p_i, and r is updated
+// with it.  A direction whose ||w^||^2 is not well above the rounding of
+// ||w||^2 (w nearly in the span of the stored directions; rel is the relative
+// floor for the vector precision) is a breakdown: the RHS's inner solve stops,
+// as for a zero direction.  Workgroup per (chunk, group of up to 16 RHS),
+// thread (l, r) with r fastest; the sums over lanes and chunks run in fixed
+// orders, so an RHS's numbers do not depend on the other RHS of the field.
+template <class C>
+__global__ __launch_bounds__(64 * kInnerRhs) void gs_update_rg_kernel(
+    const C* __restrict__ Wb, int64_t fstride, int nj, C* __restrict__ w, C* __restrict__ res,
+    const double2* __restrict__ coef, const double* __restrict__ dpart, int64_t dnch, const int* __restrict__ active,
+    int* __restrict__ breakdown, int64_t n, int nrhs, double* __restrict__ partial, double* __restrict__ hinv,
+    double2* __restrict__ ha, double rel) {
+  __shared__ double sh[kInnerRhs][64][3];
+  __shared__ double scal[kInnerRhs][3];  // 1/||w^||, Re a, Im a
+  __shared__ double2 cf[kInnerRhs][kMaxCoef];
+  using T = decltype(C::x);
+  constexpr int kE = kInnerChunk / 64;  // entries per thread
+  const int r0 = int(blockIdx.y) * kInnerRhs;
+  const int rg = min(kInnerRhs, nrhs - r0);
+  const int t = threadIdx.x;
+  const int rl = t % rg, l = t / rg;
+  const int r = r0 + rl;
+  if (l < 64) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int64_t c = l; c < dnch; c += 64) {
+      const double* p = dpart + (c * nrhs + r) * 3;
+      s0 += p[0];
+      s1 += p[1];
+      s2 += p[2];
+    }
+    sh[rl][l][0] = s0;
+    sh[rl][l][1] = s1;
+    sh[rl][l][2] = s2;
+  }
+  for (int q = t; q < rg * nj; q += blockDim.x) cf[q / nj][q % nj] = coef[(r0 + q / nj) * kMaxCoef + q % nj];
+  __syncthreads();
+  if (t < 3 * rg) {
+    const int rr = t / 3, v = t % 3;
+    double a = 0;
+    for (int k = 0; k < 64; ++k) a += sh[rr][k][v];
+    scal[rr][v] = a;
+  }
+  __syncthreads();
+  if (t < rg) {
+    const double s0 = scal[t][0], s1 = scal[t][1], s2 = scal[t][2];
+    double c2 = 0;
+    for (int j = 0; j < nj; ++j) c2 += cf[t][j].x * cf[t][j].x + cf[t][j].y * cf[t][j].y;
+    const double hw2 = s2 - c2;
+    const bool act0 = active[r0 + t] != 0;
+    const bool ok = act0 && s2 > 0.0 && hw2 > rel * s2 && isfinite(hw2);
+    const double inv = ok ? 1.0 / sqrt(hw2) : 0.0;
+    scal[t][0] = inv;
+    scal[t][1] = s0 * inv;
+    scal[t][2] = s1 * inv;
+    if (blockIdx.x == 0) {
+      if (breakdown) breakdown[r0 + t] = act0 && !ok;
+      hinv[r0 + t] = inv;
+      ha[r0 + t] = make_double2(s0 * inv, s1 * inv);
+    }
+  }
+  __syncthreads();
+  double racc = 0;
+  if (l < 64) {
+    const double inv = scal[rl][0];
+    const bool ok = inv != 0.0;
+    const C ar = mk<C>(T(scal[rl][1]), T(scal[rl][2]));
+    int64_t idx[kE];
+    bool in[kE];
+    C acc[kE];
+#pragma unroll
+    for (int i = 0; i < kE; ++i) {
+      const int64_t e = int64_t(blockIdx.x) * kInnerChunk + l + 64 * i;
+      in[i] = e < n;
+      idx[i] = in[i] ? e * nrhs + r : r;  // past the end: entry 0, in bounds, not stored
+      acc[i] = w[idx[i]];
+    }
+    if (ok) {
+      // w^ = w - sum_j c_j W_j, oldest direction first; four directions of all
+      // entries in flight together
+      constexpr int kU = 4;
+      for (int j0 = 0; j0 < nj; j0 += kU) {
+        C wl[kU][kE];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int64_t off = int64_t(min(j0 + u, nj - 1)) * fstride;
+#pragma unroll
+          for (int i = 0; i < kE; ++i) wl[u][i] = Wb[off + idx[i]];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          if (j0 + u < nj) {
+            const double2 cd = cf[rl][j0 + u];
+            const C cm = mk<C>(T(-cd.x), T(-cd.y));
+#pragma unroll
+            for (int i = 0; i < kE; ++i) cfma(acc[i], cm, wl[u][i]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kE; ++i) {
+      if (!in[i]) continue;
+      const C wn = cscale(acc[i], T(inv));
+      w[idx[i]] = wn;
+      C rr = res[idx[i]];
+      if (ok) {
+        const C aw = cmul(ar, wn);
+        rr.x -= aw.x;
+        rr.y -= aw.y;
+        res[idx[i]] = rr;
+      }
+      racc += double(rr.x) * rr.x + double(rr.y) * rr.y;
+    }
+  }
+  __syncthreads();  // sh is reused
+  if (l < 64) sh[rl][l][0] = racc;
+  __syncthreads();
+  if (t < rg) {
+    double a = 0;
+    for (int k = 0; k < 64; ++k) a += sh[t][k][0];
+    partial[int64_t(blockIdx.x) * nrhs + r0 + t] = a;
+  }
+}
+
 // Coefficients of the solution over the unmodified directions z_i of a lazy
 // inner solve (one wavefront per RHS, lane j holding coefficient j).  The GCR
 // direction is p_i = inv_i (z_i - sum_{j<i} c_ij p_j) and x = sum_i a_i p_i;
@@ -719,6 +860,28 @@ void gcr_update_lazy(int prec, void* w, void* r, const double* dpart, int64_t dn
   if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
 }
 
+bool gcr_one_pass_shape(const FieldShape& f) { return f.rs == 1 && f.es == f.nrhs; }
+
+int64_t gcr_gs_update(int prec, const void* W, int64_t fstride, int nj, void* w, void* r, const double2* coef,
+                   const double* dpart, int64_t dnch, const int* active, int* breakdown, const FieldShape& f,
+                   double* partial, double* hinv, double2* ha, hipStream_t st) {
+  CRK_REQUIRE(gcr_one_pass_shape(f), "one-pass GCR step: rhs-inner fields only");
+  CRK_REQUIRE(nj >= 0 && nj <= kMaxCoef, "one-pass GCR step: 0 <= directions <= 64");
+  const int64_t nch = gcr_partial_rows(f.n, true);  // one RHS too: the same chunks as for many
+  const dim3 g = dim3(unsigned(nch), unsigned((f.nrhs + kInnerRhs - 1) / kInnerRhs));
+  const dim3 b = dim3(unsigned(64 * std::min(f.nrhs, kInnerRhs)));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(gs_update_rg_kernel<double2>, g, b, 0, st, static_cast<const double2*>(W), fstride, nj,
+                       static_cast<double2*>(w), static_cast<double2*>(r), coef, dpart, dnch, active, breakdown, f.n,
+                       f.nrhs, partial, hinv, ha, 1e-13);
+  else
+    hipLaunchKernelGGL(gs_update_rg_kernel<float2>, g, b, 0, st, static_cast<const float2*>(W), fstride, nj,
+                       static_cast<float2*>(w), static_cast<float2*>(r), coef, dpart, dnch, active, breakdown, f.n,
+                       f.nrhs, partial, hinv, ha, 1e-6);
+  CRK_LAUNCH_CHECK();
+  return nch;
+}
+
 void gcr_lazy_solution(int prec, const void* Z, int64_t fstride, int K, void* x, const double2* hcoef,
                        const double* hinv, const double2* ha, double2* dcoef, const FieldShape& f, hipStream_t st) {
   CRK_REQUIRE(K >= 1 && K <= kMaxCoef, "lazy GCR solution: 1 <= K <= 64 directions");
@@ -750,8 +913,8 @@ void gcr_ring_materialize(const void* Z, int64_t fstride, const int* nb, int las
 
 void gcr_check(const double* partial, const FieldShape& f, double tol2, const double* b2, const int* breakdown,
                int* active, int* iters, double* rn2, int* n_active, int* level_iters, hipStream_t st,
-               int* n_active_host) {
-  const int64_t nch = shape_chunks(f);
+               int* n_active_host, int64_t partial_rows) {
+  const int64_t nch = partial_rows >= 0 ? partial_rows : shape_chunks(f);
   hipLaunchKernelGGL(check_kernel, dim3(1), dim3(kT), 0, st, partial, nch, f.nrhs, tol2, b2, breakdown, active, iters,
                      rn2, n_active, level_iters, n_active_host);
   CRK_LAUNCH_CHECK();

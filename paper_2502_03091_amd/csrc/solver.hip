@@ -111,15 +111,24 @@ void inner_fgcr(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int 
     // z_i stays as the preconditioner (or the copy of r) left it: only w_i is
     // orthogonalised and normalised, and the solution is formed after the loop
     double2* ci = s.hcoef + size_t(i) * nrhs * kMaxCoef;
-    if (i > 0) {
-      gcr_multidot(prec, W, fs, i, wi, f, s.partial, nullptr, ci, st);
-      gcr_multiaxpy_w(prec, W, fs, i, 0, wi, ci, f, st);
+    int64_t rows = -1;  // partial rows of the check: the field's own chunking unless set
+    if (gcr_one_pass_shape(f)) {
+      // coefficients and the dots of the unmodified w_i, then one pass
+      if (i > 0) gcr_multidot(prec, W, fs, i, wi, f, s.partial, nullptr, ci, st);
+      const int64_t dn = rhs_dot_launch(prec, wi, lw.r.p, f.n, nrhs, f.rs, f.es, s.dpart, st);
+      rows = gcr_gs_update(prec, W, fs, i, wi, lw.r.p, ci, s.dpart, dn, s.active, s.breakdown, f, s.partial,
+                           s.hinv + size_t(i) * nrhs, s.ha + size_t(i) * nrhs, st);
+    } else {
+      if (i > 0) {
+        gcr_multidot(prec, W, fs, i, wi, f, s.partial, nullptr, ci, st);
+        gcr_multiaxpy_w(prec, W, fs, i, 0, wi, ci, f, st);
+      }
+      const int64_t dn = rhs_dot_launch(prec, wi, lw.r.p, f.n, nrhs, f.rs, f.es, s.dpart, st);
+      gcr_update_lazy(prec, wi, lw.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, nullptr,
+                      s.hinv + size_t(i) * nrhs, s.ha + size_t(i) * nrhs, st);
     }
-    const int64_t dn = rhs_dot_launch(prec, wi, lw.r.p, f.n, nrhs, f.rs, f.es, s.dpart, st);
-    gcr_update_lazy(prec, wi, lw.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, nullptr,
-                    s.hinv + size_t(i) * nrhs, s.ha + size_t(i) * nrhs, st);
     gcr_check(s.partial, f, tol2, s.b2, s.breakdown, s.active, s.iters, s.rn2, s.n_active, s.level_iters, st,
-              lw.n_active_host.p);
+              lw.n_active_host.p, rows);
     K = i + 1;
     // Converged RHS are frozen on the device; the host only polls every few
     // iterations to stop launching once every RHS is done (the check kernel
