@@ -81,7 +81,7 @@ __global__ __launch_bounds__(64 * kDotRhs) void dot_partial_rg_kernel(const type
                                                                       const typename C2<T>::t* __restrict__ b,
                                                                       int64_t n, int nrhs,
                                                                       double* __restrict__ partial) {
-  __shared__ double sh[kDotRhs][64][3];
+  __shared__ double sh[64][kDotRhs][3];  // [lane][rhs]: the RHS of a lane in different banks
   const int rg = min(kDotRhs, nrhs - int(blockIdx.y) * kDotRhs);
   const int t = threadIdx.x;
   const int rl = t % rg, l = t / rg;
@@ -98,15 +98,15 @@ __global__ __launch_bounds__(64 * kDotRhs) void dot_partial_rg_kernel(const type
       v1 += double(x.x) * y.y - double(x.y) * y.x;
       v2 += double(x.x) * x.x + double(x.y) * x.y;
     }
-    sh[rl][l][0] = v0;
-    sh[rl][l][1] = v1;
-    sh[rl][l][2] = v2;
+    sh[l][rl][0] = v0;
+    sh[l][rl][1] = v1;
+    sh[l][rl][2] = v2;
   }
   __syncthreads();
   if (t < 3 * rg) {
     const int rr = t / 3, v = t % 3;
     double s = 0;
-    for (int k = 0; k < 64; ++k) s += sh[rr][k][v];
+    for (int k = 0; k < 64; ++k) s += sh[k][rr][v];
     partial[(int64_t(blockIdx.x) * nrhs + int(blockIdx.y) * kDotRhs + rr) * 3 + v] = s;
   }
 }

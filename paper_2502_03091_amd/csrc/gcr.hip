@@ -50,32 +50,35 @@ int64_t chunk_for_shape(int64_t n, bool inner) { return inner ? int64_t(kInnerCh
 // direction for its unused members (in-bounds loads, sums not stored).
 constexpr int kDotGroup = 16;
 
-// partial[chunk][r][2*j + {0,1}] = chunk sum of conj(W_j) w
-template <class C>
+// partial[chunk][r][2*j + {0,1}] = chunk sum of conj(W_j) w.  G directions per
+// workgroup (4, 8 or 16, the smallest that holds the pass): fewer unused sums
+// keep fewer registers live and more wavefronts in flight; an entry's sum does
+// not depend on G.
+template <class C, int G>
 __global__ __launch_bounds__(kT) void multidot_kernel(const C* __restrict__ Wb, int64_t fstride, int nj,
                                                       const C* __restrict__ w, int64_t n, int nrhs, int64_t rs,
                                                       int64_t es, int64_t chunk, double* __restrict__ partial) {
-  __shared__ double sh[2 * kDotGroup][4];
-  const int r = blockIdx.y, j0 = blockIdx.z * kDotGroup;
+  __shared__ double sh[2 * G][4];
+  const int r = blockIdx.y, j0 = blockIdx.z * G;
   const int64_t e0 = int64_t(blockIdx.x) * chunk, e1 = min(n, e0 + chunk);
-  const C* Wg[kDotGroup];
+  const C* Wg[G];
 #pragma unroll
-  for (int g = 0; g < kDotGroup; ++g) Wg[g] = Wb + int64_t(min(j0 + g, nj - 1)) * fstride;
-  double acc[2 * kDotGroup];
+  for (int g = 0; g < G; ++g) Wg[g] = Wb + int64_t(min(j0 + g, nj - 1)) * fstride;
+  double acc[2 * G];
 #pragma unroll
-  for (int q = 0; q < 2 * kDotGroup; ++q) acc[q] = 0;
+  for (int q = 0; q < 2 * G; ++q) acc[q] = 0;
   // members past the group's last direction issue no loads (the count is
   // uniform over the workgroup, so the branches are too)
-  const int ng = min(kDotGroup, nj - j0);
+  const int ng = min(G, nj - j0);
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int64_t idx = int64_t(r) * rs + e * es;
     const C y = w[idx];
-    C x[kDotGroup];
+    C x[G];
 #pragma unroll
-    for (int g = 0; g < kDotGroup; ++g)
+    for (int g = 0; g < G; ++g)
       if (g < ng) x[g] = Wg[g][idx];
 #pragma unroll
-    for (int g = 0; g < kDotGroup; ++g) {
+    for (int g = 0; g < G; ++g) {
       if (g < ng) {
         acc[2 * g] += double(x[g].x) * y.x + double(x[g].y) * y.y;
         acc[2 * g + 1] += double(x[g].x) * y.y - double(x[g].y) * y.x;
@@ -84,12 +87,12 @@ __global__ __launch_bounds__(kT) void multidot_kernel(const C* __restrict__ Wb, 
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < 2 * kDotGroup; ++q) {
+  for (int q = 0; q < 2 * G; ++q) {
     const double t = wsum(acc[q]);
     if (lane == 0) sh[q][wid] = t;
   }
   __syncthreads();
-  const int nq = 2 * min(kDotGroup, nj - j0);
+  const int nq = 2 * min(G, nj - j0);
   for (int q = threadIdx.x; q < nq; q += blockDim.x)
     partial[(int64_t(blockIdx.x) * nrhs + r) * (2 * kMaxBasis) + 2 * j0 + q] =
         sh[q][0] + sh[q][1] + sh[q][2] + sh[q][3];
@@ -149,7 +152,7 @@ template <class C>
 __global__ __launch_bounds__(64 * kInnerRhs) void multidot_inner_rg_kernel(const C* __restrict__ Wb, int64_t fstride,
                                                                            int nj, const C* __restrict__ w, int64_t n,
                                                                            int nrhs, double* __restrict__ partial) {
-  __shared__ double sh[kInnerRhs][64][2 * kInnerGroup + 1];
+  __shared__ double sh[64][kInnerRhs][2 * kInnerGroup + 1];  // [lane][rhs]: the RHS of a lane in different banks
   const int rg = min(kInnerRhs, nrhs - int(blockIdx.y) * kInnerRhs);  // RHS in this workgroup
   const int t = threadIdx.x;
   const int rl = t % rg, l = t / rg;
@@ -178,14 +181,14 @@ __global__ __launch_bounds__(64 * kInnerRhs) void multidot_inner_rg_kernel(const
       }
     }
 #pragma unroll
-    for (int q = 0; q < 2 * kInnerGroup; ++q) sh[rl][l][q] = acc[q];
+    for (int q = 0; q < 2 * kInnerGroup; ++q) sh[l][rl][q] = acc[q];
   }
   __syncthreads();
   const int nq = 2 * min(kInnerGroup, nj - j0);
   if (t < rg * nq) {
     const int rr = t / nq, q = t % nq;
     double s = 0;
-    for (int k = 0; k < 64; ++k) s += sh[rr][k][q];
+    for (int k = 0; k < 64; ++k) s += sh[k][rr][q];
     partial[(c * nrhs + int(blockIdx.y) * kInnerRhs + rr) * (2 * kMaxBasis) + 2 * j0 + q] = s;
   }
 }
@@ -353,7 +356,7 @@ __global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __re
                                                                          int nrhs, double* __restrict__ partial,
                                                                          double* __restrict__ hinv,
                                                                          double2* __restrict__ ha) {
-  __shared__ double sh[kInnerRhs][64][3];
+  __shared__ double sh[64][kInnerRhs][3];  // [lane][rhs]: the RHS of a lane in different banks
   __shared__ double scal[kInnerRhs][3];
   using T = decltype(C::x);
   const int rg = min(kInnerRhs, nrhs - int(blockIdx.y) * kInnerRhs);
@@ -369,15 +372,15 @@ __global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __re
       s1 += p[1];
       s2 += p[2];
     }
-    sh[rl][l][0] = s0;
-    sh[rl][l][1] = s1;
-    sh[rl][l][2] = s2;
+    sh[l][rl][0] = s0;
+    sh[l][rl][1] = s1;
+    sh[l][rl][2] = s2;
   }
   __syncthreads();
   if (t < 3 * rg) {
     const int rr = t / 3, v = t % 3;
     double a = 0;
-    for (int k = 0; k < 64; ++k) a += sh[rr][k][v];
+    for (int k = 0; k < 64; ++k) a += sh[k][rr][v];
     scal[rr][v] = a;
   }
   __syncthreads();
@@ -410,11 +413,11 @@ __global__ __launch_bounds__(64 * kInnerRhs) void update_fused_rg_kernel(C* __re
     }
   }
   __syncthreads();  // sh is reused
-  if (l < 64) sh[rl][l][0] = acc;
+  if (l < 64) sh[l][rl][0] = acc;
   __syncthreads();
   if (t < rg) {
     double a = 0;
-    for (int k = 0; k < 64; ++k) a += sh[t][k][0];
+    for (int k = 0; k < 64; ++k) a += sh[k][t][0];
     partial[int64_t(blockIdx.x) * nrhs + int(blockIdx.y) * kInnerRhs + t] = a;
   }
 }
@@ -442,7 +445,7 @@ __global__ __launch_bounds__(64 * kInnerRhs) void gs_update_rg_kernel(
     const double2* __restrict__ coef, const double* __restrict__ dpart, int64_t dnch, const int* __restrict__ active,
     int* __restrict__ breakdown, int64_t n, int nrhs, double* __restrict__ partial, double* __restrict__ hinv,
     double2* __restrict__ ha, double rel) {
-  __shared__ double sh[kInnerRhs][64][3];
+  __shared__ double sh[64][kInnerRhs][3];  // [lane][rhs]: the RHS of a lane in different banks
   __shared__ double scal[kInnerRhs][3];  // 1/||w^||, Re a, Im a
   __shared__ double2 cf[kInnerRhs][kMaxCoef];
   using T = decltype(C::x);
@@ -460,16 +463,16 @@ __global__ __launch_bounds__(64 * kInnerRhs) void gs_update_rg_kernel(
       s1 += p[1];
       s2 += p[2];
     }
-    sh[rl][l][0] = s0;
-    sh[rl][l][1] = s1;
-    sh[rl][l][2] = s2;
+    sh[l][rl][0] = s0;
+    sh[l][rl][1] = s1;
+    sh[l][rl][2] = s2;
   }
   for (int q = t; q < rg * nj; q += blockDim.x) cf[q / nj][q % nj] = coef[(r0 + q / nj) * kMaxCoef + q % nj];
   __syncthreads();
   if (t < 3 * rg) {
     const int rr = t / 3, v = t % 3;
     double a = 0;
-    for (int k = 0; k < 64; ++k) a += sh[rr][k][v];
+    for (int k = 0; k < 64; ++k) a += sh[k][rr][v];
     scal[rr][v] = a;
   }
   __syncthreads();
@@ -545,11 +548,11 @@ __global__ __launch_bounds__(64 * kInnerRhs) void gs_update_rg_kernel(
     }
   }
   __syncthreads();  // sh is reused
-  if (l < 64) sh[rl][l][0] = racc;
+  if (l < 64) sh[l][rl][0] = racc;
   __syncthreads();
   if (t < rg) {
     double a = 0;
-    for (int k = 0; k < 64; ++k) a += sh[t][k][0];
+    for (int k = 0; k < 64; ++k) a += sh[k][t][0];
     partial[int64_t(blockIdx.x) * nrhs + r0 + t] = a;
   }
 }
@@ -772,6 +775,21 @@ int64_t gcr_partial_rows(int64_t n, bool inner) {
 namespace {
 // Chunks of the per-RHS partial sums of a field shape (see the kernels).
 int64_t shape_chunks(const FieldShape& f) { return gcr_partial_rows(f.n, f.es != 1); }
+
+template <class C>
+void launch_multidot(int nc, int64_t nch, const FieldShape& f, const C* W, int64_t fstride, const C* w, int64_t chunk,
+                     double* partial, hipStream_t st) {
+  auto grid = [&](int G) { return dim3(unsigned(nch), unsigned(f.nrhs), unsigned((nc + G - 1) / G)); };
+  if (nc <= 4)
+    hipLaunchKernelGGL((multidot_kernel<C, 4>), grid(4), dim3(kT), 0, st, W, fstride, nc, w, f.n, f.nrhs, f.rs, f.es,
+                       chunk, partial);
+  else if (nc <= 8)
+    hipLaunchKernelGGL((multidot_kernel<C, 8>), grid(8), dim3(kT), 0, st, W, fstride, nc, w, f.n, f.nrhs, f.rs, f.es,
+                       chunk, partial);
+  else
+    hipLaunchKernelGGL((multidot_kernel<C, 16>), grid(16), dim3(kT), 0, st, W, fstride, nc, w, f.n, f.nrhs, f.rs,
+                       f.es, chunk, partial);
+}
 }  // namespace
 
 void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* w, const FieldShape& f, double* partial,
@@ -803,11 +821,11 @@ void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* 
       hipLaunchKernelGGL(multidot_inner_kernel<float2>, gi, dim3(64), 0, st, static_cast<const float2*>(Wj), fstride,
                          nc, static_cast<const float2*>(w), f.n, f.nrhs, f.rs, f.es, partial);
     else if (prec == CRK_FORM_FP64)
-      hipLaunchKernelGGL(multidot_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(Wj), fstride, nc,
-                         static_cast<const double2*>(w), f.n, f.nrhs, f.rs, f.es, chunk, partial);
+      launch_multidot<double2>(nc, nch, f, static_cast<const double2*>(Wj), fstride, static_cast<const double2*>(w),
+                               chunk, partial, st);
     else
-      hipLaunchKernelGGL(multidot_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(Wj), fstride, nc,
-                         static_cast<const float2*>(w), f.n, f.nrhs, f.rs, f.es, chunk, partial);
+      launch_multidot<float2>(nc, nch, f, static_cast<const float2*>(Wj), fstride, static_cast<const float2*>(w),
+                              chunk, partial, st);
     CRK_LAUNCH_CHECK();
     hipLaunchKernelGGL(multidot_reduce_kernel, dim3(unsigned(f.nrhs)), dim3(kT), 0, st, partial, nch, f.nrhs, j0, nc,
                        valid, coef);

@@ -39,6 +39,24 @@ __device__ __forceinline__ double2 ld2(const T2* p, int64_t i) {
   return make_double2(double(v.x), double(v.y));
 }
 
+// Element e of rows [r0, r0+nrows) of the scaled block matrix: its value and
+// its (row, column) in the chunk; consecutive e follow the source's memory order.
+template <class T2>
+__device__ __forceinline__ double2 block_row_elem(const ChiralSrc& src, const T2* base, const double* inv_norm,
+                                                  int64_t j, int alpha, int r0, int nrows, int m, int e, int& rr,
+                                                  int& i) {
+  if (src.si == 1 && !src.aosoa) { i = e % m; rr = e / m; }  // columns contiguous in memory
+  else { rr = e % nrows; i = e / nrows; }           // rows contiguous in memory
+  const int rho = r0 + rr;
+  const int c = rho / src.nb, l = rho % src.nb;
+  const int64_t site = int64_t(j) * src.nb + l;
+  const int64_t idx = src.aosoa ? aidx(i, alpha * src.h + c, site, src.Vp, src.ncomp)
+                                : int64_t(i) * src.si + int64_t(alpha * src.h + c) * src.sc + site * src.ss;
+  const double2 v = ld2(base, idx);
+  const double s = inv_norm ? inv_norm[i] : 1.0;
+  return make_double2(v.x * s, v.y * s);
+}
+
 // Load rows [r0, r0+nrows) of the scaled block matrix into lds[row][col] (ld = m).
 template <class T2>
 __device__ void load_block_rows(const ChiralSrc& src, const T2* base, const double* inv_norm, int64_t j, int alpha,
@@ -46,21 +64,18 @@ __device__ void load_block_rows(const ChiralSrc& src, const T2* base, const doub
   const int total = nrows * m;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     int rr, i;
-    if (src.si == 1 && !src.aosoa) { i = e % m; rr = e / m; }  // columns contiguous in memory
-    else { rr = e % nrows; i = e / nrows; }           // rows contiguous in memory
-    const int rho = r0 + rr;
-    const int c = rho / src.nb, l = rho % src.nb;
-    const int64_t site = int64_t(j) * src.nb + l;
-    const int64_t idx = src.aosoa ? aidx(i, alpha * src.h + c, site, src.Vp, src.ncomp)
-                                  : int64_t(i) * src.si + int64_t(alpha * src.h + c) * src.sc + site * src.ss;
-    double2 v = ld2(base, idx);
-    const double s = inv_norm ? inv_norm[i] : 1.0;
-    lds[rr * ldm + i] = make_double2(v.x * s, v.y * s);
+    const double2 v = block_row_elem(src, base, inv_norm, j, alpha, r0, nrows, m, e, rr, i);
+    lds[rr * ldm + i] = v;
   }
 }
 
-// acc[x][y] += sum_rows conj(L[row][ti*TI + x]) * L[row][tj*TI + y]
-template <int TI, int UNR = 1>
+// acc[x][y] += sum_rows conj(L[row][ti + GW x]) * L[row][tj + GW y] for
+// y >= x: the columns of a thread's tile are GW apart, so the GW threads of a
+// tile row read GW consecutive entries (no LDS bank conflicts).  The result is
+// Hermitian: the entries with y < x lie below the diagonal and are the
+// conjugates of entries another thread forms (gram_store writes both).  Each
+// entry is summed over the rows in order.
+template <int TI, int GW, int UNR = 1>
 __device__ __forceinline__ void gram_accumulate(const double2* lds, int ldm, int nrows, int ti, int tj, int m,
                                                 double2 (&acc)[TI][TI]) {
 #pragma unroll UNR
@@ -68,25 +83,30 @@ __device__ __forceinline__ void gram_accumulate(const double2* lds, int ldm, int
     double2 a[TI], b[TI];
 #pragma unroll
     for (int x = 0; x < TI; ++x) {
-      const int ia = ti * TI + x, ib = tj * TI + x;
+      const int ia = ti + GW * x, ib = tj + GW * x;
       a[x] = ia < m ? lds[r * ldm + ia] : make_double2(0, 0);
       b[x] = ib < m ? lds[r * ldm + ib] : make_double2(0, 0);
     }
 #pragma unroll
     for (int x = 0; x < TI; ++x)
 #pragma unroll
-      for (int y = 0; y < TI; ++y) cfmac(acc[x][y], a[x], b[y]);
+      for (int y = x; y < TI; ++y) cfmac(acc[x][y], a[x], b[y]);
   }
 }
 
-template <int TI>
+// Stores the entries gram_accumulate formed and, above the diagonal blocks,
+// their conjugates below it.
+template <int TI, int GW>
 __device__ __forceinline__ void gram_store(double2* G, int m, int ti, int tj, const double2 (&acc)[TI][TI]) {
 #pragma unroll
   for (int x = 0; x < TI; ++x)
 #pragma unroll
-    for (int y = 0; y < TI; ++y) {
-      const int i = ti * TI + x, ii = tj * TI + y;
-      if (i < m && ii < m) G[i * m + ii] = acc[x][y];
+    for (int y = x; y < TI; ++y) {
+      const int i = ti + GW * x, ii = tj + GW * y;
+      if (i < m && ii < m) {
+        G[i * m + ii] = acc[x][y];
+        if (y > x) G[ii * m + i] = cconj(acc[x][y]);
+      }
     }
 }
 
@@ -99,7 +119,8 @@ __device__ void load_plain_rows(const double2* Bp, int r0, int nrows, int m, dou
 }
 
 // G = A^dag A per (block, chirality): a GW x GW thread grid, each thread a
-// TI x TI tile of G (GW = 16 for m <= 64, 32 for m <= 128).  PLAIN: A is a
+// TI x TI set of entries of G, rows and columns GW apart (GW = 16 for
+// m <= 64, 32 for m <= 128).  PLAIN: A is a
 // plain row-major [pair][N_r][m] matrix instead of the test vectors.
 template <class T2, int TI, int GW, bool PLAIN>
 __global__ __launch_bounds__(GW * GW) void gram_kernel(ChiralSrc src, const T2* __restrict__ base,
@@ -121,9 +142,9 @@ __global__ __launch_bounds__(GW * GW) void gram_kernel(ChiralSrc src, const T2* 
     if constexpr (PLAIN) load_plain_rows(reinterpret_cast<const double2*>(base) + int64_t(pair) * nr * m, r0, nrows, m, lds);
     else load_block_rows(src, base, inv_norm, j, alpha, r0, nrows, m, lds, m);
     __syncthreads();
-    gram_accumulate<TI>(lds, m, nrows, ti, tj, m, acc);
+    gram_accumulate<TI, GW>(lds, m, nrows, ti, tj, m, acc);
   }
-  gram_store<TI>(G + int64_t(pair) * m * m, m, ti, tj, acc);
+  gram_store<TI, GW>(G + int64_t(pair) * m * m, m, ti, tj, acc);
 }
 
 // ---------------------------------------------------------------- Jacobi
@@ -239,6 +260,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(const double2* _
 
 // ---------------------------------------------------------------- B = A V, G2 = B^dag B
 constexpr int kRotChunk = 16;
+static_assert(kThreads == 256 && kRotChunk == 16, "rotate_kernel: 8 row pairs x 32 column pairs of threads");
 
 template <class T2, int TI>
 __global__ __launch_bounds__(kThreads) void rotate_kernel(ChiralSrc src, const T2* __restrict__ base,
@@ -249,9 +271,10 @@ __global__ __launch_bounds__(kThreads) void rotate_kernel(ChiralSrc src, const T
   const int m = src.m, nr = src.h * src.nb;
   const int pair = blockIdx.x, alpha = pair & 1;
   const int64_t j = src.j0 + (pair >> 1);
+  const int la = m + 1;                // padded row stride of As: its rows sit in different LDS banks
   double2* Vs = lds;                   // [m][m]
-  double2* As = Vs + m * m;            // [kRotChunk][m]
-  double2* Bs = As + kRotChunk * m;    // [kRotChunk][m]
+  double2* As = Vs + m * m;            // [kRotChunk][m + 1]
+  double2* Bs = As + kRotChunk * la;   // [kRotChunk][m]
   const double2* Vb = Vin + int64_t(pair) * m * m;
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) Vs[e] = Vb[e];
   const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
@@ -261,27 +284,64 @@ __global__ __launch_bounds__(kThreads) void rotate_kernel(ChiralSrc src, const T
 #pragma unroll
     for (int y = 0; y < TI; ++y) acc[x][y] = make_double2(0, 0);
   double2* Bp = B + int64_t(pair) * nr * m;
+  // the next chunk of A is loaded into registers while the current one is used
+  constexpr int kPre = kRotChunk * 64 / kThreads;  // m <= 64
+  double2 pre[kPre];
+  int prr[kPre], pi[kPre];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    const int e = threadIdx.x + u * kThreads, nrows0 = min(kRotChunk, nr);
+    prr[u] = -1;
+    if (e < nrows0 * m) pre[u] = block_row_elem(src, base, inv_norm, j, alpha, 0, nrows0, m, e, prr[u], pi[u]);
+  }
   for (int r0 = 0; r0 < nr; r0 += kRotChunk) {
     const int nrows = min(kRotChunk, nr - r0);
     __syncthreads();
-    load_block_rows(src, base, inv_norm, j, alpha, r0, nrows, m, As, m);
+#pragma unroll
+    for (int u = 0; u < kPre; ++u)
+      if (prr[u] >= 0) As[prr[u] * la + pi[u]] = pre[u];
     __syncthreads();
-    for (int e = threadIdx.x; e < nrows * m; e += blockDim.x) {
-      const int rr = e / m, col = e % m;
-      double2 t = make_double2(0, 0);
-#pragma unroll 8
-      for (int i = 0; i < m; ++i) cfma(t, As[rr * m + i], Vs[i * m + col]);
-      Bs[rr * m + col] = t;
-      Bp[int64_t(r0 + rr) * m + col] = t;
+    if (r0 + kRotChunk < nr) {
+      const int r1 = r0 + kRotChunk, nrows1 = min(kRotChunk, nr - r1);
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        prr[u] = -1;
+        if (e < nrows1 * m) pre[u] = block_row_elem(src, base, inv_norm, j, alpha, r1, nrows1, m, e, prr[u], pi[u]);
+      }
+    }
+    {
+      // thread (g, c) forms the 2 x 2 tile of B rows {g, g + 8} x columns
+      // {c, c + 32}: every A and V value it reads from LDS feeds two products.
+      // Each entry is summed over i in order, as a plain row-column product.
+      const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+      const int ra = g, rb = g + 8, ca = c, cb = c + 32;
+      const int ra_ = ra < nrows ? ra : 0, rb_ = rb < nrows ? rb : 0;  // past the end: row/column 0, not stored
+      const int ca_ = ca < m ? ca : 0, cb_ = cb < m ? cb : 0;
+      double2 taa = make_double2(0, 0), tab = taa, tba = taa, tbb = taa;
+#pragma unroll 4
+      for (int i = 0; i < m; ++i) {
+        const double2 xa = As[ra_ * la + i], xb = As[rb_ * la + i];
+        const double2 va = Vs[i * m + ca_], vb = Vs[i * m + cb_];
+        cfma(taa, xa, va);
+        cfma(tab, xa, vb);
+        cfma(tba, xb, va);
+        cfma(tbb, xb, vb);
+      }
+      if (ra < nrows && ca < m) { Bs[ra * m + ca] = taa; Bp[int64_t(r0 + ra) * m + ca] = taa; }
+      if (ra < nrows && cb < m) { Bs[ra * m + cb] = tab; Bp[int64_t(r0 + ra) * m + cb] = tab; }
+      if (rb < nrows && ca < m) { Bs[rb * m + ca] = tba; Bp[int64_t(r0 + rb) * m + ca] = tba; }
+      if (rb < nrows && cb < m) { Bs[rb * m + cb] = tbb; Bp[int64_t(r0 + rb) * m + cb] = tbb; }
     }
     __syncthreads();
-    gram_accumulate<TI, 4>(Bs, m, nrows, ti, tj, m, acc);
+    gram_accumulate<TI, 16, 4>(Bs, m, nrows, ti, tj, m, acc);
   }
-  gram_store<TI>(G2 + int64_t(pair) * m * m, m, ti, tj, acc);
+  gram_store<TI, 16>(G2 + int64_t(pair) * m * m, m, ti, tj, acc);
 }
 
 // ---------------------------------------------------------------- U_k = B T
 constexpr int kFinChunk = 32;
+static_assert(kThreads == 8 * kFinChunk, "finalize_kernel: eight column groups of kFinChunk rows");
 
 __global__ __launch_bounds__(kThreads) void finalize_kernel(int m, int nr, int k, const double2* __restrict__ Vin,
                                                             const double2* __restrict__ Win,
@@ -327,17 +387,57 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int m, int nr, int k
   const double2* Bp = B + int64_t(pair) * nr * m;
   double2* Pp = P + int64_t(pair) * k * nr;
   const int mp = m + 1;  // padded row stride: lanes of consecutive rows hit different LDS banks
+  // the next chunk of B is loaded into registers while the current one is used
+  constexpr int kPre = kFinChunk * kBigMax / kThreads;
+  double2 pre[kPre];
+  {
+    const int tot = min(kFinChunk, nr) * m;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      pre[u] = e < tot ? Bp[e] : make_double2(0, 0);
+    }
+  }
   for (int r0 = 0; r0 < nr; r0 += kFinChunk) {
     const int nrows = min(kFinChunk, nr - r0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nrows * m; e += blockDim.x) Bs[(e / m) * mp + e % m] = Bp[int64_t(r0) * m + e];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      if (e < nrows * m) Bs[(e / m) * mp + e % m] = pre[u];
+    }
     __syncthreads();
-    for (int e = threadIdx.x; e < nrows * k; e += blockDim.x) {
-      const int i = e / nrows, rr = e % nrows;
-      double2 t = make_double2(0, 0);
-#pragma unroll 8
-      for (int y = 0; y < m; ++y) cfma(t, Bs[rr * mp + y], T[y * k + i]);
-      Pp[int64_t(i) * nr + r0 + rr] = t;
+    if (r0 + kFinChunk < nr) {
+      const int r1 = r0 + kFinChunk, tot = min(kFinChunk, nr - r1) * m;
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        pre[u] = e < tot ? Bp[int64_t(r1) * m + e] : make_double2(0, 0);
+      }
+    }
+    {
+      // thread (rr, g) forms row rr of the chunk for the columns i = g + 8 q
+      // (k <= 64): each B value it reads feeds up to eight products.  Each
+      // entry is summed over y in order.
+      constexpr int kQ = 8;
+      const int rr = threadIdx.x % kFinChunk, g = threadIdx.x / kFinChunk;
+      const int rr_ = rr < nrows ? rr : 0;  // past the end: row 0, not stored
+      const int nq = (k - g + 7) / 8;       // columns g, g + 8, ... below k
+      double2 t[kQ];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) t[q] = make_double2(0, 0);
+#pragma unroll 4
+      for (int y = 0; y < m; ++y) {
+        const double2 b = Bs[rr_ * mp + y];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)
+          if (q < nq) cfma(t[q], b, T[y * k + g + 8 * q]);
+      }
+      if (rr < nrows) {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)
+          if (q < nq) Pp[int64_t(g + 8 * q) * nr + r0 + rr] = t[q];
+      }
     }
   }
 }
@@ -608,7 +708,7 @@ void launch_gram(const ChiralSrc& s, const void* base, const double* inv_norm, d
 template <class T2>
 void launch_rotate(const ChiralSrc& s, const void* base, const double* inv_norm, const double2* V, double2* B,
                    double2* G2, hipStream_t st) {
-  const size_t lds = sizeof(double2) * (size_t(s.m) * s.m + 2 * kRotChunk * s.m);
+  const size_t lds = sizeof(double2) * (size_t(s.m) * s.m + kRotChunk * (2 * size_t(s.m) + 1));
   const dim3 grid = dim3(unsigned(2 * s.nblocks));
   const T2* b = static_cast<const T2*>(base);
   allow_lds(rotate_kernel<T2, 1>, lds); allow_lds(rotate_kernel<T2, 2>, lds);
