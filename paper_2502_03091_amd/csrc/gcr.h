@@ -70,6 +70,9 @@ void gcr_check(const double* partial, const FieldShape& f, double tol2, const do
                int* n_active_host = nullptr, int64_t partial_rows = -1);
 void gcr_start(const double* sums3, int nrhs, double* b2, int* active, int* iters, int* n_active, hipStream_t st);
 void field_axpby(int prec, const void* x, void* y, double a, double b, int64_t total, hipStream_t st);
+// out = a x + b y, out separate from y (or equal to it)
+void field_axpby_to(int prec, const void* x, const void* y, void* out, double a, double b, int64_t total,
+                    hipStream_t st);
 void field_masked_copy(int prec, const void* x, void* y, const int* mask, const FieldShape& f, hipStream_t st);
 
 }  // namespace crk

@@ -738,8 +738,9 @@ __global__ void start_kernel(const double* __restrict__ sums3, int nrhs, double*
   if (threadIdx.x == 0) *n_active = cnt;
 }
 
+// out = a x + b y (out may be y)
 template <class C>
-__global__ __launch_bounds__(kT) void axpby_kernel(const C* __restrict__ x, C* __restrict__ y, double a, double b,
+__global__ __launch_bounds__(kT) void axpby_kernel(const C* __restrict__ x, const C* y, C* out, double a, double b,
                                                    int64_t total) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= total) return;
@@ -748,7 +749,7 @@ __global__ __launch_bounds__(kT) void axpby_kernel(const C* __restrict__ x, C* _
   C yv = b == 0.0 ? mk<C>(T(0), T(0)) : cscale(y[i], T(b));
   yv.x += T(a) * xv.x;
   yv.y += T(a) * xv.y;
-  y[i] = yv;
+  out[i] = yv;
 }
 
 // y[r] = x[r] for the RHS with mask[r] != 0 (fine or coarse layout)
@@ -943,16 +944,21 @@ void gcr_start(const double* sums3, int nrhs, double* b2, int* active, int* iter
   CRK_LAUNCH_CHECK();
 }
 
-void field_axpby(int prec, const void* x, void* y, double a, double b, int64_t total, hipStream_t st) {
+void field_axpby_to(int prec, const void* x, const void* y, void* out, double a, double b, int64_t total,
+                    hipStream_t st) {
   if (total <= 0) return;
   const dim3 g(ceil_div(total, kT));
   if (prec == CRK_FORM_FP64)
     hipLaunchKernelGGL(axpby_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(x),
-                       static_cast<double2*>(y), a, b, total);
+                       static_cast<const double2*>(y), static_cast<double2*>(out), a, b, total);
   else
     hipLaunchKernelGGL(axpby_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(x),
-                       static_cast<float2*>(y), a, b, total);
+                       static_cast<const float2*>(y), static_cast<float2*>(out), a, b, total);
   CRK_LAUNCH_CHECK();
+}
+
+void field_axpby(int prec, const void* x, void* y, double a, double b, int64_t total, hipStream_t st) {
+  field_axpby_to(prec, x, y, y, a, b, total, st);
 }
 
 void field_masked_copy(int prec, const void* x, void* y, const int* mask, const FieldShape& f, hipStream_t st) {

@@ -158,12 +158,10 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs
     // site and RHS) and the fine operator reads and writes them in that form.
     const int64_t V0 = H->V(0);
     const FieldShape f0 = shape(H, 0, nrhs);
-    const size_t fb32 = vec_bytes(form) * size_t(f0.total());
     void* q32 = w.fw.q.p;
     void* r32 = w.fw.rho.p;
     level_apply(H, 0, CRK_FORM_FP32, eout, q32, nrhs, st);
-    CRK_HIP(hipMemcpyAsync(r32, rin, fb32, hipMemcpyDeviceToDevice, st));
-    field_axpby(CRK_FORM_FP32, q32, r32, -1.0, 1.0, f0.total(), st);
+    field_axpby_to(CRK_FORM_FP32, q32, rin, r32, -1.0, 1.0, f0.total(), st);  // r32 = rin - D e
     void* rhoh = w.fw.q.p;  // q32 is no longer needed
     void* qh = w.fw.rho.p;  // nor is r32 once converted (stream order)
     field_convert(CRK_FORM_FP32, r32, CRK_FORM_FP16S, rhoh, V0, 12, nrhs, st);
@@ -177,7 +175,6 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs
     return;
   }
   const FieldShape f = shape(H, l, nrhs);
-  const size_t fb = vec_bytes(form) * size_t(f.total());
   void *rho, *q;
   if (l == 0) { rho = w.fw.rho.p; q = w.fw.q.p; }
   else { rho = w.lv[l].rho.p; q = w.lv[l].q.p; }
@@ -185,8 +182,7 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs
   // the scalars of level l are idle while its K-cycle runs (the cycle is called
   // between the solver's kernel phases); only sums3/partial/a are reused here.
   level_apply(H, l, opf, eout, q, nrhs, st);
-  CRK_HIP(hipMemcpyAsync(rho, rin, fb, hipMemcpyDeviceToDevice, st));
-  field_axpby(prec, q, rho, -1.0, 1.0, f.total(), st);
+  field_axpby_to(prec, q, rin, rho, -1.0, 1.0, f.total(), st);  // rho = rin - D e
   for (int it = 0; it < p.nu_post; ++it) {
     if (l == 0) {
       level_apply(H, 0, opf, rho, q, nrhs, st, s.partial);

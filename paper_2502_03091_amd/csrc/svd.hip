@@ -160,7 +160,14 @@ __device__ __forceinline__ void pair_of(int round, int k, int mm, int& p, int& q
   if (p > q) { int t = p; p = q; q = t; }
 }
 
-constexpr int kJacobiThreads = 576;  // one 2x2 block update per thread for m' = 48 (24 x 24 pairs)
+constexpr int kJacobiThreads = 1024;  // at most one 2x2 block update per thread (m' = 64: 32 x 32 pairs)
+// Threads of a Jacobi workgroup: one per 2x2 block of a round (np^2, np = mm/2
+// pairs), in whole wavefronts, at least 64 and at most kJacobiThreads.
+inline int jacobi_threads(int m) {
+  const int np = (m + (m & 1)) / 2;
+  const int t = (np * np + 63) / 64 * 64;
+  return t < 64 ? 64 : t > kJacobiThreads ? kJacobiThreads : t;
+}
 
 __global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(const double2* __restrict__ Gin, double* __restrict__ lam,
                                                           double2* __restrict__ Vout, int m, int max_sweeps,
@@ -341,7 +348,6 @@ __global__ __launch_bounds__(kThreads) void rotate_kernel(ChiralSrc src, const T
 
 // ---------------------------------------------------------------- U_k = B T
 constexpr int kFinChunk = 32;
-static_assert(kThreads == 8 * kFinChunk, "finalize_kernel: eight column groups of kFinChunk rows");
 
 __global__ __launch_bounds__(kThreads) void finalize_kernel(int m, int nr, int k, const double2* __restrict__ Vin,
                                                             const double2* __restrict__ Win,
@@ -387,57 +393,17 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(int m, int nr, int k
   const double2* Bp = B + int64_t(pair) * nr * m;
   double2* Pp = P + int64_t(pair) * k * nr;
   const int mp = m + 1;  // padded row stride: lanes of consecutive rows hit different LDS banks
-  // the next chunk of B is loaded into registers while the current one is used
-  constexpr int kPre = kFinChunk * kBigMax / kThreads;
-  double2 pre[kPre];
-  {
-    const int tot = min(kFinChunk, nr) * m;
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int e = threadIdx.x + u * kThreads;
-      pre[u] = e < tot ? Bp[e] : make_double2(0, 0);
-    }
-  }
   for (int r0 = 0; r0 < nr; r0 += kFinChunk) {
     const int nrows = min(kFinChunk, nr - r0);
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int e = threadIdx.x + u * kThreads;
-      if (e < nrows * m) Bs[(e / m) * mp + e % m] = pre[u];
-    }
+    for (int e = threadIdx.x; e < nrows * m; e += blockDim.x) Bs[(e / m) * mp + e % m] = Bp[int64_t(r0) * m + e];
     __syncthreads();
-    if (r0 + kFinChunk < nr) {
-      const int r1 = r0 + kFinChunk, tot = min(kFinChunk, nr - r1) * m;
-#pragma unroll
-      for (int u = 0; u < kPre; ++u) {
-        const int e = threadIdx.x + u * kThreads;
-        pre[u] = e < tot ? Bp[int64_t(r1) * m + e] : make_double2(0, 0);
-      }
-    }
-    {
-      // thread (rr, g) forms row rr of the chunk for the columns i = g + 8 q
-      // (k <= 64): each B value it reads feeds up to eight products.  Each
-      // entry is summed over y in order.
-      constexpr int kQ = 8;
-      const int rr = threadIdx.x % kFinChunk, g = threadIdx.x / kFinChunk;
-      const int rr_ = rr < nrows ? rr : 0;  // past the end: row 0, not stored
-      const int nq = (k - g + 7) / 8;       // columns g, g + 8, ... below k
-      double2 t[kQ];
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) t[q] = make_double2(0, 0);
-#pragma unroll 4
-      for (int y = 0; y < m; ++y) {
-        const double2 b = Bs[rr_ * mp + y];
-#pragma unroll
-        for (int q = 0; q < kQ; ++q)
-          if (q < nq) cfma(t[q], b, T[y * k + g + 8 * q]);
-      }
-      if (rr < nrows) {
-#pragma unroll
-        for (int q = 0; q < kQ; ++q)
-          if (q < nq) Pp[int64_t(g + 8 * q) * nr + r0 + rr] = t[q];
-      }
+    for (int e = threadIdx.x; e < nrows * k; e += blockDim.x) {
+      const int i = e / nrows, rr = e % nrows;
+      double2 t = make_double2(0, 0);
+#pragma unroll 8
+      for (int y = 0; y < m; ++y) cfma(t, Bs[rr * mp + y], T[y * k + i]);
+      Pp[int64_t(i) * nr + r0 + rr] = t;
     }
   }
 }
@@ -779,12 +745,12 @@ void chiral_svd(const ChiralSrc& s, int src_is_double, const void* base, const d
     if (src_is_double) launch_gram<double2, false>(b, base, inv_norm, w.G, st);
     else launch_gram<float2, false>(b, base, inv_norm, w.G, st);
     if (!big) {
-      hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kJacobiThreads), jacobi_lds(m), st, w.G, w.lam, w.V, m, 40,
+      hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(jacobi_threads(m)), jacobi_lds(m), st, w.G, w.lam, w.V, m, 40,
                          tol, w.sweeps);
       CRK_LAUNCH_CHECK();
       if (src_is_double) launch_rotate<double2>(b, base, inv_norm, w.V, w.B, w.G2, st);
       else launch_rotate<float2>(b, base, inv_norm, w.V, w.B, w.G2, st);
-      hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(kJacobiThreads), jacobi_lds(m), st, w.G2, w.lam2, w.W, m,
+      hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(jacobi_threads(m)), jacobi_lds(m), st, w.G2, w.lam2, w.W, m,
                          40, tol, w.sweeps ? w.sweeps + npair : nullptr);
       CRK_LAUNCH_CHECK();
     } else {
