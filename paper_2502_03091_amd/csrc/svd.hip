@@ -7,7 +7,8 @@
 //
 // Algorithm (one workgroup per (j, alpha), all in FP64):
 //   1. G  = A^dag A                          (streamed from the test vectors)
-//   2. G  = V diag(lambda) V^dag             (cyclic Jacobi, round-robin pairs)
+//   2. G  = V diag(lambda) V^dag             (m <= 64: Householder tridiagonal
+//                                             form + implicit QL; above: cyclic Jacobi)
 //   3. B  = A V,  G2 = B^dag B               (B stored; G2 is nearly diagonal)
 //   4. G2 = W diag(lambda2) W^dag            (Jacobi again, few sweeps)
 //   5. U_k = B W_k diag(phase_i / sigma_i),  sigma_i = sqrt(lambda2_i)
@@ -263,6 +264,251 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(const double2* _
     for (int x = 0; x < m; ++x) Vout[b * m * m + int64_t(x) * m + rank] = V[x * ld + i];
   }
   if (threadIdx.x == 0 && sweeps_out) sweeps_out[b] = sweep;
+}
+
+// ---------------------------------------------------------------- first pass: tridiagonal QL
+// Hermitian eigendecomposition G = V diag(lambda) V^dag of the first pass
+// (m <= 64), one workgroup of kThreads per matrix:
+//   1. Householder reduction G = Q T Q^dag with T Hermitian tridiagonal;
+//      reflector k = I - tau u u^dag maps column k below the diagonal onto its
+//      first entry alpha_k = T[k+1][k] (|alpha_k| = the column's norm), and u is
+//      kept in that column;
+//   2. Q = H_0 H_1 ... formed in place from the reflectors, last one first;
+//   3. T = D S D^dag, S real symmetric with off-diagonal |alpha_k|, D the
+//      diagonal of phases phi_{k+1} = phi_k alpha_k / |alpha_k|;
+//   4. S = Z diag(lambda) Z^T by the implicit QL method with Wilkinson shifts
+//      (the tql2 procedure of Bowdler, Martin, Reinsch and Wilkinson), the
+//      rotations applied to the columns of Q D, so V = Q D Z.  One wavefront,
+//      lane r holding row r of Q D's active columns; d and e live one entry per
+//      lane and the scalar recurrences read and write them lane by lane;
+//   5. eigenvalues descending, vectors permuted as jacobi_kernel writes them.
+// An order of magnitude fewer flops than cyclic Jacobi; its vectors have the
+// absolute accuracy of a backward-stable method, and the second pass (Jacobi
+// on B^dag B) resolves the small singular values to working accuracy.
+__device__ __forceinline__ double lane_get(double v, int lane) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b)), lane));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b >> 32)), lane));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+__device__ __forceinline__ double lane_set(double v, double x, int lane) {
+  return int(threadIdx.x & 63) == lane ? x : v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+constexpr int kQlMaxIter = 60;  // QL iterations per eigenvalue before giving up (never reached in practice)
+
+__global__ __launch_bounds__(kThreads) void heig_kernel(const double2* __restrict__ Gin, double* __restrict__ lam,
+                                                        double2* __restrict__ Vout, int m, int* __restrict__ iters_out) {
+  extern __shared__ double2 sh[];
+  __shared__ double2 uv[64], pv[64], ev[64], ph[64];
+  __shared__ double dv[64], er[64], tv[64];
+  const int ld = m + 1;
+  double2* A = sh;  // [m][ld]
+  const int64_t b = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const double2* Gb = Gin + b * m * m;
+  for (int e = t; e < m * m; e += blockDim.x) A[(e / m) * ld + e % m] = Gb[e];
+  __syncthreads();
+  // 1. reduction to tridiagonal form
+  for (int k = 0; k + 2 < m; ++k) {
+    const int n = m - 1 - k;  // trailing rows / columns k+1 .. m-1
+    if (wid == 0) {
+      const double2 x = lane < n ? A[(k + 1 + lane) * ld + k] : make_double2(0, 0);
+      const double nx2 = wave_sum(x.x * x.x + x.y * x.y);
+      const double2 x0 = make_double2(__shfl(x.x, 0), __shfl(x.y, 0));
+      const double nx = sqrt(nx2), a0 = hypot(x0.x, x0.y);
+      const double2 phs = a0 > 0.0 ? make_double2(x0.x / a0, x0.y / a0) : make_double2(1.0, 0.0);
+      const double2 alpha = make_double2(-phs.x * nx, -phs.y * nx);
+      double2 u = x;
+      if (lane == 0) u = make_double2(x.x - alpha.x, x.y - alpha.y);
+      const double un2 = wave_sum(u.x * u.x + u.y * u.y);
+      const double tau = (nx2 > 0.0 && un2 > 0.0) ? 2.0 / un2 : 0.0;
+      if (lane < n) {
+        uv[lane] = u;
+        A[(k + 1 + lane) * ld + k] = u;  // kept for forming Q
+      }
+      if (lane == 0) {
+        tv[k] = tau;
+        const bool nz = nx2 > 0.0;
+        ev[k] = make_double2(nz ? alpha.x : x0.x, nz ? alpha.y : x0.y);  // T[k+1][k]
+      }
+    }
+    __syncthreads();
+    const double tau = tv[k];
+    if (tau != 0.0) {
+      // p = tau S u, S = A[k+1.., k+1..]: four threads per row
+      {
+        const int i = t >> 2, q = t & 3;
+        double2 acc = make_double2(0, 0);
+        if (i < n)
+          for (int j = q; j < n; j += 4) cfma(acc, A[(k + 1 + i) * ld + k + 1 + j], uv[j]);
+        acc.x += __shfl_xor(acc.x, 1);
+        acc.y += __shfl_xor(acc.y, 1);
+        acc.x += __shfl_xor(acc.x, 2);
+        acc.y += __shfl_xor(acc.y, 2);
+        if (q == 0 && i < n) pv[i] = make_double2(tau * acc.x, tau * acc.y);
+      }
+      __syncthreads();
+      // w = p - (tau/2)(u^dag p) u
+      if (wid == 0) {
+        const double2 u = lane < n ? uv[lane] : make_double2(0, 0);
+        const double2 pp = lane < n ? pv[lane] : make_double2(0, 0);
+        double2 c = make_double2(0, 0);
+        cfmac(c, u, pp);
+        const double2 K = make_double2(0.5 * tau * wave_sum(c.x), 0.5 * tau * wave_sum(c.y));
+        if (lane < n) pv[lane] = pp - cmul(K, u);
+      }
+      __syncthreads();
+      // S -= u w^dag + w u^dag
+      for (int e = t; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        const double2 ui = uv[i], uj = uv[j], wi = pv[i], wj = pv[j];
+        double2& sij = A[(k + 1 + i) * ld + k + 1 + j];
+        sij = sij - cmul(ui, cconj(wj)) - cmul(wi, cconj(uj));
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = t; i < m; i += blockDim.x) dv[i] = A[i * ld + i].x;
+  if (t == 0 && m >= 2) ev[m - 2] = A[(m - 1) * ld + m - 2];
+  __syncthreads();
+  // 2. Q in place, last reflector first
+  for (int e = t; e < 4; e += blockDim.x) {
+    const int r = m - 2 + (e >> 1), c = m - 2 + (e & 1);
+    if (r >= 0 && c >= 0) A[r * ld + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = m - 3; k >= 0; --k) {
+    const int n = m - 1 - k;
+    // Q so far is the identity on index k+1
+    for (int e = t; e < n; e += blockDim.x) {
+      A[(k + 1 + e) * ld + k + 1] = make_double2(e == 0 ? 1.0 : 0.0, 0.0);
+      if (e > 0) A[(k + 1) * ld + k + 1 + e] = make_double2(0, 0);
+    }
+    __syncthreads();
+    const double tau = tv[k];
+    if (tau != 0.0) {
+      // y_c = tau sum_r conj(u_r) Q[r][c]
+      {
+        const int c = t >> 2, q = t & 3;
+        double2 acc = make_double2(0, 0);
+        if (c < n)
+          for (int r = q; r < n; r += 4) cfmac(acc, A[(k + 1 + r) * ld + k], A[(k + 1 + r) * ld + k + 1 + c]);
+        acc.x += __shfl_xor(acc.x, 1);
+        acc.y += __shfl_xor(acc.y, 1);
+        acc.x += __shfl_xor(acc.x, 2);
+        acc.y += __shfl_xor(acc.y, 2);
+        if (q == 0 && c < n) pv[c] = make_double2(tau * acc.x, tau * acc.y);
+      }
+      __syncthreads();
+      for (int e = t; e < n * n; e += blockDim.x) {
+        const int r = e / n, c = e % n;
+        double2& qrc = A[(k + 1 + r) * ld + k + 1 + c];
+        qrc = qrc - cmul(A[(k + 1 + r) * ld + k], pv[c]);
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < m; e += blockDim.x) {
+    A[e] = make_double2(e == 0 ? 1.0 : 0.0, 0.0);       // row 0
+    if (e > 0) A[e * ld] = make_double2(0, 0);         // column 0
+  }
+  // 3. phases
+  if (t == 0) {
+    double2 phi = make_double2(1.0, 0.0);
+    ph[0] = phi;
+    for (int j = 0; j + 1 < m; ++j) {
+      const double2 a = ev[j];
+      const double aa = hypot(a.x, a.y);
+      er[j] = aa;
+      if (aa > 0.0) phi = cmul(phi, make_double2(a.x / aa, a.y / aa));
+      ph[j + 1] = phi;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < m * m; e += blockDim.x) {
+    const int r = e / m, c = e % m;
+    A[r * ld + c] = cmul(A[r * ld + c], ph[c]);
+  }
+  __syncthreads();
+  // 4. implicit QL on (d, |alpha|), rotations applied to the columns of Q D
+  if (wid == 0) {
+    const double eps = 2.220446049250313e-16;
+    double dd = lane < m ? dv[lane] : 0.0;
+    double ee = lane + 1 < m ? er[lane] : 0.0;
+    const bool row = lane < m;
+    int its_total = 0;
+    for (int l = 0; l < m; ++l) {
+      int its = 0;
+      while (true) {
+        const double dn = __shfl_down(dd, 1);
+        const bool small = lane >= l && (lane == m - 1 || fabs(ee) <= eps * (fabs(dd) + fabs(dn)));
+        const uint64_t mask = __ballot(small);
+        const int mm = int(__builtin_ctzll(mask));
+        if (mm == l || its >= kQlMaxIter) break;
+        ++its;
+        const double dl = lane_get(dd, l), dl1 = lane_get(dd, l + 1), el = lane_get(ee, l), dm = lane_get(dd, mm);
+        double g = (dl1 - dl) / (2.0 * el);
+        double r = sqrt(g * g + 1.0);
+        g = dm - dl + el / (g + (g >= 0.0 ? r : -r));
+        double s = 1.0, c = 1.0, p = 0.0;
+        bool deflated = false;
+        double2 zc = row ? A[lane * ld + mm] : make_double2(0, 0);
+        int i = mm - 1;
+        for (; i >= l; --i) {
+          const double ei = lane_get(ee, i);
+          const double f = s * ei, bb = c * ei;
+          r = sqrt(f * f + g * g);
+          ee = lane_set(ee, r, i + 1);
+          if (r == 0.0) {  // the recurrence split: d[i+1] -= p, e[mm] = 0, test again
+            dd = lane_set(dd, lane_get(dd, i + 1) - p, i + 1);
+            ee = lane_set(ee, 0.0, mm);
+            deflated = true;
+            break;
+          }
+          const double inv = 1.0 / r;
+          s = f * inv;
+          c = g * inv;
+          g = lane_get(dd, i + 1) - p;
+          r = (lane_get(dd, i) - g) * s + 2.0 * c * bb;
+          p = s * r;
+          dd = lane_set(dd, g + p, i + 1);
+          g = c * r - bb;
+          // columns i, i+1: z_{i+1} <- s z_i + c z_{i+1}, z_i <- c z_i - s z_{i+1}
+          if (row) {
+            const double2 zi = A[lane * ld + i];
+            A[lane * ld + i + 1] = make_double2(s * zi.x + c * zc.x, s * zi.y + c * zc.y);
+            zc = make_double2(c * zi.x - s * zc.x, c * zi.y - s * zc.y);
+          }
+        }
+        if (row) A[lane * ld + (deflated ? i + 1 : l)] = zc;
+        if (deflated) continue;
+        dd = lane_set(dd, lane_get(dd, l) - p, l);
+        ee = lane_set(ee, g, l);
+        ee = lane_set(ee, 0.0, mm);
+      }
+      its_total += its;
+    }
+    if (row) dv[lane] = dd;
+    if (lane == 0 && iters_out) iters_out[b] = its_total;
+  }
+  __syncthreads();
+  // 5. descending order (ties by index), vectors permuted
+  for (int i = t; i < m; i += blockDim.x) {
+    const double li = dv[i];
+    int rank = 0;
+    for (int jj = 0; jj < m; ++jj) {
+      const double lj = dv[jj];
+      rank += (lj > li) || (lj == li && jj < i);
+    }
+    lam[b * m + rank] = li;
+    for (int x = 0; x < m; ++x) Vout[b * m * m + int64_t(x) * m + rank] = A[x * ld + i];
+  }
 }
 
 // ---------------------------------------------------------------- B = A V, G2 = B^dag B
@@ -686,6 +932,8 @@ void launch_rotate(const ChiralSrc& s, const void* base, const double* inv_norm,
   CRK_LAUNCH_CHECK();
 }
 
+size_t heig_lds(int m) { return sizeof(double2) * size_t(m) * (m + 1); }
+
 size_t jacobi_lds(int m) {
   const int mm = m + (m & 1), ld = mm + 1;
   return sizeof(double2) * 2 * mm * ld + sizeof(Rot) * (mm / 2) + sizeof(int) * mm;
@@ -735,7 +983,10 @@ void chiral_svd(const ChiralSrc& s, int src_is_double, const void* base, const d
   const bool big = m > 64;
   const size_t lds = sizeof(double2) * (size_t(m) * k + size_t(kFinChunk) * (m + 1));
   CRK_REQUIRE(lds <= 160 * 1024, "SVD finaliser: m' * k too large for LDS");
-  if (!big) allow_lds(jacobi_kernel, jacobi_lds(m));
+  if (!big) {
+    allow_lds(heig_kernel, heig_lds(m));
+    allow_lds(jacobi_kernel, jacobi_lds(m));
+  }
   allow_lds(finalize_kernel, lds);
   for (int64_t j0 = 0; j0 < s.nblocks; j0 += wcap) {
     ChiralSrc b = s;
@@ -745,8 +996,7 @@ void chiral_svd(const ChiralSrc& s, int src_is_double, const void* base, const d
     if (src_is_double) launch_gram<double2, false>(b, base, inv_norm, w.G, st);
     else launch_gram<float2, false>(b, base, inv_norm, w.G, st);
     if (!big) {
-      hipLaunchKernelGGL(jacobi_kernel, dim3(npair), dim3(jacobi_threads(m)), jacobi_lds(m), st, w.G, w.lam, w.V, m, 40,
-                         tol, w.sweeps);
+      hipLaunchKernelGGL(heig_kernel, dim3(npair), dim3(kThreads), heig_lds(m), st, w.G, w.lam, w.V, m, w.sweeps);
       CRK_LAUNCH_CHECK();
       if (src_is_double) launch_rotate<double2>(b, base, inv_norm, w.V, w.B, w.G2, st);
       else launch_rotate<float2>(b, base, inv_norm, w.V, w.B, w.G2, st);
