@@ -151,3 +151,70 @@ def compare_coarse_links(gpu_links, ora_links, dcol, normD, cdims, Pg=None, Po=N
         err_a = max(np.abs(Xg - Xa).max(), np.abs(Ypg - Ypa).max(), np.abs(Ymg - Yma).max())
         assert err_a <= tol_a, (err_a, tol_a)
     return err / scale
+
+
+def fp32_smoother_spread(op, psi0, n_iter, blocks, k, n_terms=10, replays=3, seed=0):
+    """Expected spread of the FP32 smoother's normalised test vectors and of the
+    singular values built from them, from the oracle's own recursion with FP32
+    rounding modelled as relative perturbations: every operator output entry (a
+    sum of about n_terms complex products) is multiplied by 1 + n_terms u32 xi,
+    every update psi += a r, r -= a q and the inner products by 1 + 2 u32 xi,
+    with xi independent complex normals of unit size.  The MR steps, which
+    feed alpha back into the vectors, amplify these as the kernels' roundings
+    would; the largest deviation over a few replays from the unperturbed
+    recursion (per vector, max-norm, relative) and of the singular values
+    (absolute) are returned.  The smoother tests allow the vector spread itself
+    and 10 times the singular-value spread (the SVD of the GPU path runs in FP64
+    on vectors whose rounding differs from the replays' model)."""
+    levels = fp32_setup_spread(op, [psi0], [None], [n_iter], [blocks], [k], n_terms=n_terms, replays=replays,
+                               seed=seed)
+    return levels[0]
+
+
+def fp32_setup_spread(op, init, m_prime, n_smooth, blocks, k, n_terms=10, replays=3, seed=0):
+    """fp32_smoother_spread through a whole (coarse_init) setup: each step's MR
+    smoother runs under the same perturbations on that step's operator, and a
+    step with init[l] None starts from the first m_prime[l] coarse test vectors
+    of the (perturbed) step before it.  Returns [(vector spread, sigma spread)]
+    per step."""
+    from oracle import chiral, galerkin, mr
+
+    rng = np.random.default_rng(seed)
+
+    def pert(x, rel):
+        xi = (rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape)) / np.sqrt(2.0)
+        return x * (1.0 + rel * xi)
+
+    def smooth(o, psi0, n_iter, perturb):
+        p = (lambda x, rel: pert(x, rel)) if perturb else (lambda x, rel: x)
+        psi = np.array(psi0, dtype=np.complex128, copy=True)
+        r = p(-o.apply(psi), n_terms * U32)
+        for _ in range(int(n_iter)):
+            q = p(o.apply(r), n_terms * U32)
+            qq = mr.cdot(q, q).real * (1.0 + (2 * U32 * rng.standard_normal(q.shape[-1]) if perturb else 0.0))
+            qr = mr.cdot(q, r)
+            a = np.where(qq > 0, qr / np.where(qq > 0, qq, 1.0), 0.0)
+            psi = p(psi + a * r, 2 * U32)
+            r = p(r - a * q, 2 * U32)
+        return mr.normalize_columns(psi)
+
+    def run(perturb):
+        out, o, coarse = [], op, None
+        for l in range(len(blocks)):
+            iv = init[l] if init[l] is not None else np.ascontiguousarray(coarse[:, :, :m_prime[l]])
+            psi = smooth(o, iv, n_smooth[l], perturb)
+            A = chiral.chiral_blocks(psi, o.dims, blocks[l])
+            Pb, S = chiral.prolongator_blocks(A, k[l])
+            coarse = chiral.coarse_test_vectors(A, Pb)
+            out.append((psi, S))
+            o = galerkin.galerkin(o, Pb, blocks[l])
+        return out
+
+    ref = run(False)
+    res = [(0.0, 0.0) for _ in blocks]
+    for _ in range(replays):
+        got = run(True)
+        for l, ((v, s), (rv, rs)) in enumerate(zip(got, ref)):
+            dv = float((np.abs(v - rv).max(axis=(0, 1)) / np.abs(rv).max(axis=(0, 1))).max())
+            res[l] = (max(res[l][0], dv), max(res[l][1], float(np.abs(s - rs).max())))
+    return res
