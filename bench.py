@@ -266,6 +266,7 @@ def dslash_sweep(crk, extents=(32, 48), forms=(0, 1, 2), counts=(1, 12, 64), rep
     for ext in extents:
         dims = sizes[ext]
         V = int(np.prod(dims))
+        crk.release_cached_memory()  # cached buffers of other shapes: back to the runtime before torch allocates
         U = synth.gauge_field_device(dims, ISO["eps"], ISO["n_ape"], config=ISO["config"])
         lat = crk.Lattice(dims, tuned_m0("iso_xi1_eps0.25"), ISO["xi"])
         lat.load_gauge(U)
@@ -301,6 +302,7 @@ def dslash_sweep(crk, extents=(32, 48), forms=(0, 1, 2), counts=(1, 12, 64), rep
 
 def c3_lattice(crk, progress=log):
     m0 = LIGHT_M0["iso_xi1_eps0.25"]
+    crk.release_cached_memory()  # cached buffers of other shapes: back to the runtime before torch allocates
     U = synth.gauge_field_device(C3_DIMS, ISO["eps"], ISO["n_ape"], config=ISO["config"], progress=progress)
     lat = crk.Lattice(C3_DIMS, m0, ISO["xi"])
     lat.load_gauge(U)
@@ -559,6 +561,7 @@ def serve_hierarchies(crk, lattices, n_smooth=60):
     m0 = tuned_m0("iso_xi1_eps0.25")
     out = []
     for d in lattices:
+        crk.release_cached_memory()  # cached buffers of other shapes: back to the runtime before torch allocates
         U = synth.gauge_field_device(d, ISO["eps"], ISO["n_ape"], config=ISO["config"])
         lat = crk.Lattice(d, m0, ISO["xi"])
         lat.load_gauge(U)
@@ -651,6 +654,7 @@ def workload_volume(crk, args):
     sizes = {24: [24, 24, 24, 48], 32: [32, 32, 32, 64], 48: [48, 48, 48, 96]}
     for dims in (sizes[int(x)] for x in args.volumes.split(",")):
         V = int(np.prod(dims))
+        crk.release_cached_memory()  # cached buffers of other shapes: back to the runtime before torch allocates
         U = synth.gauge_field_device(dims, ISO["eps"], ISO["n_ape"], config=ISO["config"], progress=log)
         lat = crk.Lattice(dims, m0, ISO["xi"])
         lat.load_gauge(U)
@@ -806,6 +810,7 @@ def workload_kernels(crk, args):
     for ext in (int(x) for x in args.volumes.split(",")):
         dims = sizes[ext]
         V = int(np.prod(dims))
+        crk.release_cached_memory()  # cached buffers of other shapes: back to the runtime before torch allocates
         U = synth.gauge_field_device(dims, ISO["eps"], ISO["n_ape"], config=ISO["config"])
         lat = crk.Lattice(dims, m0, ISO["xi"])
         lat.load_gauge(U)

@@ -72,6 +72,25 @@ const char* crk_last_error(void);
  * bytes and compute-unit count.  Any pointer may be NULL. */
 int crk_device_info(char* name, int32_t n, int64_t* hbm_bytes, int32_t* n_cu);
 
+/* Device memory.  Buffers the library frees (a destroyed hierarchy or
+ * lattice, a solve's work space) are kept per device and handed to later
+ * requests of about the same size (at most 1/8, or 2 MiB, larger), so that
+ * setups repeated on one lattice shape (one per gauge configuration) do not
+ * give back and re-obtain their hundreds of GB each time.  A freed buffer is
+ * cached only after its device has finished all queued work.  When a device
+ * allocation does not fit, that device's cache is given back first.  Memory
+ * the library reports as free (server budgets, batch sizes) includes the
+ * cache. */
+
+/* *bytes receives the bytes cached on the current device.  CRK_EINVAL if
+ * bytes is NULL. */
+int crk_cached_memory_bytes(int64_t* bytes);
+
+/* Give every cached buffer back to the HIP runtime, on every device the
+ * library has used (waits for those devices).  Call before large allocations
+ * outside the library in the same process. */
+int crk_release_cached_memory(void);
+
 /* ------------------------------------------------------------------ lattice */
 
 /* Create the lattice on which the Wilson-Dirac operator D of Sec. 2 (the

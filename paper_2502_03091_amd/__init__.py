@@ -143,6 +143,8 @@ def _load():
         "crk_version": (i32, []),
         "crk_last_error": (C.c_char_p, []),
         "crk_device_info": (i32, [C.c_char_p, i32, C.POINTER(i64), C.POINTER(i32)]),
+        "crk_cached_memory_bytes": (i32, [C.POINTER(i64)]),
+        "crk_release_cached_memory": (i32, []),
         "crk_create_lattice": (i32, [C.POINTER(i32), dbl, dbl, C.POINTER(vp)]),
         "crk_load_gauge": (i32, [vp, vp, i64]),
         "crk_lattice_set_clover": (i32, [vp, dbl]),
@@ -196,7 +198,8 @@ def lib():
 def exported_symbols():
     """Names the binding expects the shared library to export."""
     return [
-        "crk_version", "crk_last_error", "crk_device_info", "crk_create_lattice", "crk_load_gauge",
+        "crk_version", "crk_last_error", "crk_device_info", "crk_cached_memory_bytes", "crk_release_cached_memory",
+        "crk_create_lattice", "crk_load_gauge",
         "crk_lattice_set_clover",
         "crk_dirac_apply", "crk_dirac_apply_dev", "crk_dirac_apply_noalloc", "crk_dirac_apply_noalloc_max_bytes",
         "crk_field_bytes", "crk_field_import_dev",
@@ -235,6 +238,18 @@ def device_info():
     hbm, ncu = C.c_int64(0), C.c_int32(0)
     _check(_load().crk_device_info(name, 64, C.byref(hbm), C.byref(ncu)))
     return {"arch": name.value.decode(), "hbm_bytes": hbm.value, "n_cu": ncu.value}
+
+
+def cached_memory_bytes():
+    """Device bytes the library holds for reuse on the current device (freed buffers kept for later requests)."""
+    out = C.c_int64(0)
+    _check(_load().crk_cached_memory_bytes(C.byref(out)))
+    return out.value
+
+
+def release_cached_memory():
+    """Give the library's cached device buffers back to the HIP runtime (before large allocations elsewhere)."""
+    _check(_load().crk_release_cached_memory())
 
 
 def _as_c128(a, shape=None):

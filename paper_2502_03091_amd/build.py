@@ -32,6 +32,7 @@ SOURCES = [
     "capi.cpp",
     "capi_mg.cpp",
     "server.cpp",
+    "pool.cpp",
     "noalloc.hip",
 ]
 

@@ -67,6 +67,23 @@ int crk_device_info(char* name, int32_t n, int64_t* hbm_bytes, int32_t* n_cu) {
   });
 }
 
+int crk_cached_memory_bytes(int64_t* bytes) {
+  return guarded([&] {
+    CRK_REQUIRE(bytes != nullptr, "bytes is NULL");
+    int dev = 0;
+    CRK_HIP(hipGetDevice(&dev));
+    *bytes = int64_t(device_cached_bytes(dev));
+    return CRK_OK;
+  });
+}
+
+int crk_release_cached_memory(void) {
+  return guarded([&] {
+    device_release_cached();
+    return CRK_OK;
+  });
+}
+
 int crk_create_lattice(const int32_t dims[4], double m0, double xi, crk_lattice_t* out) {
   return guarded([&] {
     CRK_REQUIRE(out != nullptr, "out is NULL");

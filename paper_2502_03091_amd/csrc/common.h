@@ -53,6 +53,16 @@ struct Error : std::runtime_error {
 #define CRK_LAUNCH_CHECK() CRK_HIP(hipGetLastError())
 
 // ------------------------------------------------------------------ device buffer
+// Device memory comes from a process-wide cache (pool.cpp): device_free keeps
+// the buffer for a later device_alloc of about the same size, after waiting for
+// the device as hipFree does.  device_free_bytes counts the cached bytes of the
+// current device as free.
+void* device_alloc(size_t n);
+void device_free(void* p) noexcept;
+size_t device_cached_bytes(int dev);
+size_t device_free_bytes();
+void device_release_cached();
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -69,12 +79,12 @@ struct DevBuf {
   void alloc(size_t n) {
     release();
     if (n == 0) return;
-    CRK_HIP(hipMalloc(&p, n));
+    p = device_alloc(n);
     bytes = n;
   }
   void ensure(size_t n) { if (bytes < n) alloc(n); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) device_free(p);
     p = nullptr;
     bytes = 0;
   }

@@ -211,8 +211,7 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
   if (!inner && p.smooth_chunk > 0) {
     mc = std::min(m, int(p.smooth_chunk));
   } else if (!inner) {
-    size_t fr = 0, tot = 0;
-    CRK_HIP(hipMemGetInfo(&fr, &tot));
+    const size_t fr = device_free_bytes();
     while (mc > 8 && 2 * esz * size_t(n) * size_t(mc) > fr / 10 * 6) mc = (mc + 1) / 2;
   }
   const int nchunk = (m + mc - 1) / mc;
@@ -289,13 +288,15 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
   src.nblocks = t.nblocks;
   // SVD work space (Gram matrices, rotations and B = A V per block): in
   // batches of blocks when all blocks at once would not fit in a quarter of
-  // the free device memory
+  // the free device memory, and at most kSvdWorkCap bytes at once (a few
+  // thousand blocks already fill the device; allocating tens of GB for one
+  // batch costs more than the kernels of the extra batches)
   int64_t wcap = t.nblocks;
   {
-    size_t fr = 0, tot = 0;
-    CRK_HIP(hipMemGetInfo(&fr, &tot));
+    constexpr size_t kSvdWorkCap = size_t(8) << 30;
+    const size_t fr = device_free_bytes();
     const size_t per = svd_work_bytes(m, t.nr, 1);
-    const int64_t fit = int64_t(fr / 4 / per);
+    const int64_t fit = int64_t(std::min(fr / 4, kSvdWorkCap) / per);
     if (fit < wcap) wcap = std::max<int64_t>(1, fit);
     if (p.svd_batch > 0) wcap = std::min<int64_t>(t.nblocks, p.svd_batch);
   }

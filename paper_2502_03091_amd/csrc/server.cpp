@@ -23,9 +23,7 @@ Server::Server(const crk_server_params& p) : p_(p), t0_(std::chrono::steady_cloc
   if (p.hbm_budget_bytes > 0) {
     budget_ = size_t(p.hbm_budget_bytes);
   } else {
-    size_t fr = 0, tot = 0;
-    CRK_HIP(hipMemGetInfo(&fr, &tot));
-    budget_ = fr / 10 * 8;
+    budget_ = device_free_bytes() / 10 * 8;
   }
 }
 
