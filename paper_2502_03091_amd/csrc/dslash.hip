@@ -343,10 +343,28 @@ void launch_wilson_rhsloop(const WilsonArgs& a, hipStream_t st) {
   CRK_LAUNCH_CHECK();
 }
 
+// One complex entry of input storage FIN in the arithmetic type C (FP32
+// storage read by the FP64 operator: widened exactly).
+template <class C, class S> __device__ __forceinline__ C widen(const S& v) { return mk<C>(v.x, v.y); }
+
+// Spinor of site y, RHS r, of an input in storage FIN, in the arithmetic of FORM.
+template <int FORM, int FIN>
+__device__ __forceinline__ void load_as(const FineView<FIN>& in, int64_t r, int64_t y,
+                                        typename Prec<FORM>::cx (&v)[12]) {
+  if constexpr (FIN == FORM) {
+    in.load(r, y, v);
+  } else {
+    typename Prec<FIN>::cx raw[12];
+    in.load(r, y, raw);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = widen<typename Prec<FORM>::cx>(raw[c]);
+  }
+}
+
 // Both hops along MU for one RHS: the spin-MU components of the partial result
 // are returned in mine[], the other nine go to their owners' exchange slots.
-template <int FORM, int MU>
-__device__ __forceinline__ void hop_pair(const FineView<FORM>& in, int r, int64_t yf, int64_t yb,
+template <int FORM, int FIN, int MU>
+__device__ __forceinline__ void hop_pair(const FineView<FIN>& in, int r, int64_t yf, int64_t yb,
                                          const typename Prec<FORM>::cx (&uf)[9],
                                          const typename Prec<FORM>::cx (&ub)[9], typename Prec<FORM>::real coef,
                                          typename Prec<FORM>::cx (*xch)[3][kVL], int lane,
@@ -356,11 +374,11 @@ __device__ __forceinline__ void hop_pair(const FineView<FORM>& in, int r, int64_
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = czero<C>();
   C psi[12], h[6], g[6];
-  in.load(r, yf, psi);
+  load_as<FORM, FIN>(in, r, yf, psi);
   project<MU, +1>(psi, h);
   link_mul<+1>(uf, h, g);
   accumulate<MU, +1>(acc, g, coef);
-  in.load(r, yb, psi);
+  load_as<FORM, FIN>(in, r, yb, psi);
   project<MU, -1>(psi, h);
   link_mul<-1>(ub, h, g);
   accumulate<MU, -1>(acc, g, coef);
@@ -382,8 +400,11 @@ __device__ __forceinline__ void hop_pair(const FineView<FORM>& in, int r, int64_
 // result and hands the other nine to their owners through LDS; after a barrier
 // it adds the diagonal term and the four partials of spin mu in a fixed order
 // and stores them.  A second barrier frees the LDS slots for the next RHS.
-template <int FORM, bool CL>
-__global__ __launch_bounds__(256) void wilson_dir_kernel(FineView<FORM> in, FineView<FORM> out, GaugeView<FORM> U,
+// FIN is the storage of the input: FORM itself, or FP32 for the FP64 operator
+// applied to a field that holds FP32 values (the outer solver's directions in
+// the reduced-precision forms), read as such and widened exactly.
+template <int FORM, int FIN, bool CL>
+__global__ __launch_bounds__(256) void wilson_dir_kernel(FineView<FIN> in, FineView<FORM> out, GaugeView<FORM> U,
                                                          const int* __restrict__ nbr, int64_t V, int nrhs,
                                                          typename Prec<FORM>::real diag, double4 hw_d,
                                                          double* __restrict__ partial, int swz,
@@ -392,6 +413,7 @@ __global__ __launch_bounds__(256) void wilson_dir_kernel(FineView<FORM> in, Fine
   using C = typename Prec<FORM>::cx;
   using T = typename Prec<FORM>::real;
   using S = typename Prec<FORM>::store;
+  using SI = typename Prec<FIN>::store;
   // xch[3*src + slot][c][site]: spin `owner` components of wavefront src's partial,
   // slot = owner with src skipped (owner != src)
   __shared__ C xch[12][3][kVL];
@@ -416,25 +438,25 @@ __global__ __launch_bounds__(256) void wilson_dir_kernel(FineView<FORM> in, Fine
   for (int r = 0; r < nrhs; ++r) {
     C mine[3];
     switch (mu) {
-      case 0: hop_pair<FORM, 0>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
-      case 1: hop_pair<FORM, 1>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
-      case 2: hop_pair<FORM, 2>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
-      default: hop_pair<FORM, 3>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
+      case 0: hop_pair<FORM, FIN, 0>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
+      case 1: hop_pair<FORM, FIN, 1>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
+      case 2: hop_pair<FORM, FIN, 2>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
+      default: hop_pair<FORM, FIN, 3>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
     }
     __syncthreads();
     // spin mu of site s: diagonal + the partials of wavefronts 0..3 (fixed order)
-    const S* pin = in.data + aidx(r, 3 * mu, sl, in.Vp, 12);
+    const SI* pin = in.data + aidx(r, 3 * mu, sl, in.Vp, 12);
     S* pout = out.data + aidx(r, 3 * mu, sl, out.Vp, 12);
     double v0 = 0, v1 = 0, v2 = 0;
     C site[3];
     if constexpr (CL) {
       // rows 3 (mu % 2) + c of the chirality-(mu / 2) clover block times that chirality's six components
       const int al = mu >> 1, r0 = 3 * (mu & 1);
-      const C* pc = in.data + aidx(r, 6 * al, sl, in.Vp, 12);
+      const SI* pc = in.data + aidx(r, 6 * al, sl, in.Vp, 12);
       const C* X = static_cast<const C*>(clv) + aidx(0, 36 * al + 6 * r0, sl, in.Vp, 72);
       C ps[6];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) ps[j] = pc[j * kVL];
+      for (int j = 0; j < 6; ++j) ps[j] = widen<C>(pc[j * kVL]);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         C t = czero<C>();
@@ -445,7 +467,7 @@ __global__ __launch_bounds__(256) void wilson_dir_kernel(FineView<FORM> in, Fine
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const C x = pin[c * kVL];
+      const C x = widen<C>(pin[c * kVL]);
       C q;
       if constexpr (CL) q = site[c];
       else q = cscale(x, diag);
@@ -477,19 +499,20 @@ __global__ __launch_bounds__(256) void wilson_dir_kernel(FineView<FORM> in, Fine
   }
 }
 
-template <int FORM>
+template <int FORM, int FIN = FORM>
 void launch_wilson_dir(const WilsonArgs& a, hipStream_t st) {
   const int64_t nblk = (a.V + kVL - 1) / kVL;
-  FineView<FORM> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
+  FineView<FIN> in(const_cast<void*>(a.in), a.V, a.nrhs);
+  FineView<FORM> out(a.out, a.V, a.nrhs);
   GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), pad_sites(a.V)};
   const double4 hw = make_double4(a.hw[0], a.hw[1], a.hw[2], a.hw[3]);
   if (a.clover)
-    hipLaunchKernelGGL((wilson_dir_kernel<FORM, true>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U, a.nbr,
-                       a.V, a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle, a.clover,
+    hipLaunchKernelGGL((wilson_dir_kernel<FORM, FIN, true>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U,
+                       a.nbr, a.V, a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle, a.clover,
                        typename Prec<FORM>::real(a.clover_sign));
   else
-    hipLaunchKernelGGL((wilson_dir_kernel<FORM, false>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U, a.nbr,
-                       a.V, a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle, a.clover,
+    hipLaunchKernelGGL((wilson_dir_kernel<FORM, FIN, false>), dim3(unsigned(nblk)), dim3(256), 0, st, in, out, U,
+                       a.nbr, a.V, a.nrhs, typename Prec<FORM>::real(a.diag), hw, a.partial, a.swizzle, a.clover,
                        typename Prec<FORM>::real(a.clover_sign));
   CRK_LAUNCH_CHECK();
 }
@@ -709,6 +732,21 @@ void wilson_apply(const WilsonArgs& a_in, hipStream_t st) {
   if (a_in.nrhs <= 0 || a_in.V <= 0) return;
   CRK_REQUIRE(a_in.in != a_in.out, "dslash: in and out must not alias");
   const WilsonArgs& a = a_in;
+  if (a.in_form >= 0 && a.in_form != a.form) {
+    // FP64 operator on FP32-stored input, in launches of at most kDirMaxRhs RHS
+    CRK_REQUIRE(a.form == CRK_FORM_FP64 && a.in_form == CRK_FORM_FP32,
+                "dslash: mixed storage only as FP32 input to the FP64 operator");
+    CRK_REQUIRE(a.partial == nullptr || a.nrhs <= kDirMaxRhs, "dslash: fused sums need one launch");
+    const int64_t per = 12 * pad_sites(a.V);
+    for (int r0 = 0; r0 < a.nrhs; r0 += kDirMaxRhs) {
+      WilsonArgs b = a;
+      b.nrhs = a.nrhs - r0 < kDirMaxRhs ? a.nrhs - r0 : kDirMaxRhs;
+      b.in = static_cast<const float2*>(a.in) + per * r0;
+      b.out = static_cast<double2*>(a.out) + per * r0;
+      launch_wilson_dir<CRK_FORM_FP64, CRK_FORM_FP32>(b, st);
+    }
+    return;
+  }
   const int R = a.rhs_per_thread < a.nrhs ? a.rhs_per_thread : a.nrhs;
   if (a.tile4 && a.form == CRK_FORM_FP32) { launch_wilson_tile<CRK_FORM_FP32>(a, st); return; }
   if (a.tile4 && a.form == CRK_FORM_FP16S) { launch_wilson_tile<CRK_FORM_FP16S>(a, st); return; }

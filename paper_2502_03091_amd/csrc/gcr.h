@@ -59,10 +59,11 @@ void gcr_lazy_solution(int prec, const void* Z, int64_t fstride, int K, void* x,
 // window is its nb[r] (device) latest directions ending at ring slot last;
 // records are [slot][cap] (c: [slot][cap][kMaxCoef]).  Adds the not yet
 // applied part of the solution, sum over the window of a_i p_i, to x and
-// clears those a_i.
-void gcr_ring_materialize(const void* Z, int64_t fstride, const int* nb, int last, int nslots, int cap, void* x,
-                          const double2* hcoef, const double* hinv, double2* ha, double2* dcoef, const FieldShape& f,
-                          hipStream_t st);
+// clears those a_i.  z_form: storage of the directions (FP64, or FP32 when
+// they hold FP32 values: the K-cycle output of the reduced-precision forms).
+void gcr_ring_materialize(const void* Z, int z_form, int64_t fstride, const int* nb, int last, int nslots, int cap,
+                          void* x, const double2* hcoef, const double* hinv, double2* ha, double2* dcoef,
+                          const FieldShape& f, hipStream_t st);
 // n_active_host (optional): pinned host memory that also receives the count of active RHS;
 // partial_rows (optional): rows of partial, when not the field shape's own chunking.
 void gcr_check(const double* partial, const FieldShape& f, double tol2, const double* b2, const int* breakdown,

@@ -640,8 +640,10 @@ __global__ __launch_bounds__(64) void ring_lazy_coef_kernel(const double2* __res
 }
 
 // x_r += sum_k d_k z_{slot k} over RHS r's window, oldest direction first (rhs-outer fields).
-template <class C>
-__global__ __launch_bounds__(kT) void ring_lazy_x_kernel(const C* __restrict__ Zb, int64_t fstride,
+// The directions are stored as CZ: C itself, or float2 when they hold FP32
+// values (widened exactly).
+template <class C, class CZ>
+__global__ __launch_bounds__(kT) void ring_lazy_x_kernel(const CZ* __restrict__ Zb, int64_t fstride,
                                                          const int* __restrict__ nb, int last, int nslots,
                                                          const double2* __restrict__ dcoef, C* __restrict__ x,
                                                          int64_t n, int nrhs, int64_t rs) {
@@ -662,7 +664,8 @@ __global__ __launch_bounds__(kT) void ring_lazy_x_kernel(const C* __restrict__ Z
       const int sk = (last - m + 1 + k + 2 * nslots) % nslots;
       const double2 d = dcoef[int64_t(r) * kMaxCoef + k];
       c[u] = mk<C>(T(d.x), T(d.y));
-      zl[u] = Zb[int64_t(sk) * fstride + idx];
+      const CZ zv = Zb[int64_t(sk) * fstride + idx];
+      zl[u] = mk<C>(T(zv.x), T(zv.y));
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u)
@@ -916,17 +919,22 @@ void gcr_lazy_solution(int prec, const void* Z, int64_t fstride, int K, void* x,
   CRK_LAUNCH_CHECK();
 }
 
-void gcr_ring_materialize(const void* Z, int64_t fstride, const int* nb, int last, int nslots, int cap, void* x,
-                          const double2* hcoef, const double* hinv, double2* ha, double2* dcoef, const FieldShape& f,
-                          hipStream_t st) {
+void gcr_ring_materialize(const void* Z, int z_form, int64_t fstride, const int* nb, int last, int nslots, int cap,
+                          void* x, const double2* hcoef, const double* hinv, double2* ha, double2* dcoef,
+                          const FieldShape& f, hipStream_t st) {
   CRK_REQUIRE(f.es == 1, "ring materialisation: rhs-outer fields only");
   CRK_REQUIRE(nslots >= 1 && nslots <= kMaxCoef && f.nrhs <= cap, "ring materialisation: bad ring");
+  CRK_REQUIRE(z_form == CRK_FORM_FP64 || z_form == CRK_FORM_FP32, "ring materialisation: directions FP64 or FP32");
   hipLaunchKernelGGL(ring_lazy_coef_kernel, dim3(unsigned(f.nrhs)), dim3(64), 0, st, hcoef, hinv, ha, nb, last, nslots,
                      cap, dcoef);
   CRK_LAUNCH_CHECK();
-  hipLaunchKernelGGL(ring_lazy_x_kernel<double2>, dim3(ceil_div(f.n * f.nrhs, kT)), dim3(kT), 0, st,
-                     static_cast<const double2*>(Z), fstride, nb, last, nslots, dcoef, static_cast<double2*>(x), f.n,
-                     f.nrhs, f.rs);
+  const dim3 g(ceil_div(f.n * f.nrhs, kT));
+  if (z_form == CRK_FORM_FP64)
+    hipLaunchKernelGGL((ring_lazy_x_kernel<double2, double2>), g, dim3(kT), 0, st, static_cast<const double2*>(Z),
+                       fstride, nb, last, nslots, dcoef, static_cast<double2*>(x), f.n, f.nrhs, f.rs);
+  else
+    hipLaunchKernelGGL((ring_lazy_x_kernel<double2, float2>), g, dim3(kT), 0, st, static_cast<const float2*>(Z),
+                       fstride, nb, last, nslots, dcoef, static_cast<double2*>(x), f.n, f.nrhs, f.rs);
   CRK_LAUNCH_CHECK();
 }
 

@@ -46,6 +46,9 @@ struct WilsonArgs {
   // replace the scalar diag.  clover_sign multiplies them (-1 for -D).
   const void* clover = nullptr;
   double clover_sign = 1.0;
+  // Storage form of `in` when it is not `form`: only FP32 input to the FP64
+  // operator (values widened exactly, FP64 arithmetic and output).  -1: `form`.
+  int in_form = -1;
 };
 void wilson_apply(const WilsonArgs& a, hipStream_t st);
 int64_t wilson_partial_blocks(int64_t V);

@@ -80,8 +80,9 @@ Hierarchy* mg_setup(Lattice* L, const crk_mg_params& p);
 void mg_destroy(Hierarchy* H);   // drops one reference; frees at zero
 
 // Operators used by setup and solver (device fields in level layout, stream ordered).
+// in_form >= 0: storage of `in` when it is not `form` (level 0 only: FP32 input to the FP64 operator).
 void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int nrhs, hipStream_t st,
-                 double* partial = nullptr, bool negate = false, void* copy = nullptr);
+                 double* partial = nullptr, bool negate = false, void* copy = nullptr, int in_form = -1);
 void level_restrict(Hierarchy* H, int l, int form, const void* fine, void* coarse, int nrhs, hipStream_t st);
 void level_prolong(Hierarchy* H, int l, int form, const void* coarse, void* fine, int nrhs, bool add, hipStream_t st);
 

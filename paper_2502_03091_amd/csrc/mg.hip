@@ -78,7 +78,7 @@ void validate(const Lattice* L, const crk_mg_params& p) {
 
 // ------------------------------------------------------------------ level operators
 void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int nrhs, hipStream_t st, double* partial,
-                 bool negate, void* copy) {
+                 bool negate, void* copy, int in_form) {
   if (l == 0) {
     CRK_REQUIRE(copy == nullptr, "the fine operator has no fused copy");
     Lattice* L = H->lat;
@@ -100,8 +100,10 @@ void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int n
     a.clover_sign = negate ? -1.0 : 1.0;
     const Geometry& g = H->fine_geo;
     a.tile4 = g.blocked && g.block[0] == 4 && g.block[1] == 4 && g.block[2] == 4 && g.block[3] == 4;
+    a.in_form = in_form;
     wilson_apply(a, st);
   } else {
+    CRK_REQUIRE(in_form < 0 || in_form == form, "coarse apply: input must be in the operator's form");
     const CoarseLevel& c = H->coarse[l - 1];
     CRK_REQUIRE(partial == nullptr, "coarse apply has no fused reduction");
     coarse_apply(form, c.N, c.links[form].p, in, out, c.geo.nbr.as<int>(), c.V, nrhs, negate, st, copy);

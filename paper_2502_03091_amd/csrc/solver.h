@@ -62,12 +62,16 @@ struct LevelWork {      // coarse level l >= 1: inner solve buffers (+ post-smoo
 };
 
 struct FineWork {       // level-0 K-cycle fields in the vector precision
-  DevBuf rin, e, rho, q;
+  DevBuf rin, rho, q;
 };
 
 struct OuterWork {      // FP64 outer FGCR
   DevBuf b, x, r, tmp, Z, W, mask;
   int nslots = 0;
+  // Storage of the directions z_i: the K-cycle writes them into the ring in its
+  // own vector precision (FP32 in the reduced forms, whose z_i are FP32 values),
+  // and the FP64 operator and the solution update read them widened.
+  int z_form = CRK_FORM_FP64;
   GcrScalars s;
 };
 

@@ -74,6 +74,11 @@ size_t vec_bytes(int form) { return form == CRK_FORM_FP64 ? sizeof(double2) : si
 // Operator storage used on the fine level in a form (vectors there are FP32 for FP16S).
 int fine_op_form(int form) { return form == CRK_FORM_FP64 ? CRK_FORM_FP64 : CRK_FORM_FP32; }
 int ring_slots(const crk_solve_info& p) { return std::max(1, std::min(p.restart, p.max_iter)); }
+// Storage of the outer directions z_i: the K-cycle's own vector storage (FP32
+// for the reduced forms), FP64 in the plain form and without coarse levels.
+int outer_z_form(const Hierarchy* H, int form) {
+  return H->nlev > 1 && form != CRK_FORM_FP64 ? CRK_FORM_FP32 : CRK_FORM_FP64;
+}
 
 FieldShape shape(Hierarchy* H, int l, int nrhs) {
   return l == 0 ? fine_shape(H->V(0), nrhs) : coarse_shape(H->V(l), H->N(l), nrhs);
@@ -229,22 +234,24 @@ std::unique_ptr<Workspace> make_workspace(Hierarchy* H, int cap, int form, const
   const size_t f64 = sizeof(double2) * 12 * size_t(V0) * cap;
   OuterWork& o = w.ow;
   o.nslots = nslots;
+  o.z_form = outer_z_form(H, form);
+  const size_t zslot = vec_bytes(o.z_form) * 12 * size_t(V0) * cap;
   o.b.alloc(f64); o.x.alloc(f64); o.r.alloc(f64); o.tmp.alloc(f64);
-  o.Z.alloc(f64 * nslots); o.W.alloc(f64 * nslots);
+  o.Z.alloc(zslot * nslots); o.W.alloc(f64 * nslots);
   o.mask.alloc(sizeof(int) * cap);
   o.s.alloc(cap, partial_doubles(12 * V0, cap, false), true);
   // Slots may start at any ring position: every stored direction a slot's
   // kernels touch must hold finite values from the start.
-  CRK_HIP(hipMemsetAsync(o.Z.p, 0, f64 * nslots, st));
+  CRK_HIP(hipMemsetAsync(o.Z.p, 0, zslot * nslots, st));
   CRK_HIP(hipMemsetAsync(o.W.p, 0, f64 * nslots, st));
   CRK_HIP(hipMemsetAsync(o.x.p, 0, f64, st));
   CRK_HIP(hipMemsetAsync(o.r.p, 0, f64, st));
   CRK_HIP(hipMemsetAsync(o.b.p, 0, f64, st));
-  w.bytes += f64 * (4 + 2 * size_t(nslots));
+  w.bytes += f64 * (4 + size_t(nslots)) + zslot * nslots;
   if (H->nlev > 1) {
     const size_t fv = vec_bytes(form) * 12 * size_t(V0) * cap;
-    w.fw.rin.alloc(fv); w.fw.e.alloc(fv); w.fw.rho.alloc(fv); w.fw.q.alloc(fv);
-    w.bytes += 4 * fv;
+    w.fw.rin.alloc(fv); w.fw.rho.alloc(fv); w.fw.q.alloc(fv);
+    w.bytes += 3 * fv;
   }
   w.lv.resize(H->nlev);
   for (int l = 1; l < H->nlev; ++l) {
@@ -368,7 +375,7 @@ int OuterSolver::step() {
   const size_t fbcap = sizeof(double2) * size_t(fcap);
   char* Z = static_cast<char*>(o.Z.p);
   char* W = static_cast<char*>(o.W.p);
-  void* zi = Z + fbcap * ring_;
+  void* zi = Z + vec_bytes(o.z_form) * size_t(fcap) * ring_;
   void* wi = W + fbcap * ring_;
   if (H_->nlev > 1) {
     void* rin = o.r.p;
@@ -376,13 +383,11 @@ int OuterSolver::step() {
       field_convert(CRK_FORM_FP64, o.r.p, CRK_FORM_FP32, w.fw.rin.p, V, 12, wd, st_);
       rin = w.fw.rin.p;
     }
-    void* e = p_.form == CRK_FORM_FP64 ? zi : w.fw.e.p;
-    kcycle(H_, w, 0, p_, wd, rin, e, st_);
-    if (p_.form != CRK_FORM_FP64) field_convert(CRK_FORM_FP32, w.fw.e.p, CRK_FORM_FP64, zi, V, 12, wd, st_);
+    kcycle(H_, w, 0, p_, wd, rin, zi, st_);  // z_i in the ring, in the cycle's vector storage
   } else {
     CRK_HIP(hipMemcpyAsync(zi, o.r.p, sizeof(double2) * size_t(f.total()), hipMemcpyDeviceToDevice, st_));
   }
-  level_apply(H_, 0, CRK_FORM_FP64, zi, wi, wd, st_);
+  level_apply(H_, 0, CRK_FORM_FP64, zi, wi, wd, st_, nullptr, false, nullptr, o.z_form);
   used_ = std::min(used_ + 1, nslots_);
   // Lazy form: z_i stays as the K-cycle returned it, only w_i is orthogonalised
   // and normalised; c_ij, 1/||w_i|| and a_i are recorded per ring slot and the
@@ -463,8 +468,8 @@ void OuterSolver::materialize(int wd, const std::vector<int>& window, int last) 
   GcrScalars& s = o.s;
   const int64_t V = H_->V(0);
   CRK_HIP(hipMemcpyAsync(nbd_.p, window.data(), sizeof(int) * size_t(cap_), hipMemcpyHostToDevice, st_));
-  gcr_ring_materialize(o.Z.p, 12 * V * cap_, nbd_.as<int>(), last, nslots_, cap_, o.x.p, s.hcoef, s.hinv, s.ha,
-                       s.dcoef, fine_shape(V, wd), st_);
+  gcr_ring_materialize(o.Z.p, o.z_form, 12 * V * cap_, nbd_.as<int>(), last, nslots_, cap_, o.x.p, s.hcoef, s.hinv,
+                       s.ha, s.dcoef, fine_shape(V, wd), st_);
   CRK_HIP(hipStreamSynchronize(st_));  // window lives on the caller's stack
 }
 
@@ -516,8 +521,9 @@ Hierarchy::~Hierarchy() = default;
 size_t mg_solve_footprint(Hierarchy* H, int nrhs, int form, const crk_solve_info& p) {
   const int64_t V0 = H->V(0);
   const int nslots = ring_slots(p);
-  size_t b = sizeof(double2) * 12 * size_t(V0) * nrhs * (4 + 2 * size_t(nslots));
-  if (H->nlev > 1) b += 4 * vec_bytes(form) * 12 * size_t(V0) * nrhs;
+  size_t b = sizeof(double2) * 12 * size_t(V0) * nrhs * (4 + size_t(nslots)) +
+             vec_bytes(outer_z_form(H, form)) * 12 * size_t(V0) * nrhs * nslots;
+  if (H->nlev > 1) b += 3 * vec_bytes(form) * 12 * size_t(V0) * nrhs;
   for (int l = 1; l < H->nlev; ++l) {
     const int maxit = l == H->nlev - 1 ? p.coarsest_maxit : p.inner_maxit;
     b += vec_bytes(form) * size_t(H->N(l)) * H->V(l) * nrhs * (5 + 2 * size_t(maxit));
