@@ -134,7 +134,20 @@ __global__ __launch_bounds__(kT) void reduce_partial_kernel(const double* __rest
   __shared__ double sh[4];
   const int r = blockIdx.x / nv, c = blockIdx.x % nv;
   double v[1] = {0};
-  for (int64_t i = threadIdx.x; i < nchunk; i += blockDim.x) v[0] += partial[(i * nrhs + r) * nv + c];
+  // chunks i = t, t + T, t + 2T, ... added in that order, their loads issued 16 at a time
+  constexpr int kU = 16;
+  const int64_t T = blockDim.x;
+  for (int64_t i0 = threadIdx.x; i0 < nchunk; i0 += kU * T) {
+    double x[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t i = i0 + u * T;
+      x[u] = i < nchunk ? partial[(i * nrhs + r) * nv + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (i0 + u * T < nchunk) v[0] += x[u];
+  }
   block_sum<1>(v, sh);
   if (threadIdx.x == 0) out[r * nv + c] = v[0];
 }

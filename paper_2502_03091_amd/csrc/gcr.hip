@@ -26,6 +26,10 @@ namespace crk {
 namespace {
 
 constexpr int kT = 256;
+// Loads in flight per thread in the single-workgroup reductions (multidot
+// coefficients, convergence check): a few hundred rows per wavefront are
+// latency-bound, not bandwidth-bound.
+constexpr int kRedLoads = 32;
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -204,16 +208,17 @@ __global__ __launch_bounds__(kT) void multidot_reduce_kernel(const double* __res
   const int q = threadIdx.x & 63, g = threadIdx.x >> 6;
   double acc = 0;
   if (q < 2 * nj) {
-    // loads issued eight at a time, added in chunk order
-    for (int64_t c0 = g; c0 < nch; c0 += 8 * (kT / 64)) {
-      double v[8];
+    // loads issued kRedLoads at a time (the kernel is bound by their latency),
+    // added in chunk order
+    for (int64_t c0 = g; c0 < nch; c0 += kRedLoads * (kT / 64)) {
+      double v[kRedLoads];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < kRedLoads; ++u) {
         const int64_t c = c0 + int64_t(u) * (kT / 64);
         v[u] = c < nch ? partial[(c * nrhs + r) * (2 * kMaxBasis) + q] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < kRedLoads; ++u)
         if (c0 + int64_t(u) * (kT / 64) < nch) acc += v[u];
     }
   }
@@ -690,16 +695,16 @@ __global__ __launch_bounds__(kT) void check_kernel(const double* __restrict__ pa
     const int r = r0 + q;
     double acc = 0;
     if (r < nrhs) {
-      // loads issued eight at a time, added in chunk order
-      for (int64_t c0 = g; c0 < nch; c0 += 8 * (kT / 64)) {
-        double v[8];
+      // loads issued kRedLoads at a time, added in chunk order
+      for (int64_t c0 = g; c0 < nch; c0 += kRedLoads * (kT / 64)) {
+        double v[kRedLoads];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < kRedLoads; ++u) {
           const int64_t c = c0 + int64_t(u) * (kT / 64);
           v[u] = c < nch ? partial[c * nrhs + r] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < kRedLoads; ++u)
           if (c0 + int64_t(u) * (kT / 64) < nch) acc += v[u];
       }
     }
