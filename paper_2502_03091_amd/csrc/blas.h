@@ -31,11 +31,14 @@ void reduce_partials(const double* partial, int64_t nchunk, int nrhs, int nv, do
 void mr_alpha(const double* sums3, int nrhs, double2* alpha, hipStream_t st);
 
 // psi += alpha r; r -= alpha q (n entries per rhs; rhs-outer or rhs-inner layout).
+// update_r = false: psi only, for the last step of a smoother whose residual is
+// not used afterwards (q is then not read and r not written).
 void mr_update(int prec, void* psi, void* r, const void* q, const double2* alpha, int64_t n, int nrhs, bool rhs_inner,
-               hipStream_t st);
+               hipStream_t st, bool update_r = true);
 // The same update on the fine level with psi in FP32 and r, q in FP16 storage
 // (AoSoA fine fields of V sites, one scale per site and RHS; r is rescaled).
-void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st);
+void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st,
+                      bool update_r = true);
 
 // v[e*nrhs + r] *= f[r] for n entries per rhs (rhs-inner layout).
 void scale_rhs_inner(int prec, void* v, const double* f, int64_t n, int nrhs, hipStream_t st);

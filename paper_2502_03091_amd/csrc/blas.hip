@@ -164,7 +164,8 @@ __global__ void mr_alpha_kernel(const double* __restrict__ sums, int nrhs, doubl
 // as mr_update_kernel<float>, the new r stored with its site's new scale.
 __global__ __launch_bounds__(kT) void mr_update_h_kernel(float2* __restrict__ psi, FineView<CRK_FORM_FP16S> r,
                                                          FineView<CRK_FORM_FP16S> q,
-                                                         const double2* __restrict__ alpha, int64_t V, int nrhs) {
+                                                         const double2* __restrict__ alpha, int64_t V, int nrhs,
+                                                         int upd_r) {
   const int64_t Vp = pad_sites(V);
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= Vp * nrhs) return;
@@ -174,13 +175,17 @@ __global__ __launch_bounds__(kT) void mr_update_h_kernel(float2* __restrict__ ps
   const float2 a = make_float2(float(ad.x), float(ad.y));
   float2 rv[12], qv[12];
   r.load(rr, s, rv);
-  q.load(rr, s, qv);
   float2* pp = psi + aidx(rr, 0, s, Vp, 12);
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
     float2 p = pp[c * kVL];
     cfma(p, a, rv[c]);
     pp[c * kVL] = p;
+  }
+  if (!upd_r) return;
+  q.load(rr, s, qv);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
     const float2 qa = cmul(a, qv[c]);
     rv[c].x -= qa.x;
     rv[c].y -= qa.y;
@@ -194,7 +199,7 @@ __global__ __launch_bounds__(kT) void mr_update_kernel(typename C2<T>::t* __rest
                                                        typename C2<T>::t* __restrict__ r,
                                                        const typename C2<T>::t* __restrict__ q,
                                                        const double2* __restrict__ alpha, int64_t n, int nrhs,
-                                                       int rhs_inner) {
+                                                       int rhs_inner, int upd_r) {
   using CT = typename C2<T>::t;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n * nrhs) return;
@@ -205,6 +210,7 @@ __global__ __launch_bounds__(kT) void mr_update_kernel(typename C2<T>::t* __rest
   CT p = psi[i];
   cfma(p, a, rv);
   psi[i] = p;
+  if (!upd_r) return;
   CT nr = rv;
   const CT qa = cmul(a, q[i]);
   nr.x -= qa.x;
@@ -318,22 +324,25 @@ void mr_alpha(const double* sums3, int nrhs, double2* alpha, hipStream_t st) {
 }
 
 void mr_update(int prec, void* psi, void* r, const void* q, const double2* alpha, int64_t n, int nrhs, bool rhs_inner,
-               hipStream_t st) {
+               hipStream_t st, bool update_r) {
   const dim3 g(ceil_div(n * nrhs, kT));
   if (prec == CRK_FORM_FP64)
     hipLaunchKernelGGL(mr_update_kernel<double>, g, dim3(kT), 0, st, static_cast<double2*>(psi),
-                       static_cast<double2*>(r), static_cast<const double2*>(q), alpha, n, nrhs, int(rhs_inner));
+                       static_cast<double2*>(r), static_cast<const double2*>(q), alpha, n, nrhs, int(rhs_inner),
+                       int(update_r));
   else
     hipLaunchKernelGGL(mr_update_kernel<float>, g, dim3(kT), 0, st, static_cast<float2*>(psi),
-                       static_cast<float2*>(r), static_cast<const float2*>(q), alpha, n, nrhs, int(rhs_inner));
+                       static_cast<float2*>(r), static_cast<const float2*>(q), alpha, n, nrhs, int(rhs_inner),
+                       int(update_r));
   CRK_LAUNCH_CHECK();
 }
 
-void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st) {
+void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st,
+                      bool update_r) {
   if (V <= 0 || nrhs <= 0) return;
   FineView<CRK_FORM_FP16S> rv(r, V, nrhs), qv(const_cast<void*>(q), V, nrhs);
   hipLaunchKernelGGL(mr_update_h_kernel, dim3(ceil_div(pad_sites(V) * nrhs, kT)), dim3(kT), 0, st,
-                     static_cast<float2*>(psi), rv, qv, alpha, V, nrhs);
+                     static_cast<float2*>(psi), rv, qv, alpha, V, nrhs, int(update_r));
   CRK_LAUNCH_CHECK();
 }
 

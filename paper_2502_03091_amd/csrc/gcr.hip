@@ -57,11 +57,14 @@ constexpr int kDotGroup = 16;
 // partial[chunk][r][2*j + {0,1}] = chunk sum of conj(W_j) w.  G directions per
 // workgroup (4, 8 or 16, the smallest that holds the pass): fewer unused sums
 // keep fewer registers live and more wavefronts in flight; an entry's sum does
-// not depend on G.
+// not depend on G.  valid (optional): bit vbit0 + j of valid[r] set when
+// direction j belongs to RHS r's basis; the others are neither read nor summed
+// (their partials are 0, and their coefficients are zeroed when reduced).
 template <class C, int G>
 __global__ __launch_bounds__(kT) void multidot_kernel(const C* __restrict__ Wb, int64_t fstride, int nj,
                                                       const C* __restrict__ w, int64_t n, int nrhs, int64_t rs,
-                                                      int64_t es, int64_t chunk, double* __restrict__ partial) {
+                                                      int64_t es, int64_t chunk, double* __restrict__ partial,
+                                                      const uint32_t* __restrict__ valid, int vbit0) {
   __shared__ double sh[2 * G][4];
   const int r = blockIdx.y, j0 = blockIdx.z * G;
   const int64_t e0 = int64_t(blockIdx.x) * chunk, e1 = min(n, e0 + chunk);
@@ -71,19 +74,24 @@ __global__ __launch_bounds__(kT) void multidot_kernel(const C* __restrict__ Wb, 
   double acc[2 * G];
 #pragma unroll
   for (int q = 0; q < 2 * G; ++q) acc[q] = 0;
-  // members past the group's last direction issue no loads (the count is
-  // uniform over the workgroup, so the branches are too)
+  // members past the group's last direction, and directions outside this
+  // RHS's basis, issue no loads (both are uniform over the workgroup, whose RHS
+  // is blockIdx.y, so the branches are too)
   const int ng = min(G, nj - j0);
+  const uint32_t vm = valid ? valid[r] >> (vbit0 + j0) : ~0u;
+  bool use[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) use[g] = g < ng && ((vm >> g) & 1u);
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int64_t idx = int64_t(r) * rs + e * es;
     const C y = w[idx];
     C x[G];
 #pragma unroll
     for (int g = 0; g < G; ++g)
-      if (g < ng) x[g] = Wg[g][idx];
+      if (use[g]) x[g] = Wg[g][idx];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      if (g < ng) {
+      if (use[g]) {
         acc[2 * g] += double(x[g].x) * y.x + double(x[g].y) * y.y;
         acc[2 * g + 1] += double(x[g].x) * y.y - double(x[g].y) * y.x;
       }
@@ -787,17 +795,17 @@ int64_t shape_chunks(const FieldShape& f) { return gcr_partial_rows(f.n, f.es !=
 
 template <class C>
 void launch_multidot(int nc, int64_t nch, const FieldShape& f, const C* W, int64_t fstride, const C* w, int64_t chunk,
-                     double* partial, hipStream_t st) {
+                     double* partial, const uint32_t* valid, int vbit0, hipStream_t st) {
   auto grid = [&](int G) { return dim3(unsigned(nch), unsigned(f.nrhs), unsigned((nc + G - 1) / G)); };
   if (nc <= 4)
     hipLaunchKernelGGL((multidot_kernel<C, 4>), grid(4), dim3(kT), 0, st, W, fstride, nc, w, f.n, f.nrhs, f.rs, f.es,
-                       chunk, partial);
+                       chunk, partial, valid, vbit0);
   else if (nc <= 8)
     hipLaunchKernelGGL((multidot_kernel<C, 8>), grid(8), dim3(kT), 0, st, W, fstride, nc, w, f.n, f.nrhs, f.rs, f.es,
-                       chunk, partial);
+                       chunk, partial, valid, vbit0);
   else
     hipLaunchKernelGGL((multidot_kernel<C, 16>), grid(16), dim3(kT), 0, st, W, fstride, nc, w, f.n, f.nrhs, f.rs,
-                       f.es, chunk, partial);
+                       f.es, chunk, partial, valid, vbit0);
 }
 }  // namespace
 
@@ -831,10 +839,10 @@ void gcr_multidot(int prec, const void* W, int64_t fstride, int nj, const void* 
                          nc, static_cast<const float2*>(w), f.n, f.nrhs, f.rs, f.es, partial);
     else if (prec == CRK_FORM_FP64)
       launch_multidot<double2>(nc, nch, f, static_cast<const double2*>(Wj), fstride, static_cast<const double2*>(w),
-                               chunk, partial, st);
+                               chunk, partial, valid, j0, st);
     else
       launch_multidot<float2>(nc, nch, f, static_cast<const float2*>(Wj), fstride, static_cast<const float2*>(w),
-                              chunk, partial, st);
+                              chunk, partial, valid, j0, st);
     CRK_LAUNCH_CHECK();
     hipLaunchKernelGGL(multidot_reduce_kernel, dim3(unsigned(f.nrhs)), dim3(kT), 0, st, partial, nch, f.nrhs, j0, nc,
                        valid, coef);

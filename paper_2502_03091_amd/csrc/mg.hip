@@ -243,7 +243,8 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
         rhs_dot(form, q.p, r.p, n, mm, rs, es, partial.as<double>(), sums.as<double>(), st);
       }
       mr_alpha(sums.as<double>(), mm, alpha.as<double2>(), st);
-      mr_update(form, pc, r.p, q.p, alpha.as<double2>(), n, mm, inner, st);
+      // the residual after the last sweep is not used: that update skips it
+      mr_update(form, pc, r.p, q.p, alpha.as<double2>(), n, mm, inner, st, it + 1 < p.n_smooth[l]);
     }
   }
   ev.mark(1, st);

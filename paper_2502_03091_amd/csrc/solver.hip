@@ -175,7 +175,7 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs
       level_apply(H, 0, CRK_FORM_FP16S, rhoh, qh, nrhs, st, s0.partial);
       reduce_partials(s0.partial, wilson_partial_blocks(V0), nrhs, 3, s0.sums3, st);
       mr_alpha(s0.sums3, nrhs, s0.a, st);
-      mr_update_fine_h(eout, rhoh, qh, s0.a, V0, nrhs, st);
+      mr_update_fine_h(eout, rhoh, qh, s0.a, V0, nrhs, st, it + 1 < p.nu_post);  // last step: e only
     }
     return;
   }
@@ -197,7 +197,7 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs
       rhs_dot(prec, q, rho, f.n, nrhs, f.rs, f.es, s.partial, s.sums3, st);
     }
     mr_alpha(s.sums3, nrhs, s.a, st);
-    mr_update(prec, eout, rho, q, s.a, f.n, nrhs, l > 0, st);
+    mr_update(prec, eout, rho, q, s.a, f.n, nrhs, l > 0, st, it + 1 < p.nu_post);  // last step: e only
   }
 }
 

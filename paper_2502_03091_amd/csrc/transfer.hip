@@ -43,27 +43,48 @@ __global__ __launch_bounds__(kT) void restrict_lds_kernel(TransferGeom g, const 
   const C* Pp = P + int64_t(pair) * k * nr;
   const int64_t jp = g.pos_c ? g.pos_c[j] : j;
   const int q = threadIdx.x % kRhsChunk, i0 = threadIdx.x / kRhsChunk, i1 = i0 + 16;
+  // The chunk after the current one is loaded into registers while the current
+  // one is multiplied (each thread stages the same entries of every chunk).
+  constexpr int kPL = 32 * kRowChunk / kT, kVL2 = kRhsChunk * kRowChunk / kT;
+  static_assert(32 * kRowChunk % kT == 0 && kRhsChunk * kRowChunk % kT == 0, "restriction staging");
+  C pn[kPL], vn[kVL2];
+  auto load_chunk = [&](int c0, int r0) {
+#pragma unroll
+    for (int u = 0; u < kPL; ++u) {
+      const int e = int(threadIdx.x) + u * kT, i = e / kRowChunk, rr = e % kRowChunk;
+      pn[u] = (i < k && c0 + rr < nr) ? Pp[int64_t(i) * nr + c0 + rr] : C{0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < kVL2; ++u) {
+      const int e = int(threadIdx.x) + u * kT, qq = e / kRowChunk, rr = e % kRowChunk, rho = c0 + rr;
+      C val = C{0, 0};
+      if (rho < nr && r0 + qq < nrhs) {
+        const int cp = rho / g.nb, l = rho % g.nb;
+        const int64_t site = j * g.nb + l;
+        const int r = r0 + qq;
+        val = v[g.aosoa ? aidx(r, alpha * g.h + cp, site, g.Vp, g.ncomp)
+                        : int64_t(r) * g.vr + int64_t(alpha * g.h + cp) * g.vc + site * g.vs];
+      }
+      vn[u] = val;
+    }
+  };
   for (int r0 = 0; r0 < nrhs; r0 += kRhsChunk) {
     C a0 = C{0, 0}, a1 = C{0, 0};
+    load_chunk(0, r0);
     for (int c0 = 0; c0 < nr; c0 += kRowChunk) {
       __syncthreads();
-      for (int e = threadIdx.x; e < 32 * kRowChunk; e += kT) {
-        const int i = e / kRowChunk, rr = e % kRowChunk;
-        Ps[i][rr] = (i < k && c0 + rr < nr) ? Pp[int64_t(i) * nr + c0 + rr] : C{0, 0};
+#pragma unroll
+      for (int u = 0; u < kPL; ++u) {
+        const int e = int(threadIdx.x) + u * kT;
+        Ps[e / kRowChunk][e % kRowChunk] = pn[u];
       }
-      for (int e = threadIdx.x; e < kRhsChunk * kRowChunk; e += kT) {
-        const int qq = e / kRowChunk, rr = e % kRowChunk, rho = c0 + rr;
-        C val = C{0, 0};
-        if (rho < nr && r0 + qq < nrhs) {
-          const int cp = rho / g.nb, l = rho % g.nb;
-          const int64_t site = j * g.nb + l;
-          const int r = r0 + qq;
-          val = v[g.aosoa ? aidx(r, alpha * g.h + cp, site, g.Vp, g.ncomp)
-                          : int64_t(r) * g.vr + int64_t(alpha * g.h + cp) * g.vc + site * g.vs];
-        }
-        Vs[rr][qq] = val;
+#pragma unroll
+      for (int u = 0; u < kVL2; ++u) {
+        const int e = int(threadIdx.x) + u * kT;
+        Vs[e % kRowChunk][e / kRowChunk] = vn[u];
       }
       __syncthreads();
+      if (c0 + kRowChunk < nr) load_chunk(c0 + kRowChunk, r0);
 #pragma unroll 8
       for (int rr = 0; rr < kRowChunk; ++rr) {
         const C x = Vs[rr][q];
