@@ -47,6 +47,14 @@ void gcr_update_lazy(int prec, void* w, void* r, const double* dpart, int64_t dn
 // chunks whatever the RHS count; returns their number of rows (gcr_check's
 // partial_rows).
 bool gcr_one_pass_shape(const FieldShape& f);
+// One-pass step on rhs-outer fields over a ring of nj (>= 0) stored directions
+// (summed from slot j_first on, oldest first; zero coefficients skipped):
+// w^ = w - sum c_j W_j with ||w^||^2 = ||w||^2 - sum |c_j|^2 and
+// <w^, r> = <w, r> from dpart (the dots of the unmodified w), w <- w^/||w^||,
+// r -= a w, ||r||^2 reduced into rn2 (if not NULL); hinv, ha as gcr_update_lazy.
+void gcr_gs_update_ring(int prec, const void* W, int64_t fstride, int nj, int j_first, void* w, void* r,
+                        const double2* coef, const double* dpart, int64_t dnch, const int* active, int* breakdown,
+                        const FieldShape& f, double* partial, double* rn2, double* hinv, double2* ha, hipStream_t st);
 int64_t gcr_gs_update(int prec, const void* W, int64_t fstride, int nj, void* w, void* r, const double2* coef,
                    const double* dpart, int64_t dnch, const int* active, int* breakdown, const FieldShape& f,
                    double* partial, double* hinv, double2* ha, hipStream_t st);

@@ -357,6 +357,110 @@ __global__ __launch_bounds__(kT) void update_fused_kernel(C* __restrict__ w, C* 
   if (threadIdx.x == 0) partial[int64_t(blockIdx.x) * nrhs + r] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// One-pass step of the outer solve on rhs-outer fields whose stored
+// directions sit in a ring (the formulas of gs_update_rg_kernel below):
+// ||w^||^2 = ||w||^2 - sum_j |c_j|^2 and <w^, r> = <w, r> from the multidot
+// coefficients and the dots of the unmodified w, then one pass forms
+// w^ = w - sum_j c_j W_j (the ring from slot j_first on, oldest first; slots
+// with a zero coefficient, outside the RHS's basis, are not read: the same
+// sum, in the same order, as multiaxpy_kernel), stores w^/||w^|| and updates
+// r -= a w^/||w^|| with the ||r||^2 partials.  Workgroup per (chunk, RHS):
+// every workgroup of RHS r adds the dot partials and the coefficients of its
+// RHS in the same order, so all of them use the same scalars.
+template <class C>
+__global__ __launch_bounds__(kT) void gs_update_ring_kernel(
+    const C* __restrict__ Wb, int64_t fstride, int nj, int j_first, C* __restrict__ w, C* __restrict__ res,
+    const double2* __restrict__ coef, const double* __restrict__ dpart, int64_t dnch, const int* __restrict__ active,
+    int* __restrict__ breakdown, int64_t n, int nrhs, int64_t rs, int64_t chunk, double* __restrict__ partial,
+    double* __restrict__ hinv, double2* __restrict__ ha, double rel) {
+  __shared__ double sh[4];
+  __shared__ double scal[3];
+  __shared__ double2 cf[kMaxCoef];
+  __shared__ int slot[kMaxCoef];
+  __shared__ int nuse;
+  using T = decltype(C::x);
+  const int r = blockIdx.y;
+  if (threadIdx.x < 64) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int64_t c = threadIdx.x; c < dnch; c += 64) {
+      const double* p = dpart + (c * nrhs + r) * 3;
+      s0 += p[0];
+      s1 += p[1];
+      s2 += p[2];
+    }
+    s0 = wsum(s0);
+    s1 = wsum(s1);
+    s2 = wsum(s2);
+    if (threadIdx.x == 0) {
+      scal[0] = s0;
+      scal[1] = s1;
+      scal[2] = s2;
+      int m = 0;
+      for (int tt = 0; tt < nj; ++tt) {
+        const int j = tt + j_first < nj ? tt + j_first : tt + j_first - nj;
+        const double2 cd = coef[r * kMaxCoef + j];
+        if (cd.x != 0.0 || cd.y != 0.0) {
+          cf[m] = cd;
+          slot[m] = j;
+          ++m;
+        }
+      }
+      nuse = m;
+    }
+  }
+  __syncthreads();
+  const int m = nuse;
+  double c2 = 0;
+  for (int u = 0; u < m; ++u) c2 += cf[u].x * cf[u].x + cf[u].y * cf[u].y;
+  const double s2 = scal[2], hw2 = s2 - c2;
+  const bool act0 = active[r] != 0;
+  const bool ok = act0 && s2 > 0.0 && hw2 > rel * s2 && isfinite(hw2);
+  const double nw = sqrt(hw2), inv = ok ? 1.0 / nw : 0.0;
+  const double2 a = ok ? make_double2(scal[0] / nw, scal[1] / nw) : make_double2(0, 0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (breakdown) breakdown[r] = act0 && !ok;
+    hinv[r] = inv;
+    ha[r] = a;
+  }
+  const T s = T(inv);
+  const C ar = mk<C>(T(a.x), T(a.y));
+  const int64_t e0 = int64_t(blockIdx.x) * chunk, e1 = min(n, e0 + chunk);
+  double racc = 0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int64_t idx = int64_t(r) * rs + e;
+    C ww = w[idx];
+    if (ok) {
+      constexpr int kU = 4;  // directions whose loads are issued together
+      for (int u0 = 0; u0 < m; u0 += kU) {
+        C wl[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) wl[u] = Wb[int64_t(slot[min(u0 + u, m - 1)]) * fstride + idx];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          if (u0 + u < m) {
+            const C c = mk<C>(T(-cf[u0 + u].x), T(-cf[u0 + u].y));
+            cfma(ww, c, wl[u]);
+          }
+        }
+      }
+    }
+    const C wn = cscale(ww, s);
+    w[idx] = wn;
+    C rr = res[idx];
+    if (ok) {
+      const C aw = cmul(ar, wn);
+      rr.x -= aw.x;
+      rr.y -= aw.y;
+      res[idx] = rr;
+    }
+    racc += double(rr.x) * rr.x + double(rr.y) * rr.y;
+  }
+  const double t = wsum(racc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[int64_t(blockIdx.x) * nrhs + r] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
 // update_fused_kernel for rhs-inner fields: workgroup per (chunk, group of up
 // to 16 RHS), thread (l, r) with r fastest (coalesced), entries l, l + 64, ...
 // of the chunk per thread; every sum over lanes runs in lane order, so an RHS's
@@ -915,6 +1019,25 @@ int64_t gcr_gs_update(int prec, const void* W, int64_t fstride, int nj, void* w,
                        f.nrhs, partial, hinv, ha, 1e-6);
   CRK_LAUNCH_CHECK();
   return nch;
+}
+
+void gcr_gs_update_ring(int prec, const void* W, int64_t fstride, int nj, int j_first, void* w, void* r,
+                        const double2* coef, const double* dpart, int64_t dnch, const int* active, int* breakdown,
+                        const FieldShape& f, double* partial, double* rn2, double* hinv, double2* ha, hipStream_t st) {
+  CRK_REQUIRE(f.es == 1, "one-pass ring step: rhs-outer fields only");
+  CRK_REQUIRE(nj >= 0 && nj <= kMaxCoef && j_first >= 0 && (nj == 0 || j_first < nj), "one-pass ring step: bad ring");
+  const int64_t nch = shape_chunks(f), chunk = chunk_for_shape(f.n, false);
+  const dim3 g = dim3(unsigned(nch), unsigned(f.nrhs));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(gs_update_ring_kernel<double2>, g, dim3(kT), 0, st, static_cast<const double2*>(W), fstride,
+                       nj, j_first, static_cast<double2*>(w), static_cast<double2*>(r), coef, dpart, dnch, active,
+                       breakdown, f.n, f.nrhs, f.rs, chunk, partial, hinv, ha, 1e-13);
+  else
+    hipLaunchKernelGGL(gs_update_ring_kernel<float2>, g, dim3(kT), 0, st, static_cast<const float2*>(W), fstride,
+                       nj, j_first, static_cast<float2*>(w), static_cast<float2*>(r), coef, dpart, dnch, active,
+                       breakdown, f.n, f.nrhs, f.rs, chunk, partial, hinv, ha, 1e-6);
+  CRK_LAUNCH_CHECK();
+  if (rn2) reduce_partials(partial, nch, f.nrhs, 1, rn2, st);
 }
 
 void gcr_lazy_solution(int prec, const void* Z, int64_t fstride, int K, void* x, const double2* hcoef,

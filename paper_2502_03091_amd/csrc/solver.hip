@@ -393,18 +393,24 @@ int OuterSolver::step() {
   // and normalised; c_ij, 1/||w_i|| and a_i are recorded per ring slot and the
   // solution is brought up to date (materialize) whenever it is needed.
   double2* ci = s.hcoef + size_t(ring_) * cap_ * kMaxCoef;
+  std::vector<uint32_t> valid(wd, 0);  // read by a copy on the stream: lives until the sync below
   if (used_ > 1) {
-    std::vector<uint32_t> valid(wd, 0);
     for (int r = 0; r < wd; ++r)
       for (int a = 1; a <= nbasis_[r]; ++a) valid[r] |= 1u << ((ring_ - a + nslots_) % nslots_);
     CRK_HIP(hipMemcpyAsync(s.valid, valid.data(), sizeof(uint32_t) * wd, hipMemcpyHostToDevice, st_));
     gcr_multidot(CRK_FORM_FP64, W, fcap, used_, wi, f, s.partial, s.valid, ci, st_);
-    gcr_multiaxpy_w(CRK_FORM_FP64, W, fcap, used_, (ring_ + 1) % used_, wi, ci, f, st_);
-    CRK_HIP(hipStreamSynchronize(st_));  // valid lives on the host stack
   }
+  // one pass over the ring: w^ = w - sum c_j W_j with its norm and <w^, r>
+  // from the coefficients and the dots of the unmodified w (r is orthogonal to
+  // every direction of its basis), normalised, and the residual update.  The
+  // first step of the ring runs the same kernel with no stored direction, so
+  // that an RHS's first step has the same bits whether or not it joins a ring
+  // that other RHS already fill.
   const int64_t dn = rhs_dot_launch(CRK_FORM_FP64, wi, o.r.p, f.n, wd, f.rs, f.es, s.dpart, st_);
-  gcr_update_lazy(CRK_FORM_FP64, wi, o.r.p, s.dpart, dn, s.active, s.breakdown, f, s.partial, s.rn2,
-                  s.hinv + size_t(ring_) * cap_, s.ha + size_t(ring_) * cap_, st_);
+  gcr_gs_update_ring(CRK_FORM_FP64, W, fcap, used_ > 1 ? used_ : 0, used_ > 1 ? (ring_ + 1) % used_ : 0, wi, o.r.p,
+                     ci, s.dpart, dn, s.active, s.breakdown, f, s.partial, s.rn2, s.hinv + size_t(ring_) * cap_,
+                     s.ha + size_t(ring_) * cap_, st_);
+  if (used_ > 1) CRK_HIP(hipStreamSynchronize(st_));  // valid lives on the host stack
   std::vector<double> rn2(wd);
   std::vector<int> bd(wd);
   CRK_HIP(hipMemcpyAsync(rn2.data(), s.rn2, sizeof(double) * wd, hipMemcpyDeviceToHost, st_));
