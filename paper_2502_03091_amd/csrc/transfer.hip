@@ -23,19 +23,27 @@ constexpr int kT = 256;
 
 // Restriction as a blocked product out = P_{j,alpha}^dag v over row chunks of
 // 64: the workgroup stages the chunk of P (k x 64) and of v (64 x 16 RHS) in
-// LDS with coalesced loads, then thread (i-pair, rhs) accumulates its two
-// outputs over the chunk.  Rows are summed in order (chunk by chunk), so every
-// output has one fixed summation order.
+// LDS with coalesced loads (the next chunk's loads in flight while the current
+// one is multiplied), then either thread (i-pair, rhs) accumulates its two
+// outputs over the chunk (FMA form), or (MF, FP32) wavefront w multiplies rows
+// 16w .. 16w+15 of the chunk on the matrix cores: two 16-row tiles of conj(P)
+// times the 16-RHS tile, v_mfma_f32_16x16x4f32 with four real products per
+// complex one, and the four wavefronts' tiles are added in LDS in wavefront
+// order.  Either way every output has one fixed summation order.
 constexpr int kRowChunk = 64;
 constexpr int kRhsChunk = 16;
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <class T>
+template <class T, bool MF>
 __global__ __launch_bounds__(kT) void restrict_lds_kernel(TransferGeom g, const typename cplx_t<T>::type* __restrict__ P,
                                                           const typename cplx_t<T>::type* __restrict__ v,
                                                           typename cplx_t<T>::type* __restrict__ out, int nrhs) {
   using C = typename cplx_t<T>::type;
+  static_assert(!MF || sizeof(T) == 4, "matrix-core restriction: FP32 only");
   __shared__ C Ps[32][kRowChunk + 1];
   __shared__ C Vs[kRowChunk][kRhsChunk];
+  // partial tiles of wavefronts 1..3: [wave-1][row tile][re, im][accumulator entry][lane]
+  __shared__ float red[MF ? kT / 64 - 1 : 1][2][2][4][MF ? 64 : 1];
   const int pair = blockIdx.x;
   const int64_t j = pair >> 1;
   const int alpha = pair & 1;
@@ -68,8 +76,12 @@ __global__ __launch_bounds__(kT) void restrict_lds_kernel(TransferGeom g, const 
       vn[u] = val;
     }
   };
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int r0 = 0; r0 < nrhs; r0 += kRhsChunk) {
     C a0 = C{0, 0}, a1 = C{0, 0};
+    floatx4 are0[2], are1[2], aim0[2], aim1[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) are0[mt] = are1[mt] = aim0[mt] = aim1[mt] = floatx4{0, 0, 0, 0};
     load_chunk(0, r0);
     for (int c0 = 0; c0 < nr; c0 += kRowChunk) {
       __syncthreads();
@@ -85,14 +97,60 @@ __global__ __launch_bounds__(kT) void restrict_lds_kernel(TransferGeom g, const 
       }
       __syncthreads();
       if (c0 + kRowChunk < nr) load_chunk(c0 + kRowChunk, r0);
+      if constexpr (MF) {
+        // lane (row = lane % 16, kq = lane / 16): A = conj(P)[row][k], B = v[k][rhs = lane % 16],
+        // k = 16 wv + 4 ks + kq; conj(P) v = (Pr Vr + Pi Vi) + i (Pr Vi - Pi Vr)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int rr = 16 * wv + 4 * ks + (lane >> 4);
+          const C b = Vs[rr][lane & 15];
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            const C a = Ps[16 * mt + (lane & 15)][rr];
+            are0[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, are0[mt], 0, 0, 0);
+            aim0[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, aim0[mt], 0, 0, 0);
+            are1[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, are1[mt], 0, 0, 0);
+            aim1[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.x, aim1[mt], 0, 0, 0);
+          }
+        }
+      } else {
 #pragma unroll 8
-      for (int rr = 0; rr < kRowChunk; ++rr) {
-        const C x = Vs[rr][q];
-        cfmac(a0, Ps[i0][rr], x);
-        cfmac(a1, Ps[i1][rr], x);
+        for (int rr = 0; rr < kRowChunk; ++rr) {
+          const C x = Vs[rr][q];
+          cfmac(a0, Ps[i0][rr], x);
+          cfmac(a1, Ps[i1][rr], x);
+        }
       }
     }
-    if (r0 + q < nrhs) {
+    if constexpr (MF) {
+      if (wv > 0) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            red[wv - 1][mt][0][e][lane] = are0[mt][e] + are1[mt][e];
+            red[wv - 1][mt][1][e][lane] = aim0[mt][e] + aim1[mt][e];
+          }
+      }
+      __syncthreads();
+      if (wv == 0) {
+        const int col = lane & 15;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            // accumulator entry e of lane: row 4 (lane / 16) + e of the tile, column lane % 16
+            float re = are0[mt][e] + are1[mt][e], im = aim0[mt][e] + aim1[mt][e];
+#pragma unroll
+            for (int w = 0; w < kT / 64 - 1; ++w) {
+              re += red[w][mt][0][e][lane];
+              im += red[w][mt][1][e][lane];
+            }
+            const int i = 16 * mt + 4 * (lane >> 4) + e;
+            if (i < k && r0 + col < nrhs) out[(jp * N + alpha * k + i) * nrhs + r0 + col] = C{re, im};
+          }
+      }
+    } else if (r0 + q < nrhs) {
       if (i0 < k) out[(jp * N + alpha * k + i0) * nrhs + r0 + q] = a0;
       if (i1 < k) out[(jp * N + alpha * k + i1) * nrhs + r0 + q] = a1;
     }
@@ -160,10 +218,10 @@ void transfer_restrict(int prec, const TransferGeom& g, const void* P, const voi
   CRK_REQUIRE(g.k >= 1 && g.k <= 32, "restriction: k must be in [1, 32]");
   const dim3 grid = dim3(unsigned(2 * g.nblocks));
   if (prec == CRK_FORM_FP64)
-    hipLaunchKernelGGL(restrict_lds_kernel<double>, grid, dim3(kT), 0, st, g, static_cast<const double2*>(P),
+    hipLaunchKernelGGL((restrict_lds_kernel<double, false>), grid, dim3(kT), 0, st, g, static_cast<const double2*>(P),
                        static_cast<const double2*>(fine), static_cast<double2*>(coarse), nrhs);
   else
-    hipLaunchKernelGGL(restrict_lds_kernel<float>, grid, dim3(kT), 0, st, g, static_cast<const float2*>(P),
+    hipLaunchKernelGGL((restrict_lds_kernel<float, true>), grid, dim3(kT), 0, st, g, static_cast<const float2*>(P),
                        static_cast<const float2*>(fine), static_cast<float2*>(coarse), nrhs);
   CRK_LAUNCH_CHECK();
 }
