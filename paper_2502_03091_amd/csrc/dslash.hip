@@ -595,12 +595,13 @@ __device__ __forceinline__ void tile_hop(const float2 (*sp)[kTileSlots], int slo
 
 // With the clover term the site blocks add to the live registers: that variant
 // runs one workgroup per CU (up to 512 registers) instead of spilling.
-template <int FORM, bool CL>  // FP32, or FP16S storage (half spinors with a per-site scale, half links) in FP32 arithmetic
+template <int FORM, bool CL, bool SUB = false>  // FP32, or FP16S storage (half spinors with a per-site scale, half links) in FP32 arithmetic
 __global__ __launch_bounds__(kTile, CL ? 1 : 2) void wilson_tile_kernel(FineView<FORM> in, FineView<FORM> out,
                                                                GaugeView<FORM> U,
                                                                const int* __restrict__ nbr, int64_t V, int nrhs,
                                                                float diag, float4 hw, double* __restrict__ partial,
-                                                               int swz, const float2* __restrict__ clv, float csign) {
+                                                               int swz, const float2* __restrict__ clv, float csign,
+                                                               const float2* __restrict__ sub) {
   __shared__ float2 sp[12][kTileSlots];  // [component][slot], 72 KiB
   const int64_t blk = swz ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
   const int l = threadIdx.x, lane = l & 63, wid = l >> 6;
@@ -667,11 +668,18 @@ __global__ __launch_bounds__(kTile, CL ? 1 : 2) void wilson_tile_kernel(FineView
       // read as face neighbours
       typedef float v2f __attribute__((ext_vector_type(2)));
       float2* po = out.data + aidx(r, 0, s, out.Vp, 12);
+      // sub (FP32 only): out = sub - D in, the residual of the next step formed here
+      const float2* pb = sub + aidx(r, 0, s, out.Vp, 12);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         v2f v;
         v.x = acc[c].x;
         v.y = acc[c].y;
+        if constexpr (SUB) {
+          const float2 b = pb[c * kVL];
+          v.x = b.x - v.x;
+          v.y = b.y - v.y;
+        }
         __builtin_nontemporal_store(v, reinterpret_cast<v2f*>(po + c * kVL));
       }
     } else {
@@ -714,14 +722,21 @@ void launch_wilson_tile(const WilsonArgs& a, hipStream_t st) {
   FineView<FORM> in(const_cast<void*>(a.in), a.V, a.nrhs), out(a.out, a.V, a.nrhs);
   GaugeView<FORM> U{static_cast<const typename Prec<FORM>::store*>(a.gauge), pad_sites(a.V)};
   const float4 hw = make_float4(float(a.hw[0]), float(a.hw[1]), float(a.hw[2]), float(a.hw[3]));
+  CRK_REQUIRE(a.sub == nullptr || (FORM == CRK_FORM_FP32 && a.partial == nullptr && a.clover == nullptr),
+              "tile dslash: b - D x only in FP32, without fused sums or the clover term");
+  const float2* sub = static_cast<const float2*>(a.sub);
   if (a.clover)
     hipLaunchKernelGGL((wilson_tile_kernel<FORM, true>), dim3(unsigned(nblk)), dim3(kTile), 0, st, in, out, U, a.nbr,
                        a.V, a.nrhs, float(a.diag), hw, a.partial, a.swizzle, static_cast<const float2*>(a.clover),
-                       float(a.clover_sign));
+                       float(a.clover_sign), sub);
+  else if (sub)
+    hipLaunchKernelGGL((wilson_tile_kernel<FORM, false, FORM == CRK_FORM_FP32>), dim3(unsigned(nblk)), dim3(kTile), 0,
+                       st, in, out, U, a.nbr, a.V, a.nrhs, float(a.diag), hw, a.partial, a.swizzle,
+                       static_cast<const float2*>(a.clover), float(a.clover_sign), sub);
   else
     hipLaunchKernelGGL((wilson_tile_kernel<FORM, false>), dim3(unsigned(nblk)), dim3(kTile), 0, st, in, out, U, a.nbr,
                        a.V, a.nrhs, float(a.diag), hw, a.partial, a.swizzle, static_cast<const float2*>(a.clover),
-                       float(a.clover_sign));
+                       float(a.clover_sign), sub);
   CRK_LAUNCH_CHECK();
 }
 }  // namespace
@@ -748,6 +763,7 @@ void wilson_apply(const WilsonArgs& a_in, hipStream_t st) {
     return;
   }
   const int R = a.rhs_per_thread < a.nrhs ? a.rhs_per_thread : a.nrhs;
+  CRK_REQUIRE(a.sub == nullptr || (a.tile4 && a.form == CRK_FORM_FP32), "dslash: b - D x only with the FP32 tile");
   if (a.tile4 && a.form == CRK_FORM_FP32) { launch_wilson_tile<CRK_FORM_FP32>(a, st); return; }
   if (a.tile4 && a.form == CRK_FORM_FP16S) { launch_wilson_tile<CRK_FORM_FP16S>(a, st); return; }
   if (a.form == CRK_FORM_FP32) { launch_wilson_rhsloop<CRK_FORM_FP32>(a, st); return; }

@@ -49,6 +49,9 @@ struct WilsonArgs {
   // Storage form of `in` when it is not `form`: only FP32 input to the FP64
   // operator (values widened exactly, FP64 arithmetic and output).  -1: `form`.
   int in_form = -1;
+  // When set (FP32 on 4^4 blocks, no fused sums): out = sub - D in, sub a field
+  // in the layout of out.  Other operators leave it to the caller (level_apply).
+  const void* sub = nullptr;
 };
 void wilson_apply(const WilsonArgs& a, hipStream_t st);
 int64_t wilson_partial_blocks(int64_t V);

@@ -83,6 +83,9 @@ void mg_destroy(Hierarchy* H);   // drops one reference; frees at zero
 // in_form >= 0: storage of `in` when it is not `form` (level 0 only: FP32 input to the FP64 operator).
 void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int nrhs, hipStream_t st,
                  double* partial = nullptr, bool negate = false, void* copy = nullptr, int in_form = -1);
+// out = b - D_l in (the residual of `in` for the right-hand sides b, in the level's layout).
+void level_residual(Hierarchy* H, int l, int form, const void* in, const void* b, void* out, int nrhs,
+                    hipStream_t st);
 void level_restrict(Hierarchy* H, int l, int form, const void* fine, void* coarse, int nrhs, hipStream_t st);
 void level_prolong(Hierarchy* H, int l, int form, const void* coarse, void* fine, int nrhs, bool add, hipStream_t st);
 

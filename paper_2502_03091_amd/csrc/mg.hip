@@ -14,6 +14,7 @@
 #include "blas.h"
 #include "coarse.h"
 #include "galerkin.h"
+#include "gcr.h"
 #include "transfer.h"
 
 namespace crk {
@@ -108,6 +109,34 @@ void level_apply(Hierarchy* H, int l, int form, const void* in, void* out, int n
     CRK_REQUIRE(partial == nullptr, "coarse apply has no fused reduction");
     coarse_apply(form, c.N, c.links[form].p, in, out, c.geo.nbr.as<int>(), c.V, nrhs, negate, st, copy);
   }
+}
+
+void level_residual(Hierarchy* H, int l, int form, const void* in, const void* b, void* out, int nrhs,
+                    hipStream_t st) {
+  const Geometry& g = H->fine_geo;
+  const bool tile4 = g.blocked && g.block[0] == 4 && g.block[1] == 4 && g.block[2] == 4 && g.block[3] == 4;
+  if (l == 0 && form == CRK_FORM_FP32 && tile4 && H->fine_clover[form].p == nullptr) {
+    // the FP32 tile operator forms b - D in in its store (one pass fewer over
+    // the fine field than the operator followed by b - out)
+    Lattice* L = H->lat;
+    WilsonArgs a{};
+    a.form = form;
+    a.in = in;
+    a.out = out;
+    a.gauge = H->fine_gauge[form].p;
+    a.nbr = g.nbr.as<int>();
+    a.V = g.V;
+    a.nrhs = nrhs;
+    a.diag = L->diag();
+    L->hw(a.hw);
+    a.tile4 = 1;
+    a.sub = b;
+    wilson_apply(a, st);
+    return;
+  }
+  level_apply(H, l, form, in, out, nrhs, st);
+  const FieldShape f = l == 0 ? fine_shape(H->V(0), nrhs) : coarse_shape(H->V(l), H->N(l), nrhs);
+  field_axpby_to(form == CRK_FORM_FP64 ? CRK_FORM_FP64 : CRK_FORM_FP32, out, b, out, -1.0, 1.0, f.total(), st);
 }
 
 static TransferGeom transfer_geom(Hierarchy* H, int l, int nrhs) {

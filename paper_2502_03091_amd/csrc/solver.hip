@@ -162,13 +162,10 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs
     // the MR residual rho and q = D rho are held in FP16 storage (one scale per
     // site and RHS) and the fine operator reads and writes them in that form.
     const int64_t V0 = H->V(0);
-    const FieldShape f0 = shape(H, 0, nrhs);
-    void* q32 = w.fw.q.p;
     void* r32 = w.fw.rho.p;
-    level_apply(H, 0, CRK_FORM_FP32, eout, q32, nrhs, st);
-    field_axpby_to(CRK_FORM_FP32, q32, rin, r32, -1.0, 1.0, f0.total(), st);  // r32 = rin - D e
-    void* rhoh = w.fw.q.p;  // q32 is no longer needed
-    void* qh = w.fw.rho.p;  // nor is r32 once converted (stream order)
+    level_residual(H, 0, CRK_FORM_FP32, eout, rin, r32, nrhs, st);  // r32 = rin - D e
+    void* rhoh = w.fw.q.p;
+    void* qh = w.fw.rho.p;  // r32 is no longer needed once converted (stream order)
     field_convert(CRK_FORM_FP32, r32, CRK_FORM_FP16S, rhoh, V0, 12, nrhs, st);
     GcrScalars& s0 = w.ow.s;
     for (int it = 0; it < p.nu_post; ++it) {
@@ -186,8 +183,7 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs
   GcrScalars& s = l == 0 ? w.ow.s : w.lv[l].s;
   // the scalars of level l are idle while its K-cycle runs (the cycle is called
   // between the solver's kernel phases); only sums3/partial/a are reused here.
-  level_apply(H, l, opf, eout, q, nrhs, st);
-  field_axpby_to(prec, q, rin, rho, -1.0, 1.0, f.total(), st);  // rho = rin - D e
+  level_residual(H, l, opf, eout, rin, rho, nrhs, st);  // rho = rin - D e
   for (int it = 0; it < p.nu_post; ++it) {
     if (l == 0) {
       level_apply(H, 0, opf, rho, q, nrhs, st, s.partial);
