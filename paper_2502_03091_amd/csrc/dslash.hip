@@ -362,13 +362,16 @@ __device__ __forceinline__ void load_as(const FineView<FIN>& in, int64_t r, int6
 }
 
 // Both hops along MU for one RHS: the spin-MU components of the partial result
-// are returned in mine[], the other nine go to their owners' exchange slots.
+// are returned in m0, m1, m2 (three scalars, not an array: an array written in
+// the four branches of the caller's switch was kept on the stack), the other
+// nine go to their owners' exchange slots.
 template <int FORM, int FIN, int MU>
 __device__ __forceinline__ void hop_pair(const FineView<FIN>& in, int r, int64_t yf, int64_t yb,
                                          const typename Prec<FORM>::cx (&uf)[9],
                                          const typename Prec<FORM>::cx (&ub)[9], typename Prec<FORM>::real coef,
                                          typename Prec<FORM>::cx (*xch)[3][kVL], int lane,
-                                         typename Prec<FORM>::cx (&mine)[3]) {
+                                         typename Prec<FORM>::cx& m0, typename Prec<FORM>::cx& m1,
+                                         typename Prec<FORM>::cx& m2) {
   using C = typename Prec<FORM>::cx;
   C acc[12];
 #pragma unroll
@@ -386,7 +389,11 @@ __device__ __forceinline__ void hop_pair(const FineView<FIN>& in, int r, int64_t
   for (int o = 0; o < 4; ++o) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      if (o == MU) mine[c] = acc[3 * o + c];
+      if (o == MU) {
+        if (c == 0) m0 = acc[3 * o];
+        else if (c == 1) m1 = acc[3 * o + 1];
+        else m2 = acc[3 * o + 2];
+      }
       else xch[3 * MU + (o < MU ? o : o - 1)][c][lane] = acc[3 * o + c];
     }
   }
@@ -436,12 +443,12 @@ __global__ __launch_bounds__(256) void wilson_dir_kernel(FineView<FIN> in, FineV
   }
   const T coef = T(mu == 0 ? hw_d.x : mu == 1 ? hw_d.y : mu == 2 ? hw_d.z : hw_d.w);
   for (int r = 0; r < nrhs; ++r) {
-    C mine[3];
+    C m0, m1, m2;
     switch (mu) {
-      case 0: hop_pair<FORM, FIN, 0>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
-      case 1: hop_pair<FORM, FIN, 1>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
-      case 2: hop_pair<FORM, FIN, 2>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
-      default: hop_pair<FORM, FIN, 3>(in, r, yf, yb, uf, ub, coef, xch, lane, mine); break;
+      case 0: hop_pair<FORM, FIN, 0>(in, r, yf, yb, uf, ub, coef, xch, lane, m0, m1, m2); break;
+      case 1: hop_pair<FORM, FIN, 1>(in, r, yf, yb, uf, ub, coef, xch, lane, m0, m1, m2); break;
+      case 2: hop_pair<FORM, FIN, 2>(in, r, yf, yb, uf, ub, coef, xch, lane, m0, m1, m2); break;
+      default: hop_pair<FORM, FIN, 3>(in, r, yf, yb, uf, ub, coef, xch, lane, m0, m1, m2); break;
     }
     __syncthreads();
     // spin mu of site s: diagonal + the partials of wavefronts 0..3 (fixed order)
@@ -472,8 +479,14 @@ __global__ __launch_bounds__(256) void wilson_dir_kernel(FineView<FIN> in, FineV
       if constexpr (CL) q = site[c];
       else q = cscale(x, diag);
 #pragma unroll
-      for (int src = 0; src < 4; ++src)
-        q = q + (src == mu ? mine[c] : xch[3 * src + (mu < src ? mu : mu - 1)][c][lane]);
+      for (int src = 0; src < 4; ++src) {
+        // the slot is read for every src (src == mu: slot 3 src, a valid one whose
+        // value is not used) so that the choice below is between values: a choice
+        // between the LDS slot and the wavefront's own partial as addresses put
+        // the partial in private memory behind a generic load
+        const C other = xch[3 * src + (mu < src ? mu : mu > src ? mu - 1 : 0)][c][lane];
+        q = q + (src == mu ? (c == 0 ? m0 : c == 1 ? m1 : m2) : other);
+      }
       if (live) {
         pout[c * kVL] = q;
         v0 += double(q.x) * x.x + double(q.y) * x.y;
