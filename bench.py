@@ -416,12 +416,18 @@ def workload_c3(crk, args):
         "launch_timing": "HIP events on the setup stream around every smoother dslash launch (library-side)",
     }
     if not args.no_fp64:
+        # each form gets one untimed step first, as the FP32 rows get their warmup
+        # steps: the library's buffer cache then holds this form's shapes, and the
+        # timed step does not pay for giving back another form's buffers
+        c3_step(crk, lat, b, x, crk.FORM_FP64, crk.FORM_FP64)
         fp64 = [c3_step(crk, lat, b, x, crk.FORM_FP64, crk.FORM_FP64)]
         result["fp64_plain"] = form_summary(fp64, V, crk.FORM_FP64)
         log("fp64_plain", json.dumps(result["fp64_plain"]))
+        c3_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP16S)
         f16 = [c3_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP16S)]
         result["fp16s"] = form_summary(f16, V, crk.FORM_FP32)
         log("fp16s", json.dumps(result["fp16s"]))
+        c3_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP32, m_prime=C3_K, k=C3_K)
         conv = [c3_step(crk, lat, b, x, crk.FORM_FP32, crk.FORM_FP32, m_prime=C3_K, k=C3_K)]
         result["conventional_m24"] = form_summary(conv, V, crk.FORM_FP32, m_prime=C3_K)
         log("conventional", json.dumps(result["conventional_m24"]))

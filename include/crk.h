@@ -198,6 +198,13 @@ typedef struct {
                                           first m'_l (normalised) test vectors of step l-1, computed
                                           on the device by the restriction in the setup form.
                                           Requires m'_l <= m'_{l-1}.  0 (default): random vectors. */
+  int32_t smooth_defer;                /* fine-level smoother: sweeps whose psi updates share one pass
+                                          over psi (each sweep still forms its residual, into a ring
+                                          of smooth_defer + 1 fields); 1 = every sweep updates psi,
+                                          2..8 as given, 0 (default) = the largest of 8, 4, 2 for
+                                          which the ring and q take at most 30 % of the free device
+                                          memory, else 1.  The hierarchy is bitwise the same for
+                                          every value. */
 } crk_mg_params;
 
 /* Fill p with defaults (two levels, m'=48, k=24, 4^4 blocks, 20 sweeps, FP32 smoother). */

@@ -53,6 +53,7 @@ class MGParams(C.Structure):
         ("smooth_chunk", C.c_int32),
         ("svd_batch", C.c_int32),
         ("coarse_init", C.c_int32),
+        ("smooth_defer", C.c_int32),
     ]
 
 
@@ -346,7 +347,7 @@ class Hierarchy:
 
     def __init__(self, lattice, m_prime=(48,), k=(24,), block=((4, 4, 4, 4),), n_smooth=(20,),
                  setup_form=FORM_FP32, normalize=True, seed=0x2502030910, init_vectors=None, smooth_chunk=0,
-                 svd_batch=0, coarse_init=False):
+                 svd_batch=0, coarse_init=False, smooth_defer=0):
         self.lattice = lattice
         p = MGParams()
         _load().crk_mg_params_default(C.byref(p))
@@ -364,6 +365,7 @@ class Hierarchy:
         p.smooth_chunk = int(smooth_chunk)
         p.svd_batch = int(svd_batch)
         p.coarse_init = int(bool(coarse_init))
+        p.smooth_defer = int(smooth_defer)
         keep = []
         if init_vectors is not None:
             for l, v in enumerate(init_vectors):

@@ -35,6 +35,23 @@ void mr_alpha(const double* sums3, int nrhs, double2* alpha, hipStream_t st);
 // not used afterwards (q is then not read and r not written).
 void mr_update(int prec, void* psi, void* r, const void* q, const double2* alpha, int64_t n, int nrhs, bool rhs_inner,
                hipStream_t st, bool update_r = true);
+// MR updates of several sweeps applied to psi in one pass.  Each sweep k still
+// forms its residual r_{k+1} = r_k - alpha_k q_k, into a field of its own, but
+// psi is read and written only when the pending sweeps are flushed:
+// psi += alpha_j r_j for the pending sweeps j in order.  Per element this is
+// the sequence of fused multiply-adds of one mr_update per sweep, so the
+// result is bitwise the same; each sweep moves r, q in and r out, and a flush
+// adds psi in and out and the older pending residuals in.
+constexpr int kMrMaxDefer = 8;
+struct MrPending {
+  const void* r[kMrMaxDefer];        // r_j of the pending sweeps, oldest first; the last is the current r_k
+  const double2* alpha[kMrMaxDefer];  // their alpha_j [nrhs]
+  int n;                              // pending sweeps (>= 1)
+};
+// rnext = r_k - alpha_k q (skipped when rnext is null); when psi is not null,
+// psi += alpha_j r_j over all pending sweeps.  Layouts as mr_update.
+void mr_update_ring(int prec, void* psi, const MrPending& pend, const void* q, void* rnext, int64_t n, int nrhs,
+                    bool rhs_inner, hipStream_t st);
 // The same update on the fine level with psi in FP32 and r, q in FP16 storage
 // (AoSoA fine fields of V sites, one scale per site and RHS; r is rescaled).
 void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st,

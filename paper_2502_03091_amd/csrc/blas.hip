@@ -218,6 +218,48 @@ __global__ __launch_bounds__(kT) void mr_update_kernel(typename C2<T>::t* __rest
   r[i] = nr;
 }
 
+// rnext = r_k - alpha_k q; psi += alpha_j r_j over the pending sweeps (the
+// per-sweep arithmetic of mr_update_kernel, in the same order).
+template <class T>
+__global__ __launch_bounds__(kT) void mr_update_ring_kernel(typename C2<T>::t* __restrict__ psi, MrPending pend,
+                                                            const typename C2<T>::t* __restrict__ q,
+                                                            typename C2<T>::t* __restrict__ rnext, int64_t n,
+                                                            int nrhs, int rhs_inner) {
+  using CT = typename C2<T>::t;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  const int rr = rhs_inner ? int(i % nrhs) : int(i / n);
+  const int last = pend.n - 1;
+  CT x[kMrMaxDefer];
+#pragma unroll
+  for (int j = 0; j < kMrMaxDefer; ++j)
+    if (j <= last && (psi != nullptr || j == last)) x[j] = static_cast<const CT*>(pend.r[j])[i];
+  if (rnext != nullptr) {
+    CT rk = x[0];
+#pragma unroll
+    for (int j = 1; j < kMrMaxDefer; ++j)
+      if (j == last) rk = x[j];
+    const double2 ad = pend.alpha[last][rr];
+    const CT a = mk<CT>(T(ad.x), T(ad.y));
+    CT nr = rk;
+    const CT qa = cmul(a, q[i]);
+    nr.x -= qa.x;
+    nr.y -= qa.y;
+    rnext[i] = nr;
+  }
+  if (psi != nullptr) {
+    CT p = psi[i];
+#pragma unroll
+    for (int j = 0; j < kMrMaxDefer; ++j) {
+      if (j > last) break;
+      const double2 ad = pend.alpha[j][rr];
+      const CT a = mk<CT>(T(ad.x), T(ad.y));
+      cfma(p, a, x[j]);
+    }
+    psi[i] = p;
+  }
+}
+
 // v[e * nrhs + r] *= f[r] (rhs-inner field of n entries per rhs); the product in FP64.
 template <class T>
 __global__ __launch_bounds__(kT) void scale_rhs_inner_kernel(typename C2<T>::t* __restrict__ v,
@@ -334,6 +376,20 @@ void mr_update(int prec, void* psi, void* r, const void* q, const double2* alpha
     hipLaunchKernelGGL(mr_update_kernel<float>, g, dim3(kT), 0, st, static_cast<float2*>(psi),
                        static_cast<float2*>(r), static_cast<const float2*>(q), alpha, n, nrhs, int(rhs_inner),
                        int(update_r));
+  CRK_LAUNCH_CHECK();
+}
+
+void mr_update_ring(int prec, void* psi, const MrPending& pend, const void* q, void* rnext, int64_t n, int nrhs,
+                    bool rhs_inner, hipStream_t st) {
+  CRK_REQUIRE(pend.n >= 1 && pend.n <= kMrMaxDefer, "mr_update_ring: 1 to 8 pending sweeps");
+  if (n <= 0 || nrhs <= 0) return;
+  const dim3 g(ceil_div(n * nrhs, kT));
+  if (prec == CRK_FORM_FP64)
+    hipLaunchKernelGGL(mr_update_ring_kernel<double>, g, dim3(kT), 0, st, static_cast<double2*>(psi), pend,
+                       static_cast<const double2*>(q), static_cast<double2*>(rnext), n, nrhs, int(rhs_inner));
+  else
+    hipLaunchKernelGGL(mr_update_ring_kernel<float>, g, dim3(kT), 0, st, static_cast<float2*>(psi), pend,
+                       static_cast<const float2*>(q), static_cast<float2*>(rnext), n, nrhs, int(rhs_inner));
   CRK_LAUNCH_CHECK();
 }
 

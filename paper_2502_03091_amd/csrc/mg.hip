@@ -45,6 +45,7 @@ void validate(const Lattice* L, const crk_mg_params& p) {
   CRK_REQUIRE(p.setup_form == CRK_FORM_FP64 || p.setup_form == CRK_FORM_FP32, "setup_form must be FP64 or FP32");
   CRK_REQUIRE(p.smooth_chunk >= 0 && p.svd_batch >= 0, "smooth_chunk and svd_batch must be >= 0");
   CRK_REQUIRE(p.coarse_init == 0 || p.coarse_init == 1, "coarse_init must be 0 or 1");
+  CRK_REQUIRE(p.smooth_defer >= 0 && p.smooth_defer <= kMrMaxDefer, "smooth_defer must be in [0, 8]");
   static_assert(CRK_MAX_LEVELS == 3, "coarse_init restricts from the fine step only");
   for (int l = 1; p.coarse_init && l < p.n_levels - 1; ++l)
     CRK_REQUIRE(p.init_vectors[l] != nullptr || p.m_prime[l] <= p.m_prime[l - 1],
@@ -246,11 +247,31 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
     while (mc > 8 && 2 * esz * size_t(n) * size_t(mc) > fr / 10 * 6) mc = (mc + 1) / 2;
   }
   const int nchunk = (m + mc - 1) / mc;
-  DevBuf r(esz * n * mc), q(esz * n * mc);
+  // Fine level: D sweeps share one pass over psi (mr_update_ring); the
+  // residuals of the pending sweeps live in a ring of D + 1 fields.  Per
+  // sweep this moves 4 fields plus 1/D of a field instead of 5.  The automatic
+  // depth keeps the ring and q within 30 % of the free device memory.
+  int D = 1;
+  if (!inner && p.n_smooth[l] > 1) {
+    if (p.smooth_defer > 0) {
+      D = p.smooth_defer;
+    } else {
+      const size_t fr = device_free_bytes(), field = esz * size_t(n) * size_t(mc);
+      for (int d : {8, 4, 2})
+        if (size_t(d + 2) * field <= fr / 10 * 3) {
+          D = d;
+          break;
+        }
+    }
+  }
+  std::vector<DevBuf> ring(D == 1 ? 1 : D + 1);
+  for (auto& b : ring) b.alloc(esz * n * mc);
+  DevBuf& r = ring[0];
+  DevBuf q(esz * n * mc);
   const int64_t nsb = wilson_partial_blocks(V);
   const int64_t ndp = rhs_dot_partials(n, inner);
   DevBuf partial(sizeof(double) * 3 * mc * (nsb > ndp ? nsb : ndp));
-  DevBuf sums(sizeof(double) * 3 * mc), alpha(sizeof(double2) * mc);
+  DevBuf sums(sizeof(double) * 3 * mc), alpha(sizeof(double2) * mc * D);
   // events around every fine operator launch; read once after the stage
   std::vector<hipEvent_t> dev_ev(inner ? 0 : 2 * size_t(p.n_smooth[l]) * nchunk);
   for (auto& e : dev_ev) CRK_HIP(hipEventCreate(&e));
@@ -259,21 +280,40 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
     void* pc = static_cast<char*>(psi.p) + esz * size_t(n) * c0;  // rhs-outer: vectors c0 .. c0+mm-1
     const int64_t rs = inner ? 1 : n, es = inner ? mm : 1;
     level_apply(H, l, form, pc, r.p, mm, st, nullptr, /*negate=*/true);
+    int pending = 0;  // sweeps whose psi update has not been applied
     for (int it = 0; it < p.n_smooth[l]; ++it) {
+      void* rk = ring[size_t(it) % ring.size()].p;
+      double2* ak = alpha.as<double2>() + size_t(it % D) * mc;
       if (!inner) {
         hipEvent_t* e = dev_ev.data() + 2 * (size_t(ch) * p.n_smooth[l] + it);
         CRK_HIP(hipEventRecord(e[0], st));
-        level_apply(H, l, form, r.p, q.p, mm, st, partial.as<double>());
+        level_apply(H, l, form, rk, q.p, mm, st, partial.as<double>());
         CRK_HIP(hipEventRecord(e[1], st));
         reduce_partials(partial.as<double>(), nsb, mm, 3, sums.as<double>(), st);
       } else {
-        level_apply(H, l, form, r.p, q.p, mm, st);
+        level_apply(H, l, form, rk, q.p, mm, st);
         // sums = (<q, r>, <q, q>)
-        rhs_dot(form, q.p, r.p, n, mm, rs, es, partial.as<double>(), sums.as<double>(), st);
+        rhs_dot(form, q.p, rk, n, mm, rs, es, partial.as<double>(), sums.as<double>(), st);
       }
-      mr_alpha(sums.as<double>(), mm, alpha.as<double2>(), st);
+      mr_alpha(sums.as<double>(), mm, ak, st);
       // the residual after the last sweep is not used: that update skips it
-      mr_update(form, pc, r.p, q.p, alpha.as<double2>(), n, mm, inner, st, it + 1 < p.n_smooth[l]);
+      const bool more = it + 1 < p.n_smooth[l];
+      if (D == 1) {
+        mr_update(form, pc, rk, q.p, ak, n, mm, inner, st, more);
+        continue;
+      }
+      ++pending;
+      const bool flush = pending == D || !more;
+      MrPending pend{};
+      pend.n = flush ? pending : 1;
+      for (int j = 0; j < pend.n; ++j) {
+        const int sw = it - pend.n + 1 + j;
+        pend.r[j] = ring[size_t(sw) % ring.size()].p;
+        pend.alpha[j] = alpha.as<double2>() + size_t(sw % D) * mc;
+      }
+      mr_update_ring(form, flush ? pc : nullptr, pend, q.p, more ? ring[size_t(it + 1) % ring.size()].p : nullptr, n,
+                     mm, inner, st);
+      if (flush) pending = 0;
     }
   }
   ev.mark(1, st);
@@ -290,7 +330,7 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
   // the smoother's residual fields are as large as the test vectors: give them
   // back before the SVD and Galerkin stages allocate P and the coarse links
   CRK_HIP(hipStreamSynchronize(st));
-  r.release();
+  ring.clear();
   q.release();
   const int launches = inner ? 0 : p.n_smooth[l] * nchunk;
   tm.dslash_count = launches;

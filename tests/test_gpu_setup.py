@@ -307,3 +307,30 @@ def test_chunked_smoother_and_batched_svd_equal_full(crk):
         assert np.array_equal(s, out[0][0]) and np.array_equal(v, out[0][1])
         assert np.array_equal(P, out[0][3]) and all(np.array_equal(a, b) for a, b in zip(X, out[0][4]))
     assert out[1][2]["dslash_count"] == 2 * 20 and out[2][2]["dslash_count"] == 4 * 20
+
+
+def test_deferred_psi_updates_equal_per_sweep(crk):
+    """The fine-level smoother may apply the psi updates of several sweeps in one
+    pass over psi (each sweep still forms its residual): per element the fused
+    multiply-adds are those of one update per sweep, in the same order, so the
+    hierarchy is bitwise the same for every depth, with ragged last groups
+    (20 sweeps in groups of 3), chunked vectors, and both setup precisions."""
+    dims, block = [4, 4, 4, 8], [2, 2, 2, 2]
+    U = synth.gauge_field(dims, 0.3, 0, config=4)
+    v0 = synth.gaussian_vectors(16, 512, 12, config=4, level=0)
+    lat = crk.Lattice(dims, -0.4, 1.0)
+    lat.load_gauge(U)
+    for form in (crk.FORM_FP64, crk.FORM_FP32):
+        for sweeps in (20, 7, 1):
+            out = []
+            for defer, chunk in ((1, 0), (2, 0), (3, 0), (8, 0), (0, 0), (3, 5)):
+                H = crk.Hierarchy(lat, m_prime=[16], k=[8], block=[block], n_smooth=[sweeps], setup_form=form,
+                                  init_vectors=[v0], smooth_chunk=chunk, smooth_defer=defer)
+                out.append((H.vectors(0), H.sigma(0), H.coarse_links(0)))
+                H.close()
+            for v, s, X in out[1:]:
+                assert np.array_equal(v, out[0][0]), (form, sweeps)
+                assert np.array_equal(s, out[0][1]) and all(np.array_equal(a, b) for a, b in zip(X, out[0][2]))
+    with pytest.raises(crk.CrkError):
+        crk.Hierarchy(lat, m_prime=[16], k=[8], block=[block], n_smooth=[4], init_vectors=[v0], smooth_defer=9)
+    lat.close()
