@@ -1,6 +1,8 @@
 // Per-RHS BLAS-1 launchers (see blas.hip).
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace crk {
@@ -52,6 +54,30 @@ struct MrPending {
 // psi += alpha_j r_j over all pending sweeps.  Layouts as mr_update.
 void mr_update_ring(int prec, void* psi, const MrPending& pend, const void* q, void* rnext, int64_t n, int nrhs,
                     bool rhs_inner, hipStream_t st);
+
+// Host side of one run of MR sweeps with psi updates deferred over D sweeps:
+// the residual of sweep k lives in slot k mod (D + 1) and its alpha in row
+// k mod D of `alpha` (rows `alpha_stride` apart).  One slot means D = 1, the
+// in-place update of mr_update.  Use one object per run of sweeps.
+class MrSweeps {
+ public:
+  MrSweeps(std::vector<void*> slots, double2* alpha, size_t alpha_stride)
+      : slots_(std::move(slots)), alpha_(alpha), stride_(alpha_stride),
+        D_(slots_.size() > 1 ? int(slots_.size()) - 1 : 1) {}
+  void* r(int it) const { return slots_[size_t(it) % slots_.size()]; }
+  double2* alpha(int it) const { return alpha_ + size_t(it % D_) * stride_; }
+  // After sweep `it` of `nsweeps` formed q = D r(it) and alpha(it): the psi
+  // updates that are due and r(it + 1) (not formed after the last sweep).
+  void update(int prec, void* psi, const void* q, int it, int nsweeps, int64_t n, int nrhs, bool rhs_inner,
+              hipStream_t st);
+
+ private:
+  std::vector<void*> slots_;
+  double2* alpha_;
+  size_t stride_;
+  int D_;
+  int pending_ = 0;
+};
 // The same update on the fine level with psi in FP32 and r, q in FP16 storage
 // (AoSoA fine fields of V sites, one scale per site and RHS; r is rescaled).
 void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st,

@@ -393,6 +393,26 @@ void mr_update_ring(int prec, void* psi, const MrPending& pend, const void* q, v
   CRK_LAUNCH_CHECK();
 }
 
+void MrSweeps::update(int prec, void* psi, const void* q, int it, int nsweeps, int64_t n, int nrhs, bool rhs_inner,
+                      hipStream_t st) {
+  const bool more = it + 1 < nsweeps;
+  if (slots_.size() == 1) {
+    mr_update(prec, psi, slots_[0], q, alpha(it), n, nrhs, rhs_inner, st, more);
+    return;
+  }
+  ++pending_;
+  const bool flush = pending_ == D_ || !more;
+  MrPending pend{};
+  pend.n = flush ? pending_ : 1;
+  for (int j = 0; j < pend.n; ++j) {
+    const int sw = it - pend.n + 1 + j;
+    pend.r[j] = r(sw);
+    pend.alpha[j] = alpha(sw);
+  }
+  mr_update_ring(prec, flush ? psi : nullptr, pend, q, more ? r(it + 1) : nullptr, n, nrhs, rhs_inner, st);
+  if (flush) pending_ = 0;
+}
+
 void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st,
                       bool update_r) {
   if (V <= 0 || nrhs <= 0) return;

@@ -266,7 +266,8 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
   }
   std::vector<DevBuf> ring(D == 1 ? 1 : D + 1);
   for (auto& b : ring) b.alloc(esz * n * mc);
-  DevBuf& r = ring[0];
+  std::vector<void*> slots;
+  for (auto& b : ring) slots.push_back(b.p);
   DevBuf q(esz * n * mc);
   const int64_t nsb = wilson_partial_blocks(V);
   const int64_t ndp = rhs_dot_partials(n, inner);
@@ -279,11 +280,11 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
     const int c0 = ch * mc, mm = std::min(mc, m - c0);
     void* pc = static_cast<char*>(psi.p) + esz * size_t(n) * c0;  // rhs-outer: vectors c0 .. c0+mm-1
     const int64_t rs = inner ? 1 : n, es = inner ? mm : 1;
-    level_apply(H, l, form, pc, r.p, mm, st, nullptr, /*negate=*/true);
-    int pending = 0;  // sweeps whose psi update has not been applied
+    MrSweeps mr(slots, alpha.as<double2>(), size_t(mc));
+    level_apply(H, l, form, pc, mr.r(0), mm, st, nullptr, /*negate=*/true);
     for (int it = 0; it < p.n_smooth[l]; ++it) {
-      void* rk = ring[size_t(it) % ring.size()].p;
-      double2* ak = alpha.as<double2>() + size_t(it % D) * mc;
+      void* rk = mr.r(it);
+      double2* ak = mr.alpha(it);
       if (!inner) {
         hipEvent_t* e = dev_ev.data() + 2 * (size_t(ch) * p.n_smooth[l] + it);
         CRK_HIP(hipEventRecord(e[0], st));
@@ -297,23 +298,7 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
       }
       mr_alpha(sums.as<double>(), mm, ak, st);
       // the residual after the last sweep is not used: that update skips it
-      const bool more = it + 1 < p.n_smooth[l];
-      if (D == 1) {
-        mr_update(form, pc, rk, q.p, ak, n, mm, inner, st, more);
-        continue;
-      }
-      ++pending;
-      const bool flush = pending == D || !more;
-      MrPending pend{};
-      pend.n = flush ? pending : 1;
-      for (int j = 0; j < pend.n; ++j) {
-        const int sw = it - pend.n + 1 + j;
-        pend.r[j] = ring[size_t(sw) % ring.size()].p;
-        pend.alpha[j] = alpha.as<double2>() + size_t(sw % D) * mc;
-      }
-      mr_update_ring(form, flush ? pc : nullptr, pend, q.p, more ? ring[size_t(it + 1) % ring.size()].p : nullptr, n,
-                     mm, inner, st);
-      if (flush) pending = 0;
+      mr.update(form, pc, q.p, it, p.n_smooth[l], n, mm, inner, st);
     }
   }
   ev.mark(1, st);

@@ -63,6 +63,10 @@ struct LevelWork {      // coarse level l >= 1: inner solve buffers (+ post-smoo
 
 struct FineWork {       // level-0 K-cycle fields in the vector precision
   DevBuf rin, rho, q;
+  // post-smoother residuals of the deferred psi updates (FP32 form): rho and
+  // `defer` more fields; alpha rows of the pending sweeps [defer][cap]
+  DevBuf ring, alpha;
+  int defer = 1;
 };
 
 struct OuterWork {      // FP64 outer FGCR

@@ -74,6 +74,11 @@ size_t vec_bytes(int form) { return form == CRK_FORM_FP64 ? sizeof(double2) : si
 // Operator storage used on the fine level in a form (vectors there are FP32 for FP16S).
 int fine_op_form(int form) { return form == CRK_FORM_FP64 ? CRK_FORM_FP64 : CRK_FORM_FP32; }
 int ring_slots(const crk_solve_info& p) { return std::max(1, std::min(p.restart, p.max_iter)); }
+// Sweeps of the fine post-smoother whose psi updates share one pass (FP32
+// vectors; the FP16-storage form updates in place).
+int post_defer(int nlev, int form, const crk_solve_info& p) {
+  return nlev > 1 && form == CRK_FORM_FP32 ? std::max(1, std::min(p.nu_post, 4)) : 1;
+}
 // Storage of the outer directions z_i: the K-cycle's own vector storage (FP32
 // for the reduced forms), FP64 in the plain form and without coarse levels.
 int outer_z_form(const Hierarchy* H, int form) {
@@ -177,23 +182,28 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs
     return;
   }
   const FieldShape f = shape(H, l, nrhs);
-  void *rho, *q;
-  if (l == 0) { rho = w.fw.rho.p; q = w.fw.q.p; }
-  else { rho = w.lv[l].rho.p; q = w.lv[l].q.p; }
+  void* q = l == 0 ? w.fw.q.p : w.lv[l].q.p;
   GcrScalars& s = l == 0 ? w.ow.s : w.lv[l].s;
   // the scalars of level l are idle while its K-cycle runs (the cycle is called
   // between the solver's kernel phases); only sums3/partial/a are reused here.
-  level_residual(H, l, opf, eout, rin, rho, nrhs, st);  // rho = rin - D e
+  // On the fine level the e updates of up to four sweeps share one pass.
+  std::vector<void*> slots{l == 0 ? w.fw.rho.p : w.lv[l].rho.p};
+  if (l == 0 && w.fw.defer > 1) {
+    const size_t fv = vec_bytes(form) * 12 * size_t(H->V(0)) * w.cap;
+    for (int j = 0; j < w.fw.defer; ++j) slots.push_back(static_cast<char*>(w.fw.ring.p) + fv * j);
+  }
+  MrSweeps mr(slots, slots.size() > 1 ? w.fw.alpha.as<double2>() : s.a, size_t(w.cap));
+  level_residual(H, l, opf, eout, rin, mr.r(0), nrhs, st);  // rho = rin - D e
   for (int it = 0; it < p.nu_post; ++it) {
     if (l == 0) {
-      level_apply(H, 0, opf, rho, q, nrhs, st, s.partial);
+      level_apply(H, 0, opf, mr.r(it), q, nrhs, st, s.partial);
       reduce_partials(s.partial, wilson_partial_blocks(H->V(0)), nrhs, 3, s.sums3, st);
     } else {
-      level_apply(H, l, opf, rho, q, nrhs, st);
-      rhs_dot(prec, q, rho, f.n, nrhs, f.rs, f.es, s.partial, s.sums3, st);
+      level_apply(H, l, opf, mr.r(it), q, nrhs, st);
+      rhs_dot(prec, q, mr.r(it), f.n, nrhs, f.rs, f.es, s.partial, s.sums3, st);
     }
-    mr_alpha(s.sums3, nrhs, s.a, st);
-    mr_update(prec, eout, rho, q, s.a, f.n, nrhs, l > 0, st, it + 1 < p.nu_post);  // last step: e only
+    mr_alpha(s.sums3, nrhs, mr.alpha(it), st);
+    mr.update(prec, eout, q, it, p.nu_post, f.n, nrhs, l > 0, st);  // last step: e only
   }
 }
 
@@ -212,7 +222,7 @@ void validate(Hierarchy* H, const crk_solve_info& p) {
 
 bool workspace_fits(const Workspace& w, int cap, int form, const crk_solve_info& p) {
   return w.cap >= cap && w.form == form && w.restart == ring_slots(p) && w.inner == p.inner_maxit &&
-         w.coarsest == p.coarsest_maxit;
+         w.coarsest == p.coarsest_maxit && w.fw.defer == post_defer(int(w.lv.size()), form, p);
 }
 
 std::unique_ptr<Workspace> make_workspace(Hierarchy* H, int cap, int form, const crk_solve_info& p, hipStream_t st) {
@@ -248,6 +258,12 @@ std::unique_ptr<Workspace> make_workspace(Hierarchy* H, int cap, int form, const
     const size_t fv = vec_bytes(form) * 12 * size_t(V0) * cap;
     w.fw.rin.alloc(fv); w.fw.rho.alloc(fv); w.fw.q.alloc(fv);
     w.bytes += 3 * fv;
+    w.fw.defer = post_defer(H->nlev, form, p);
+    if (w.fw.defer > 1) {
+      w.fw.ring.alloc(fv * w.fw.defer);
+      w.fw.alpha.alloc(sizeof(double2) * w.fw.defer * cap);
+      w.bytes += fv * w.fw.defer;
+    }
   }
   w.lv.resize(H->nlev);
   for (int l = 1; l < H->nlev; ++l) {
@@ -525,7 +541,8 @@ size_t mg_solve_footprint(Hierarchy* H, int nrhs, int form, const crk_solve_info
   const int nslots = ring_slots(p);
   size_t b = sizeof(double2) * 12 * size_t(V0) * nrhs * (4 + size_t(nslots)) +
              vec_bytes(outer_z_form(H, form)) * 12 * size_t(V0) * nrhs * nslots;
-  if (H->nlev > 1) b += 3 * vec_bytes(form) * 12 * size_t(V0) * nrhs;
+  const int defer = post_defer(H->nlev, form, p);
+  if (H->nlev > 1) b += (3 + size_t(defer > 1 ? defer : 0)) * vec_bytes(form) * 12 * size_t(V0) * nrhs;
   for (int l = 1; l < H->nlev; ++l) {
     const int maxit = l == H->nlev - 1 ? p.coarsest_maxit : p.inner_maxit;
     b += vec_bytes(form) * size_t(H->N(l)) * H->V(l) * nrhs * (5 + 2 * size_t(maxit));
