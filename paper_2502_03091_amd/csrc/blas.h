@@ -70,6 +70,9 @@ class MrSweeps {
   // updates that are due and r(it + 1) (not formed after the last sweep).
   void update(int prec, void* psi, const void* q, int it, int nsweeps, int64_t n, int nrhs, bool rhs_inner,
               hipStream_t st);
+  // The same for the fine level with psi in FP32 and r, q in FP16 storage
+  // (the arithmetic of mr_update_fine_h).
+  void update_fine_h(void* psi, const void* q, int it, int nsweeps, int64_t V, int nrhs, hipStream_t st);
 
  private:
   std::vector<void*> slots_;

@@ -159,6 +159,16 @@ __global__ void mr_alpha_kernel(const double* __restrict__ sums, int nrhs, doubl
   alpha[r] = qq > 0 ? make_double2(sums[3 * r] / qq, sums[3 * r + 1] / qq) : make_double2(0, 0);
 }
 
+// r - a q for one component of an FP16-storage residual, each product and the
+// difference rounded as written: the decoded r (a product with its site scale)
+// is kept out of any fused multiply-add, so every kernel that forms the next
+// residual gets the same bits whether or not it also uses r for psi.
+__device__ __forceinline__ float2 mr_next_h(float2 r, float2 a, float2 q) {
+  asm volatile("" : "+v"(r.x), "+v"(r.y));
+  const float qx = fmaf(a.x, q.x, -(a.y * q.y)), qy = fmaf(a.x, q.y, a.y * q.x);
+  return mk<float2>(r.x - qx, r.y - qy);
+}
+
 // psi += alpha r ;  r -= alpha q  with psi FP32 and r, q in FP16 storage: one
 // thread per (site, rhs) of the fine AoSoA layout, the same complex arithmetic
 // as mr_update_kernel<float>, the new r stored with its site's new scale.
@@ -185,12 +195,63 @@ __global__ __launch_bounds__(kT) void mr_update_h_kernel(float2* __restrict__ ps
   if (!upd_r) return;
   q.load(rr, s, qv);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const float2 qa = cmul(a, qv[c]);
-    rv[c].x -= qa.x;
-    rv[c].y -= qa.y;
-  }
+  for (int c = 0; c < 12; ++c) rv[c] = mr_next_h(rv[c], a, qv[c]);
   r.store(rr, s, rv);
+}
+
+// Deferred updates with psi FP32 and r, q in FP16 storage (one thread per
+// site and RHS): rnext = r_k - alpha_k q stored with its new site scale, and
+// psi += alpha_j r_j over the pending sweeps, the arithmetic of
+// mr_update_h_kernel in the same order.
+struct MrPendingH {
+  FineView<CRK_FORM_FP16S> r[kMrMaxDefer];
+  const double2* alpha[kMrMaxDefer];
+  int n;
+};
+__global__ __launch_bounds__(kT) void mr_update_h_ring_kernel(float2* __restrict__ psi, MrPendingH pend,
+                                                              FineView<CRK_FORM_FP16S> q,
+                                                              FineView<CRK_FORM_FP16S> rnext, int64_t V, int nrhs) {
+  const int64_t Vp = pad_sites(V);
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= Vp * nrhs) return;
+  const int64_t rr = i / Vp, s = i % Vp;
+  if (s >= V) return;  // padding sites are never read
+  const int last = pend.n - 1;
+  if (rnext.data != nullptr) {
+    FineView<CRK_FORM_FP16S> rk = pend.r[0];
+    const double2* ak = pend.alpha[0];
+#pragma unroll
+    for (int j = 1; j < kMrMaxDefer; ++j)
+      if (j == last) {
+        rk = pend.r[j];
+        ak = pend.alpha[j];
+      }
+    const double2 ad = ak[rr];
+    const float2 a = make_float2(float(ad.x), float(ad.y));
+    float2 rv[12], qv[12];
+    rk.load(rr, s, rv);
+    q.load(rr, s, qv);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rv[c] = mr_next_h(rv[c], a, qv[c]);
+    rnext.store(rr, s, rv);
+  }
+  if (psi == nullptr) return;
+  float2* pp = psi + aidx(rr, 0, s, Vp, 12);
+  float2 p[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) p[c] = pp[c * kVL];
+#pragma unroll
+  for (int j = 0; j < kMrMaxDefer; ++j) {
+    if (j > last) break;
+    const double2 ad = pend.alpha[j][rr];
+    const float2 a = make_float2(float(ad.x), float(ad.y));
+    float2 x[12];
+    pend.r[j].load(rr, s, x);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) cfma(p[c], a, x[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) pp[c * kVL] = p[c];
 }
 
 // psi += alpha r ;  r -= alpha q    (rhs-outer layout, n entries per rhs)
@@ -410,6 +471,31 @@ void MrSweeps::update(int prec, void* psi, const void* q, int it, int nsweeps, i
     pend.alpha[j] = alpha(sw);
   }
   mr_update_ring(prec, flush ? psi : nullptr, pend, q, more ? r(it + 1) : nullptr, n, nrhs, rhs_inner, st);
+  if (flush) pending_ = 0;
+}
+
+void MrSweeps::update_fine_h(void* psi, const void* q, int it, int nsweeps, int64_t V, int nrhs, hipStream_t st) {
+  const bool more = it + 1 < nsweeps;
+  if (slots_.size() == 1) {
+    mr_update_fine_h(psi, slots_[0], q, alpha(it), V, nrhs, st, more);
+    return;
+  }
+  ++pending_;
+  const bool flush = pending_ == D_ || !more;
+  if (V > 0 && nrhs > 0) {
+    MrPendingH pend{};
+    pend.n = flush ? pending_ : 1;
+    for (int j = 0; j < pend.n; ++j) {
+      const int sw = it - pend.n + 1 + j;
+      pend.r[j] = FineView<CRK_FORM_FP16S>(r(sw), V, nrhs);
+      pend.alpha[j] = alpha(sw);
+    }
+    FineView<CRK_FORM_FP16S> qv(const_cast<void*>(q), V, nrhs), rn;
+    if (more) rn = FineView<CRK_FORM_FP16S>(r(it + 1), V, nrhs);
+    hipLaunchKernelGGL(mr_update_h_ring_kernel, dim3(ceil_div(pad_sites(V) * nrhs, kT)), dim3(kT), 0, st,
+                       static_cast<float2*>(flush ? psi : nullptr), pend, qv, rn, V, nrhs);
+    CRK_LAUNCH_CHECK();
+  }
   if (flush) pending_ = 0;
 }
 

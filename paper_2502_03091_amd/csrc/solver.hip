@@ -74,10 +74,10 @@ size_t vec_bytes(int form) { return form == CRK_FORM_FP64 ? sizeof(double2) : si
 // Operator storage used on the fine level in a form (vectors there are FP32 for FP16S).
 int fine_op_form(int form) { return form == CRK_FORM_FP64 ? CRK_FORM_FP64 : CRK_FORM_FP32; }
 int ring_slots(const crk_solve_info& p) { return std::max(1, std::min(p.restart, p.max_iter)); }
-// Sweeps of the fine post-smoother whose psi updates share one pass (FP32
-// vectors; the FP16-storage form updates in place).
+// Sweeps of the fine post-smoother whose e updates share one pass (the
+// reduced forms, whose K-cycle runs in FP32 or FP16 storage).
 int post_defer(int nlev, int form, const crk_solve_info& p) {
-  return nlev > 1 && form == CRK_FORM_FP32 ? std::max(1, std::min(p.nu_post, 4)) : 1;
+  return nlev > 1 && form != CRK_FORM_FP64 ? std::max(1, std::min(p.nu_post, 4)) : 1;
 }
 // Storage of the outer directions z_i: the K-cycle's own vector storage (FP32
 // for the reduced forms), FP64 in the plain form and without coarse levels.
@@ -173,11 +173,16 @@ void kcycle(Hierarchy* H, Workspace& w, int l, const crk_solve_info& p, int nrhs
     void* qh = w.fw.rho.p;  // r32 is no longer needed once converted (stream order)
     field_convert(CRK_FORM_FP32, r32, CRK_FORM_FP16S, rhoh, V0, 12, nrhs, st);
     GcrScalars& s0 = w.ow.s;
+    // the e updates of up to four sweeps share one pass (residuals in a ring)
+    std::vector<void*> slots{rhoh};
+    const size_t fv = vec_bytes(form) * 12 * size_t(V0) * w.cap;  // each ring field holds an FP16 field set
+    for (int j = 0; w.fw.defer > 1 && j < w.fw.defer; ++j) slots.push_back(static_cast<char*>(w.fw.ring.p) + fv * j);
+    MrSweeps mr(slots, slots.size() > 1 ? w.fw.alpha.as<double2>() : s0.a, size_t(w.cap));
     for (int it = 0; it < p.nu_post; ++it) {
-      level_apply(H, 0, CRK_FORM_FP16S, rhoh, qh, nrhs, st, s0.partial);
+      level_apply(H, 0, CRK_FORM_FP16S, mr.r(it), qh, nrhs, st, s0.partial);
       reduce_partials(s0.partial, wilson_partial_blocks(V0), nrhs, 3, s0.sums3, st);
-      mr_alpha(s0.sums3, nrhs, s0.a, st);
-      mr_update_fine_h(eout, rhoh, qh, s0.a, V0, nrhs, st, it + 1 < p.nu_post);  // last step: e only
+      mr_alpha(s0.sums3, nrhs, mr.alpha(it), st);
+      mr.update_fine_h(eout, qh, it, p.nu_post, V0, nrhs, st);  // last step: e only
     }
     return;
   }
