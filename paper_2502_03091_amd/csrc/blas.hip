@@ -159,6 +159,23 @@ __global__ void mr_alpha_kernel(const double* __restrict__ sums, int nrhs, doubl
   alpha[r] = qq > 0 ? make_double2(sums[3 * r] / qq, sums[3 * r + 1] / qq) : make_double2(0, 0);
 }
 
+// r - a q for FP32 fields with each product and the difference rounded as
+// written (the barrier keeps a q out of any fusion with the subtraction), so
+// the one-sweep update and the deferred updates form the same residuals.
+__device__ __forceinline__ float2 mr_next_f(float2 r, float2 a, float2 q) {
+  float qx = fmaf(a.x, q.x, -(a.y * q.y)), qy = fmaf(a.y, q.x, a.x * q.y);
+  asm volatile("" : "+v"(qx), "+v"(qy));
+  return mk<float2>(r.x - qx, r.y - qy);
+}
+__device__ __forceinline__ double2 mr_next(double2 r, double2 a, double2 q) {
+  double2 nr = r;
+  const double2 qa = cmul(a, q);
+  nr.x -= qa.x;
+  nr.y -= qa.y;
+  return nr;
+}
+__device__ __forceinline__ float2 mr_next(float2 r, float2 a, float2 q) { return mr_next_f(r, a, q); }
+
 // r - a q for one component of an FP16-storage residual, each product and the
 // difference rounded as written: the decoded r (a product with its site scale)
 // is kept out of any fused multiply-add, so every kernel that forms the next
@@ -197,6 +214,46 @@ __global__ __launch_bounds__(kT) void mr_update_h_kernel(float2* __restrict__ ps
 #pragma unroll
   for (int c = 0; c < 12; ++c) rv[c] = mr_next_h(rv[c], a, qv[c]);
   r.store(rr, s, rv);
+}
+
+// mr_update_ring_kernel<float> for rhs-outer fields with an even number of
+// entries per RHS: two complex entries per thread, 16-byte accesses.
+__global__ __launch_bounds__(kT) void mr_update_ring2_kernel(float4* __restrict__ psi, MrPending pend,
+                                                             const float4* __restrict__ q,
+                                                             float4* __restrict__ rnext, int64_t n2, int nrhs) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n2 * nrhs) return;
+  const int rr = int(i / n2);
+  const int last = pend.n - 1;
+  float4 x[kMrMaxDefer];
+#pragma unroll
+  for (int j = 0; j < kMrMaxDefer; ++j)
+    if (j <= last && (psi != nullptr || j == last)) x[j] = static_cast<const float4*>(pend.r[j])[i];
+  if (rnext != nullptr) {
+    float4 rk = x[0];
+#pragma unroll
+    for (int j = 1; j < kMrMaxDefer; ++j)
+      if (j == last) rk = x[j];
+    const double2 ad = pend.alpha[last][rr];
+    const float2 a = make_float2(float(ad.x), float(ad.y));
+    const float4 qv = q[i];
+    const float2 n0 = mr_next_f(make_float2(rk.x, rk.y), a, make_float2(qv.x, qv.y));
+    const float2 n1 = mr_next_f(make_float2(rk.z, rk.w), a, make_float2(qv.z, qv.w));
+    rnext[i] = make_float4(n0.x, n0.y, n1.x, n1.y);
+  }
+  if (psi != nullptr) {
+    const float4 pv = psi[i];
+    float2 p0 = make_float2(pv.x, pv.y), p1 = make_float2(pv.z, pv.w);
+#pragma unroll
+    for (int j = 0; j < kMrMaxDefer; ++j) {
+      if (j > last) break;
+      const double2 ad = pend.alpha[j][rr];
+      const float2 a = make_float2(float(ad.x), float(ad.y));
+      cfma(p0, a, make_float2(x[j].x, x[j].y));
+      cfma(p1, a, make_float2(x[j].z, x[j].w));
+    }
+    psi[i] = make_float4(p0.x, p0.y, p1.x, p1.y);
+  }
 }
 
 // Deferred updates with psi FP32 and r, q in FP16 storage (one thread per
@@ -272,11 +329,7 @@ __global__ __launch_bounds__(kT) void mr_update_kernel(typename C2<T>::t* __rest
   cfma(p, a, rv);
   psi[i] = p;
   if (!upd_r) return;
-  CT nr = rv;
-  const CT qa = cmul(a, q[i]);
-  nr.x -= qa.x;
-  nr.y -= qa.y;
-  r[i] = nr;
+  r[i] = mr_next(rv, a, q[i]);
 }
 
 // rnext = r_k - alpha_k q; psi += alpha_j r_j over the pending sweeps (the
@@ -302,11 +355,7 @@ __global__ __launch_bounds__(kT) void mr_update_ring_kernel(typename C2<T>::t* _
       if (j == last) rk = x[j];
     const double2 ad = pend.alpha[last][rr];
     const CT a = mk<CT>(T(ad.x), T(ad.y));
-    CT nr = rk;
-    const CT qa = cmul(a, q[i]);
-    nr.x -= qa.x;
-    nr.y -= qa.y;
-    rnext[i] = nr;
+    rnext[i] = mr_next(rk, a, q[i]);
   }
   if (psi != nullptr) {
     CT p = psi[i];
@@ -444,6 +493,17 @@ void mr_update_ring(int prec, void* psi, const MrPending& pend, const void* q, v
                     bool rhs_inner, hipStream_t st) {
   CRK_REQUIRE(pend.n >= 1 && pend.n <= kMrMaxDefer, "mr_update_ring: 1 to 8 pending sweeps");
   if (n <= 0 || nrhs <= 0) return;
+  bool pairs = prec != CRK_FORM_FP64 && !rhs_inner && n % 2 == 0;
+  auto al16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  for (int j = 0; j < pend.n; ++j) pairs = pairs && al16(pend.r[j]);
+  pairs = pairs && al16(psi) && al16(q) && al16(rnext);
+  if (pairs) {
+    hipLaunchKernelGGL(mr_update_ring2_kernel, dim3(ceil_div(n / 2 * nrhs, kT)), dim3(kT), 0, st,
+                       static_cast<float4*>(psi), pend, static_cast<const float4*>(q), static_cast<float4*>(rnext),
+                       n / 2, nrhs);
+    CRK_LAUNCH_CHECK();
+    return;
+  }
   const dim3 g(ceil_div(n * nrhs, kT));
   if (prec == CRK_FORM_FP64)
     hipLaunchKernelGGL(mr_update_ring_kernel<double>, g, dim3(kT), 0, st, static_cast<double2*>(psi), pend,
