@@ -227,6 +227,11 @@ typedef struct {
   int32_t inner_maxit; /* iterations of an intermediate-level coarse solve */
   int32_t coarsest_maxit; /* iterations of the coarsest solve */
   int32_t nu_post;     /* MR post-smoothing steps */
+  int32_t post_defer;  /* fine-level post-smoothing steps whose e updates share one pass over e
+                          (each step still forms its residual, into a ring of post_defer + 1
+                          fields): 1 = every step updates e, 2..8 as given (at most nu_post),
+                          0 (default) = min(nu_post, 4).  The solve is bitwise the same for
+                          every value. */
   /* out (maxima over right-hand sides) */
   int32_t iters;                         /* outer iterations */
   int32_t level_iters[CRK_MAX_LEVELS];   /* total iterations per level */
@@ -353,7 +358,7 @@ typedef struct {
   int32_t slots_per_lane;   /* RHS slots per lane = the largest request size, 1..64 (default 12) */
   int32_t max_lanes;        /* lanes per lattice, 1..16 (default 4) */
   int32_t idle_ms;          /* an idle lane that is not its lattice's last closes after this long (default 200) */
-  crk_solve_info solve;     /* tol, max_iter, form, restart, tau, inner_maxit, coarsest_maxit, nu_post */
+  crk_solve_info solve;     /* tol, max_iter, form, restart, tau, inner_maxit, coarsest_maxit, nu_post, post_defer */
 } crk_server_params;
 
 typedef struct {

@@ -67,6 +67,7 @@ class SolveInfo(C.Structure):
         ("inner_maxit", C.c_int32),
         ("coarsest_maxit", C.c_int32),
         ("nu_post", C.c_int32),
+        ("post_defer", C.c_int32),
         ("iters", C.c_int32),
         ("level_iters", C.c_int32 * MAX_LEVELS),
         ("true_rel_resid", C.c_double),

@@ -63,9 +63,9 @@ struct LevelWork {      // coarse level l >= 1: inner solve buffers (+ post-smoo
 
 struct FineWork {       // level-0 K-cycle fields in the vector precision
   DevBuf rin, rho, q;
-  // post-smoother residuals of the deferred e updates (reduced forms): rho
-  // (q in the FP16-storage form) and `defer` more fields; alpha rows of the
-  // pending sweeps [defer][cap]
+  // post-smoother residuals of the deferred e updates: rho (q in the
+  // FP16-storage form) and `defer` more fields; alpha rows of the pending
+  // steps [defer][cap]
   DevBuf ring, alpha;
   int defer = 1;
 };

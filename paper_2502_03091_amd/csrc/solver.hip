@@ -74,10 +74,10 @@ size_t vec_bytes(int form) { return form == CRK_FORM_FP64 ? sizeof(double2) : si
 // Operator storage used on the fine level in a form (vectors there are FP32 for FP16S).
 int fine_op_form(int form) { return form == CRK_FORM_FP64 ? CRK_FORM_FP64 : CRK_FORM_FP32; }
 int ring_slots(const crk_solve_info& p) { return std::max(1, std::min(p.restart, p.max_iter)); }
-// Sweeps of the fine post-smoother whose e updates share one pass (the
-// reduced forms, whose K-cycle runs in FP32 or FP16 storage).
-int post_defer(int nlev, int form, const crk_solve_info& p) {
-  return nlev > 1 && form != CRK_FORM_FP64 ? std::max(1, std::min(p.nu_post, 4)) : 1;
+// Steps of the fine post-smoother whose e updates share one pass.
+int post_defer(int nlev, const crk_solve_info& p) {
+  if (nlev <= 1) return 1;
+  return std::max(1, std::min(p.post_defer > 0 ? p.post_defer : 4, p.nu_post));
 }
 // Storage of the outer directions z_i: the K-cycle's own vector storage (FP32
 // for the reduced forms), FP64 in the plain form and without coarse levels.
@@ -220,6 +220,7 @@ void validate(Hierarchy* H, const crk_solve_info& p) {
   CRK_REQUIRE(p.coarsest_maxit >= 1 && p.coarsest_maxit <= 64, "coarsest_maxit must be in [1, 64]");
   CRK_REQUIRE(p.form == CRK_FORM_FP64 || p.form == CRK_FORM_FP32 || p.form == CRK_FORM_FP16S, "unknown form");
   CRK_REQUIRE(p.tau > 0 && p.nu_post >= 0, "tau must be > 0 and nu_post >= 0");
+  CRK_REQUIRE(p.post_defer >= 0 && p.post_defer <= kMrMaxDefer, "post_defer must be in [0, 8]");
   (void)H;
 }
 
@@ -227,7 +228,7 @@ void validate(Hierarchy* H, const crk_solve_info& p) {
 
 bool workspace_fits(const Workspace& w, int cap, int form, const crk_solve_info& p) {
   return w.cap >= cap && w.form == form && w.restart == ring_slots(p) && w.inner == p.inner_maxit &&
-         w.coarsest == p.coarsest_maxit && w.fw.defer == post_defer(int(w.lv.size()), form, p);
+         w.coarsest == p.coarsest_maxit && w.fw.defer == post_defer(int(w.lv.size()), p);
 }
 
 std::unique_ptr<Workspace> make_workspace(Hierarchy* H, int cap, int form, const crk_solve_info& p, hipStream_t st) {
@@ -263,7 +264,7 @@ std::unique_ptr<Workspace> make_workspace(Hierarchy* H, int cap, int form, const
     const size_t fv = vec_bytes(form) * 12 * size_t(V0) * cap;
     w.fw.rin.alloc(fv); w.fw.rho.alloc(fv); w.fw.q.alloc(fv);
     w.bytes += 3 * fv;
-    w.fw.defer = post_defer(H->nlev, form, p);
+    w.fw.defer = post_defer(H->nlev, p);
     if (w.fw.defer > 1) {
       w.fw.ring.alloc(fv * w.fw.defer);
       w.fw.alpha.alloc(sizeof(double2) * w.fw.defer * cap);
@@ -546,7 +547,7 @@ size_t mg_solve_footprint(Hierarchy* H, int nrhs, int form, const crk_solve_info
   const int nslots = ring_slots(p);
   size_t b = sizeof(double2) * 12 * size_t(V0) * nrhs * (4 + size_t(nslots)) +
              vec_bytes(outer_z_form(H, form)) * 12 * size_t(V0) * nrhs * nslots;
-  const int defer = post_defer(H->nlev, form, p);
+  const int defer = post_defer(H->nlev, p);
   if (H->nlev > 1) b += (3 + size_t(defer > 1 ? defer : 0)) * vec_bytes(form) * 12 * size_t(V0) * nrhs;
   for (int l = 1; l < H->nlev; ++l) {
     const int maxit = l == H->nlev - 1 ? p.coarsest_maxit : p.inner_maxit;

@@ -56,6 +56,7 @@ def test_struct_defaults_without_gpu():
     lib.crk_solve_info_default(ctypes.byref(si))
     assert si.tol == 1e-10 and si.max_iter == 200 and si.restart == 16 and si.form == crk.FORM_FP64
     assert si.tau == 0.1 and si.inner_maxit == 20 and si.coarsest_maxit == 50 and si.nu_post == 4
+    assert si.post_defer == 0
     sp = crk.ServerParams()
     lib.crk_server_params_default(ctypes.byref(sp))
     assert sp.slots_per_lane == 12 and sp.max_lanes == 4 and sp.idle_ms == 200 and sp.hbm_budget_bytes == 0

@@ -185,3 +185,33 @@ def test_three_level_solve_matches_oracle(crk):
     for form in (1, 2):
         x, info = H.solve(b, form=form)
         assert info["converged"] and info["true_rel_resid"] <= 1e-10
+
+
+def test_deferred_post_smoother_updates_equal_per_step(crk):
+    """The fine post-smoother may apply the e updates of several MR steps in one
+    pass over e (post_defer; each step still forms its residual): per element
+    the fused multiply-adds are those of one update per step, so the solve is
+    bitwise the same for every depth, ragged last groups (8 steps in groups of
+    3) included, in every form (FP16 residual storage included)."""
+    dims, block = [8, 4, 8, 4], [4, 4, 4, 4]
+    V = int(np.prod(dims))
+    U = synth.gauge_field(dims, 0.3, 1, config=12)
+    lat = crk.Lattice(dims, 0.1, 1.0)
+    lat.load_gauge(U)
+    H = crk.Hierarchy(lat, m_prime=[16], k=[8], block=[block], n_smooth=[20], setup_form=1)
+    try:
+        b = synth.gaussian_rhs(3, V, config=12)
+        for form in (0, 1, 2):
+            out = []
+            for defer in (1, 3, 4, 8, 0):
+                x, info = H.solve(b, form=form, nu_post=8, post_defer=defer)
+                out.append((x, info["iters"], info["level_iters"], info["true_rel_resid"]))
+            print("form", form, "iterations", out[0][1], out[0][2], "residual", out[0][3], flush=True)
+            for x, it, li, res in out[1:]:
+                assert np.array_equal(x, out[0][0]), form
+                assert (it, li, res) == out[0][1:], form
+        with pytest.raises(crk.CrkError):
+            H.solve(b, form=1, post_defer=9)
+    finally:
+        H.close()
+        lat.close()
