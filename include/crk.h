@@ -201,7 +201,8 @@ typedef struct {
   int32_t smooth_defer;                /* fine-level smoother: sweeps whose psi updates share one pass
                                           over psi (each sweep still forms its residual, into a ring
                                           of smooth_defer + 1 fields); 1 = every sweep updates psi,
-                                          2..8 as given, 0 (default) = the largest of 8, 4, 2 for
+                                          2..8 as given (at most n_smooth), 0 (default) = the
+                                          largest of 8, 4, 2 (at most n_smooth) for
                                           which the ring and q take at most 30 % of the free device
                                           memory, else 1.  The hierarchy is bitwise the same for
                                           every value. */

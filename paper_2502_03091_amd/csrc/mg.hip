@@ -264,6 +264,7 @@ void setup_step(Hierarchy* H, int l, hipStream_t st) {
         }
     }
   }
+  D = std::min(D, std::max(1, p.n_smooth[l]));  // a ring longer than the sweeps is never filled
   std::vector<DevBuf> ring(D == 1 ? 1 : D + 1);
   for (auto& b : ring) b.alloc(esz * n * mc);
   std::vector<void*> slots;
