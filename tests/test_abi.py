@@ -75,3 +75,36 @@ def test_null_handles_fail_cleanly_without_gpu():
     assert b"NULL" in lib.crk_last_error()
     lib.crk_server_destroy(None)
     lib.crk_mg_destroy(None)
+
+
+STRUCTS = [("crk_mg_params", "MGParams"), ("crk_solve_info", "SolveInfo"), ("crk_server_params", "ServerParams"),
+           ("crk_request_info", "RequestInfo"), ("crk_server_stats", "ServerStats")]
+
+
+def test_ctypes_layouts_match_the_header(tmp_path):
+    """Every field of the binding's ctypes structures sits at the offset the C
+    compiler gives it in include/crk.h, and the sizes agree (a field added on one
+    side only would shift every later field)."""
+    import shutil
+    import subprocess
+    import paper_2502_03091_amd as crk
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "crk.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS:
+        lines.append(f'  printf("{pyname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in getattr(crk, pyname)._fields_:
+            lines.append(f'  printf("{pyname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for _, pyname in STRUCTS:
+        cls = getattr(crk, pyname)
+        assert got[(pyname, "size")] == ctypes.sizeof(cls), pyname
+        for fname, _ in cls._fields_:
+            assert got[(pyname, fname)] == getattr(cls, fname).offset, (pyname, fname)
