@@ -1,6 +1,7 @@
 // Per-RHS BLAS-1 launchers (see blas.hip).
 #pragma once
 
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -37,6 +38,11 @@ void mr_alpha(const double* sums3, int nrhs, double2* alpha, hipStream_t st);
 // not used afterwards (q is then not read and r not written).
 void mr_update(int prec, void* psi, void* r, const void* q, const double2* alpha, int64_t n, int nrhs, bool rhs_inner,
                hipStream_t st, bool update_r = true);
+// The same update on the fine level with psi in FP32 and r, q in FP16 storage
+// (AoSoA fine fields of V sites, one scale per site and RHS; r is rescaled).
+void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st,
+                      bool update_r = true);
+
 // MR updates of several sweeps applied to psi in one pass.  Each sweep k still
 // forms its residual r_{k+1} = r_k - alpha_k q_k, into a field of its own, but
 // psi is read and written only when the pending sweeps are flushed:
@@ -81,10 +87,6 @@ class MrSweeps {
   int D_;
   int pending_ = 0;
 };
-// The same update on the fine level with psi in FP32 and r, q in FP16 storage
-// (AoSoA fine fields of V sites, one scale per site and RHS; r is rescaled).
-void mr_update_fine_h(void* psi, void* r, const void* q, const double2* alpha, int64_t V, int nrhs, hipStream_t st,
-                      bool update_r = true);
 
 // v[e*nrhs + r] *= f[r] for n entries per rhs (rhs-inner layout).
 void scale_rhs_inner(int prec, void* v, const double* f, int64_t n, int nrhs, hipStream_t st);
